@@ -1,0 +1,277 @@
+"""ctypes wrapper around ``kd_oracle.c``, the plain CPU reference build.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU product path.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kd_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libkd_oracle.so")
+
+KEY_CYCLIC, KEY_MAXVAR = 0, 1
+SPLIT_EXACT, SPLIT_FOURIER, SPLIT_SUBSET = 0, 1, 2
+OK, EINVAL, ENOMEM, ENONFINITE, ECAPACITY = 0, 1, 2, 3, 4
+
+_CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build():
+    """Compile the oracle with gcc (contraction off, no fast-math)."""
+    subprocess.check_call(["gcc", *_CFLAGS, "-o", _LIB_PATH, _SRC, "-lm"])
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("leaf_size", ctypes.c_uint32),
+        ("max_depth", ctypes.c_uint32),
+        ("num_subsets", ctypes.c_uint32),
+        ("key_rule", ctypes.c_uint32),
+        ("split_rule", ctypes.c_uint32),
+        ("fourier_J", ctypes.c_uint32),
+        ("pool", ctypes.c_void_p),
+        ("pool_entries", ctypes.c_uint32),
+        ("pad_", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+        ("node_capacity", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        u32, u64, i32, vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
+        L.kdo_key_of_bits.restype = u32
+        L.kdo_key_of_bits.argtypes = [u32]
+        L.kdo_bits_of_key.restype = u32
+        L.kdo_bits_of_key.argtypes = [u32]
+        L.kdo_splitmix64.restype = u64
+        L.kdo_splitmix64.argtypes = [u64]
+        L.kdo_lower_median.restype = u32
+        L.kdo_lower_median.argtypes = [vp, u64]
+        L.kdo_tie_rule.restype = ctypes.c_int
+        L.kdo_tie_rule.argtypes = [u64, u64, u64, u32, ctypes.POINTER(u32)]
+        L.kdo_subset_bounds.restype = None
+        L.kdo_subset_bounds.argtypes = [u64, u32, vp, u32, u64, u32, u64, vp]
+        L.kdo_maxvar_shift.restype = ctypes.c_int
+        L.kdo_maxvar_shift.argtypes = [vp, u64, u32, u64]
+        L.kdo_maxvar_key.restype = u32
+        L.kdo_maxvar_key.argtypes = [vp, u32, u64, vp, u64, ctypes.c_int]
+        L.kdo_sincos_f32.restype = None
+        L.kdo_sincos_f32.argtypes = [ctypes.c_float, ctypes.POINTER(ctypes.c_float),
+                                     ctypes.POINTER(ctypes.c_float)]
+        L.kdo_sincos_f64.restype = None
+        L.kdo_sincos_f64.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.kdo_fourier_exponent.restype = ctypes.c_int
+        L.kdo_fourier_exponent.argtypes = [u32, u32]
+        L.kdo_fourier_map.restype = None
+        L.kdo_fourier_map.argtypes = [vp, u64, u32, ctypes.c_int, u32, vp, vp]
+        L.kdo_fourier_F.restype = ctypes.c_double
+        L.kdo_fourier_F.argtypes = [vp, vp, u32, ctypes.c_double]
+        L.kdo_fourier_solve.restype = u32
+        L.kdo_fourier_solve.argtypes = [vp, vp, u32, u32, u32, ctypes.c_int]
+        L.kdo_cell_split.restype = ctypes.c_int
+        L.kdo_cell_split.argtypes = [vp, u32, u64, ctypes.POINTER(Params), ctypes.c_int, vp, u64,
+                                     u32, u64, ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                     ctypes.POINTER(u32)]
+        L.kdo_build.restype = ctypes.c_int
+        L.kdo_build.argtypes = [vp, u64, u32, u64, ctypes.POINTER(Params)] + [vp] * 10
+        L.kdo_query_leaf.restype = u32
+        L.kdo_query_leaf.argtypes = [vp, vp, vp, vp, vp, u64]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+# ---------------------------------------------------------------- primitives
+
+def key_of_bits(b):
+    return lib().kdo_key_of_bits(int(b) & 0xFFFFFFFF)
+
+
+def bits_of_key(u):
+    return lib().kdo_bits_of_key(int(u) & 0xFFFFFFFF)
+
+
+def keys_of_floats(x):
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).ravel()
+    return np.array([key_of_bits(v) for v in b], dtype=np.uint32)
+
+
+def splitmix64(x):
+    return lib().kdo_splitmix64(int(x) & 0xFFFFFFFFFFFFFFFF)
+
+
+def lower_median(keys):
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    return lib().kdo_lower_median(_ptr(k), k.size)
+
+
+def tie_rule(n, lt, le, m):
+    s = ctypes.c_uint32(0)
+    ok = lib().kdo_tie_rule(n, lt, le, int(m) & 0xFFFFFFFF, ctypes.byref(s))
+    return (True, s.value) if ok else (False, None)
+
+
+def subset_bounds(n, S, pool=None, seed=0, depth=0, rank=0):
+    out = np.zeros(S + 1, dtype=np.uint64)
+    pool_arr = None if pool is None else np.ascontiguousarray(pool, dtype=np.uint32)
+    P = 0 if pool_arr is None else pool_arr.shape[0]
+    lib().kdo_subset_bounds(n, S, _ptr(pool_arr), P, seed, depth, rank, _ptr(out))
+    return out
+
+
+def maxvar_shift(points):
+    p = np.ascontiguousarray(points, dtype=np.float32)
+    d, n = p.shape
+    return lib().kdo_maxvar_shift(_ptr(p), n, d, n)
+
+
+def maxvar_key(points, idx, shift):
+    p = np.ascontiguousarray(points, dtype=np.float32)
+    d, n = p.shape
+    ix = np.ascontiguousarray(idx, dtype=np.uint32)
+    return lib().kdo_maxvar_key(_ptr(p), d, n, _ptr(ix), ix.size, shift)
+
+
+def sincos_f32(x):
+    s, c = ctypes.c_float(), ctypes.c_float()
+    lib().kdo_sincos_f32(float(x), ctypes.byref(s), ctypes.byref(c))
+    return s.value, c.value
+
+
+def sincos_f64(x):
+    s, c = ctypes.c_double(), ctypes.c_double()
+    lib().kdo_sincos_f64(float(x), ctypes.byref(s), ctypes.byref(c))
+    return s.value, c.value
+
+
+def fourier_exponent(lo_key, hi_key):
+    return lib().kdo_fourier_exponent(lo_key, hi_key)
+
+
+def fourier_map(keys, lo_key, e, J):
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    Cc = np.zeros(J, dtype=np.int64)
+    Cs = np.zeros(J, dtype=np.int64)
+    lib().kdo_fourier_map(_ptr(k), k.size, lo_key, e, J, _ptr(Cc), _ptr(Cs))
+    return Cc, Cs
+
+
+def fourier_F(Cc, Cs, v):
+    Cc = np.ascontiguousarray(Cc, dtype=np.int64)
+    Cs = np.ascontiguousarray(Cs, dtype=np.int64)
+    return lib().kdo_fourier_F(_ptr(Cc), _ptr(Cs), Cc.size, float(v))
+
+
+def fourier_solve(Cc, Cs, lo_key, hi_key, e):
+    Cc = np.ascontiguousarray(Cc, dtype=np.int64)
+    Cs = np.ascontiguousarray(Cs, dtype=np.int64)
+    return lib().kdo_fourier_solve(_ptr(Cc), _ptr(Cs), Cc.size, lo_key, hi_key, e)
+
+
+def default_node_capacity(n, leaf_size):
+    return 4 * ((n + leaf_size - 1) // leaf_size) + 64
+
+
+def make_params(leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
+                split_rule=SPLIT_EXACT, fourier_J=15, pool=None, seed=0, node_capacity=0,
+                n=None):
+    p = Params()
+    p.leaf_size = leaf_size
+    p.max_depth = max_depth
+    p.num_subsets = num_subsets
+    p.key_rule = key_rule
+    p.split_rule = split_rule
+    p.fourier_J = fourier_J
+    p.pool = None if pool is None else pool.ctypes.data
+    p.pool_entries = 0 if pool is None else pool.shape[0]
+    p.seed = seed
+    if node_capacity == 0 and n is not None:
+        node_capacity = default_node_capacity(n, leaf_size)
+    p.node_capacity = node_capacity
+    return p
+
+
+def cell_split(points, idx, depth=0, rank=0, shift=0, **kw):
+    """Key, split and candidate of one cell (idx: original indices in cell order)."""
+    p = np.ascontiguousarray(points, dtype=np.float32)
+    d, n = p.shape
+    pool = kw.get("pool")
+    if pool is not None:
+        pool = np.ascontiguousarray(pool, dtype=np.uint32)
+        kw["pool"] = pool
+    prm = make_params(**kw)
+    ix = np.ascontiguousarray(idx, dtype=np.uint32)
+    dim, split, cand = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    ok = lib().kdo_cell_split(_ptr(p), d, n, ctypes.byref(prm), shift, _ptr(ix), ix.size,
+                              depth, rank, ctypes.byref(dim), ctypes.byref(split),
+                              ctypes.byref(cand))
+    return bool(ok), dim.value, split.value, cand.value
+
+
+def build_tree(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
+               split_rule=SPLIT_EXACT, fourier_J=15, pool=None, seed=0, node_capacity=0):
+    """Build one tree on the CPU.  points: float32 array of shape (d, n) (SoA).
+
+    Returns a dict with perm, node_* arrays (trimmed to num_nodes), leaf_node,
+    leaf_offsets (trimmed to num_leaves + 1) and header fields.
+    """
+    p = np.ascontiguousarray(points, dtype=np.float32)
+    d, n = p.shape
+    if pool is not None:
+        pool = np.ascontiguousarray(pool, dtype=np.uint32)
+    prm = make_params(leaf_size, max_depth, num_subsets, key_rule, split_rule, fourier_J,
+                      pool, seed, node_capacity, n=n)
+    cap = prm.node_capacity
+    perm = np.zeros(n, dtype=np.uint32)
+    nb = np.zeros(cap, dtype=np.uint32)
+    ne = np.zeros(cap, dtype=np.uint32)
+    nc = np.zeros(cap, dtype=np.int32)
+    nd = np.zeros(cap, dtype=np.uint32)
+    ns = np.zeros(cap, dtype=np.uint32)
+    nl = np.zeros(cap, dtype=np.uint32)
+    ln = np.zeros(cap, dtype=np.uint32)
+    lo = np.zeros(cap + 1, dtype=np.uint32)
+    hdr = np.zeros(7, dtype=np.uint64)
+    st = lib().kdo_build(_ptr(p), n, d, n, ctypes.byref(prm), _ptr(perm), _ptr(nb), _ptr(ne),
+                         _ptr(nc), _ptr(nd), _ptr(ns), _ptr(nl), _ptr(ln), _ptr(lo), _ptr(hdr))
+    nn, nlv = int(hdr[0]), int(hdr[1])
+    return {
+        "status": int(st), "num_nodes": nn, "num_leaves": nlv, "depth": int(hdr[2]),
+        "point_levels": int(hdr[4]), "unsplittable": int(hdr[5]), "oversize": int(hdr[6]),
+        "perm": perm, "node_begin": nb[:nn], "node_end": ne[:nn], "node_child": nc[:nn],
+        "node_dim": nd[:nn], "node_split": ns[:nn], "node_leaf": nl[:nn],
+        "leaf_node": ln[:nlv], "leaf_offsets": lo[:nlv + 1],
+    }
+
+
+def query_leaf(tree, queries):
+    """Leaf index of each query (queries: float32 (d, nq)); NaN -> 0xFFFFFFFF."""
+    q = np.ascontiguousarray(queries, dtype=np.float32)
+    d, nq = q.shape
+    nc = np.ascontiguousarray(tree["node_child"], dtype=np.int32)
+    nd = np.ascontiguousarray(tree["node_dim"], dtype=np.uint32)
+    ns = np.ascontiguousarray(tree["node_split"], dtype=np.uint32)
+    nl = np.ascontiguousarray(tree["node_leaf"], dtype=np.uint32)
+    out = np.zeros(nq, dtype=np.uint32)
+    L = lib()
+    base = q.ctypes.data
+    for i in range(nq):
+        out[i] = L.kdo_query_leaf(_ptr(nc), _ptr(nd), _ptr(ns), _ptr(nl),
+                                  ctypes.c_void_p(base + 4 * i), nq)
+    return out

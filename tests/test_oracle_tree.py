@@ -1,0 +1,165 @@
+"""Whole-tree pins of the oracle: brute force on tiny inputs, invariants on
+larger ones, closed-form shapes, and the paper's reported accuracy panel."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_08288_amd import synth
+from tests import brute
+from tests.invariants import check_tree, depth_of_nodes, descend, keys_of
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _compare_with_brute(x, L, key, rule, S=1, max_depth=64):
+    kr = oracle.KEY_CYCLIC if key == "cyclic" else oracle.KEY_MAXVAR
+    sr = {"exact": oracle.SPLIT_EXACT, "subset": oracle.SPLIT_SUBSET}[rule]
+    t = oracle.build_tree(x, leaf_size=L, key_rule=kr, split_rule=sr, num_subsets=S,
+                          max_depth=max_depth)
+    assert t["status"] == 0
+    nodes, perm = brute.build(x, L, key=key, rule=rule, S=S, max_depth=max_depth)
+    assert t["num_nodes"] == len(nodes)
+    assert np.array_equal(t["perm"], np.array(perm, dtype=np.uint32))
+    for k, nd in enumerate(nodes):
+        assert t["node_begin"][k] == nd["begin"] and t["node_end"][k] == nd["end"]
+        assert t["node_child"][k] == nd["child"]
+        if nd["child"] >= 0:
+            assert t["node_dim"][k] == nd["dim"]
+            mk = int(keys_of(np.array([[nd["split"]]], dtype=np.float32))[0, 0])
+            s = int(t["node_split"][k])
+            if nd["kind"] == "le":
+                assert s in (mk, mk - 1) if rule == "subset" else s == mk
+            else:
+                assert s == mk - 1
+    return t
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 33, 64, 100, 199])
+@pytest.mark.parametrize("L", [1, 4, 7])
+def test_exact_cyclic_matches_brute_force(n, L):
+    x = synth.uniform24(n, 3, seed=n * 31 + L)
+    _compare_with_brute(x, L, "cyclic", "exact")
+
+
+@pytest.mark.parametrize("n", [20, 77, 150])
+def test_exact_heavy_ties_matches_brute_force(n):
+    rng = np.random.default_rng(n)
+    x = rng.integers(0, 4, size=(2, n)).astype(np.float32)
+    _compare_with_brute(x, 3, "cyclic", "exact")
+    x[:] = 1.0  # all equal: unsplittable root
+    t = _compare_with_brute(x, 3, "cyclic", "exact")
+    assert t["num_nodes"] == 1 and t["unsplittable"] == 1 and t["oversize"] == 1
+
+
+@pytest.mark.parametrize("n", [30, 90, 180])
+def test_exact_maxvar_matches_brute_force(n):
+    rng = np.random.default_rng(n + 1)
+    x = (np.rint(rng.standard_normal((4, n)) * np.array([[0.3], [2.0], [1.0], [1.5]]) * 1024)
+         / 1024).clip(-7.99, 7.99).astype(np.float32)
+    _compare_with_brute(x, 5, "maxvar", "exact")
+
+
+@pytest.mark.parametrize("n,S", [(50, 1), (120, 4), (199, 16), (64, 64)])
+def test_subset_matches_brute_force(n, S):
+    x = synth.gmm(n, 2, seed=n + S)
+    _compare_with_brute(x, 3, "cyclic", "subset", S=S)
+
+
+def test_subset_with_one_subset_is_exact():
+    x = synth.gmm(3000, 3, seed=2)
+    a = oracle.build_tree(x, leaf_size=16, split_rule=oracle.SPLIT_SUBSET, num_subsets=1)
+    b = oracle.build_tree(x, leaf_size=16, split_rule=oracle.SPLIT_EXACT)
+    for k in ("perm", "node_begin", "node_child", "node_split", "leaf_offsets"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_depth_cap_gives_fixed_depth_tree():
+    # §4: a depth-D tree has 2^D cells of about |X|/2^D points each.
+    x = synth.uniform24(3000, 3, seed=4)
+    t = oracle.build_tree(x, leaf_size=1, max_depth=5)
+    assert t["num_leaves"] == 32 and t["depth"] == 5
+    sizes = np.diff(t["leaf_offsets"].astype(np.int64))
+    assert sizes.min() >= 3000 // 32 and sizes.max() <= -(-3000 // 32)
+
+
+@pytest.mark.parametrize("k,l", [(10, 3), (12, 5), (16, 5)])
+def test_power_of_two_exact_tree_is_perfect(k, l):
+    # distinct keys in every coordinate: every leaf holds 2^l points at depth k - l
+    rng = np.random.default_rng(k)
+    n = 1 << k
+    x = np.stack([rng.permutation(n) for _ in range(3)]).astype(np.float32) / np.float32(n)
+    t = oracle.build_tree(x, leaf_size=1 << l)
+    sizes = np.diff(t["leaf_offsets"].astype(np.int64))
+    dep = depth_of_nodes(t)
+    assert (sizes == 1 << l).all()
+    assert (dep[t["leaf_node"]] == k - l).all()
+    assert t["num_leaves"] == 1 << (k - l) and t["num_nodes"] == (1 << (k - l + 1)) - 1
+    assert t["point_levels"] == (k - l) * n
+
+
+@pytest.mark.parametrize("rule", [oracle.SPLIT_EXACT, oracle.SPLIT_FOURIER, oracle.SPLIT_SUBSET])
+@pytest.mark.parametrize("gen,key", [("uniform24", oracle.KEY_CYCLIC), ("gmm", oracle.KEY_CYCLIC),
+                                     ("student_t_grid", oracle.KEY_MAXVAR)])
+def test_invariants_all_rules(rule, gen, key):
+    x = synth.generate(gen, 5000, 4, seed=17)
+    pool = synth.dirichlet_pool(128, 8, seed=2) if gen == "student_t_grid" else None
+    t = oracle.build_tree(x, leaf_size=20, split_rule=rule, key_rule=key, num_subsets=8,
+                          pool=pool, seed=99)
+    assert t["status"] == 0
+    check_tree(x, t, 20)
+    # (iii) every point descends to the leaf that holds it
+    leaf_of_point = np.empty(5000, dtype=np.int64)
+    for k in range(t["num_leaves"]):
+        leaf_of_point[t["perm"][t["leaf_offsets"][k]:t["leaf_offsets"][k + 1]]] = k
+    assert np.array_equal(descend(t, x), leaf_of_point)
+    assert np.array_equal(oracle.query_leaf(t, x[:, :300]), leaf_of_point[:300])
+    sizes = np.diff(t["leaf_offsets"].astype(np.int64))
+    assert (sizes[sizes > 20].size == t["oversize"])
+
+
+def test_exact_children_sizes_ceil_floor():
+    x = synth.uniform24(4097, 2, seed=8)
+    t = oracle.build_tree(x, leaf_size=10)
+    ch = t["node_child"]
+    sz = (t["node_end"] - t["node_begin"]).astype(np.int64)
+    for k in np.nonzero(ch >= 0)[0]:
+        assert sz[ch[k]] == (sz[k] + 1) // 2 and sz[ch[k] + 1] == sz[k] // 2
+
+
+def test_capacity_and_nonfinite_status():
+    x = synth.uniform24(1000, 2, seed=1)
+    t = oracle.build_tree(x, leaf_size=4, node_capacity=50)
+    assert t["status"] == oracle.ECAPACITY
+    y = x.copy()
+    y[1, 7] = np.nan
+    assert oracle.build_tree(y, leaf_size=4)["status"] == oracle.ENONFINITE
+    y[1, 7] = np.inf
+    assert oracle.build_tree(y, leaf_size=4)["status"] == oracle.ENONFINITE
+
+
+def test_nan_query_returns_sentinel():
+    x = synth.uniform24(500, 2, seed=3)
+    t = oracle.build_tree(x, leaf_size=8)
+    q = np.array([[np.nan], [0.5]], dtype=np.float32)
+    assert oracle.query_leaf(t, q)[0] == 0xFFFFFFFF
+
+
+def test_paper_accuracy_panel_fourier_J15():
+    """§5.1 reports, for the trivariate normal with rho = 0.5, depth 6 and the
+    J = (3,5) accuracy parameter (J = 15), cell counts between 2^25.45 and
+    2^25.52 for an ideal 2^25.48232.  The per-level FOURIER rule must be at
+    least that accurate, relative to the ideal count, at a smaller N."""
+    with open(os.path.join(GOLDEN, "paper_accuracy_panel.json")) as f:
+        g = json.load(f)
+    lo_rel = 2.0 ** (g["observed_min_log2"] - g["ideal_log2"])
+    hi_rel = 2.0 ** (g["observed_max_log2"] - g["ideal_log2"])
+    n = 3 * (1 << 16)
+    x = synth.corr_normal(n, 3, rho=g["rho"], seed=21)
+    t = oracle.build_tree(x, leaf_size=1, max_depth=g["depth"], split_rule=oracle.SPLIT_FOURIER,
+                          fourier_J=g["J"], num_subsets=16)
+    assert t["num_leaves"] == 2 ** g["depth"]
+    rel = np.diff(t["leaf_offsets"].astype(np.int64)) / (n / 2 ** g["depth"])
+    assert rel.min() >= lo_rel and rel.max() <= hi_rel, (rel.min(), rel.max())
