@@ -1,0 +1,157 @@
+/*
+ * kdtree.h -- C ABI of the MI355X k-d tree builder (libkdtree.so).
+ *
+ * The library builds k-d trees level by level (Chakravorty, Cleveland &
+ * Wolfe, "Scalable k-d trees for distributed data", §2 and §4): on every
+ * level each cell's points are split into subsets, per-subset statistics of
+ * the cell's key coordinate are combined into a split value, and the cell
+ * is stably partitioned into its two children.
+ *
+ * Problem statement (§2, §4): a data set X of n points in d dimensions; a
+ * tree of cells obtained by recursive splits along one coordinate (the key)
+ * at an (approximate) median.  The split values are "all the information
+ * needed to build the tree" (§2); the leaves are cells of about equal count
+ * (§4).
+ *
+ * Conventions for every entry point
+ *   - Points are fp32, structure of arrays: coordinate c of point i is at
+ *     pts[c * ld + i].  All point, tree and workspace pointers are DEVICE
+ *     pointers owned by the caller; the library never allocates, frees or
+ *     keeps them.
+ *   - Keys are compared through an order-preserving map of the fp32 bit
+ *     pattern to uint32 (-0 folded onto +0).  Split values are stored in that
+ *     key domain; descent is "key(x[dim]) <= split -> left child".
+ *   - `stream` is a hipStream_t (NULL = the null stream).
+ *   - A KD_E* return value means nothing was enqueued (bad arguments, a
+ *     launch failure).  Data-dependent errors (non-finite input, node
+ *     capacity) are written to hdr->status on the device.
+ *   - Calls on distinct streams with distinct workspaces may run
+ *     concurrently; the library has no mutable global state.
+ */
+#ifndef KDTREE_H
+#define KDTREE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kd_status;
+enum {
+    KD_OK = 0,
+    KD_EINVAL = 1,      /* bad argument (sizes, rules, null pointers)        */
+    KD_ENOMEM = 2,      /* workspace smaller than kd_tree_bounds() asked for */
+    KD_ENAN = 3,        /* (hdr->status) input holds NaN or +-Inf            */
+    KD_ECAPACITY = 4,   /* (hdr->status) node arrays too small: retry larger */
+    KD_EDEVICE = 5,     /* a HIP call or kernel launch failed                */
+    KD_ECANCELLED = 6   /* request withdrawn by the caller (serving loop)    */
+};
+
+/* Key coordinate of a cell (§1): cyclic x, y, z, x, ... over the levels, or
+ * the coordinate of largest variance within the cell.                      */
+enum { KD_KEY_CYCLIC = 0, KD_KEY_MAXVAR = 1 };
+
+/* Split rule.
+ *   EXACT   lower median of the cell's keys (the canonical tree, §1, §2);
+ *           per-subset digit histograms are added (reduce by +, App. C.2).
+ *   FOURIER the paper's approximate median (§3.2, Eq. (1)-(2)) with p = 1
+ *           on the cell's key: additive trigonometric moments of the scaled
+ *           key, J odd harmonics, summed over subsets; the split is a sign
+ *           change of the equal-count equation found by bisection.
+ *   SUBSET  not from the paper: size-weighted mean (subset order) of the
+ *           lower medians of the cell's subsets.                          */
+enum { KD_SPLIT_EXACT = 0, KD_SPLIT_FOURIER = 1, KD_SPLIT_SUBSET = 2 };
+
+typedef struct kd_params {
+    uint32_t leaf_size;        /* cells with > leaf_size points are split (>= 1)   */
+    uint32_t max_depth;        /* cells at this depth stay leaves (0 -> 64)         */
+    uint32_t num_subsets;      /* S: subsets per cell (1..65536)                    */
+    uint32_t key_rule;         /* KD_KEY_*                                          */
+    uint32_t split_rule;       /* KD_SPLIT_*                                        */
+    uint32_t fourier_J;        /* harmonics for FOURIER (1..64)                     */
+    const uint32_t *subset_pool; /* device, pool_entries x S uint32 cumulative
+                                  * weights in units of 2^-32 (entry 0 unused);
+                                  * NULL -> equal subsets floor(r*n_c/S)          */
+    uint32_t pool_entries;
+    uint32_t reserved;
+    uint64_t seed;             /* picks the pool row of each cell                   */
+    uint64_t node_capacity;    /* 0 -> 4*ceil(n/leaf_size)+64                       */
+} kd_params;
+
+/* Device-side header, written by the build (read it after the stream syncs). */
+typedef struct kd_header {
+    uint32_t num_nodes;
+    uint32_t num_leaves;
+    uint32_t depth;            /* largest node depth (root = 0)                     */
+    int32_t status;            /* KD_OK, KD_ENAN or KD_ECAPACITY                    */
+    uint64_t point_levels;     /* sum of the sizes of all split cells               */
+    uint32_t unsplittable;     /* cells kept as leaves because all keys were equal  */
+    uint32_t oversize;         /* leaves with more than leaf_size points            */
+} kd_header;
+
+/* Output tree: DEVICE arrays owned by the caller, sized by kd_tree_bounds().
+ * Node ids are breadth first: node 0 is the root; the children of the cells
+ * split at depth l get the next ids, two per split cell, in position order.
+ * Leaves are numbered in position order.                                     */
+typedef struct kd_tree {
+    uint32_t *perm;            /* [n]   original index of each position            */
+    uint32_t *node_begin;      /* [cap] first position of the node's points        */
+    uint32_t *node_end;        /* [cap] one past the last position                 */
+    int32_t *node_child;       /* [cap] left child id (right = left+1), -1: leaf   */
+    uint32_t *node_dim;        /* [cap] key coordinate of internal nodes           */
+    uint32_t *node_split;      /* [cap] split in the key domain                    */
+    float *node_split_f;       /* [cap] split decoded to fp32 (informational)      */
+    uint32_t *node_leaf;       /* [cap] leaf index of leaves, 0xFFFFFFFF otherwise */
+    uint32_t *leaf_node;       /* [cap] node id of each leaf                       */
+    uint32_t *leaf_offsets;    /* [cap+1] first position of each leaf, then n      */
+    kd_header *hdr;            /* [1]                                              */
+    float *points_out;         /* optional [d][n] points in perm order, or NULL    */
+    uint64_t node_capacity;    /* entries in the node arrays                        */
+} kd_tree;
+
+/* Sizes to allocate for a build of n points in d dimensions (host only, no
+ * device work).  node_capacity: entries of each node array; workspace_bytes:
+ * device workspace for kd_build.  Returns KD_EINVAL on bad parameters.     */
+kd_status kd_tree_bounds(uint64_t n, uint32_t d, const kd_params *params,
+                         uint64_t *node_capacity, uint64_t *workspace_bytes);
+
+/* Build one tree (§4).  pts: device [d][ld] fp32, read only.  out: device
+ * arrays of capacity out->node_capacity.  workspace: device, ws_bytes >=
+ * kd_tree_bounds().  Enqueued on `stream`; the call returns when the tree is
+ * complete on the device (it reads each level's cell count back).          */
+kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
+                   const kd_params *params, kd_tree *out, void *workspace,
+                   uint64_t ws_bytes, void *stream);
+
+/* One tree of a batch. */
+typedef struct kd_batch_item {
+    const float *pts;          /* device [d][ld] */
+    uint64_t n;
+    uint32_t d;
+    uint32_t reserved;
+    uint64_t ld;
+    kd_tree out;
+} kd_batch_item;
+
+/* Workspace for kd_build_batched over the given items (host only). */
+kd_status kd_batch_bounds(uint32_t count, const kd_batch_item *items, const kd_params *params,
+                          uint64_t *workspace_bytes);
+
+/* Build `count` independent trees with one set of level launches over the
+ * union of their cells.  Every tree is bit-identical to kd_build on it.    */
+kd_status kd_build_batched(uint32_t count, const kd_batch_item *items, const kd_params *params,
+                           void *workspace, uint64_t ws_bytes, void *stream);
+
+/* Leaf of each query point by descent from the root (§2's cells).  q: device
+ * [d][ldq] fp32; leaf_out: device [nq].  NaN query -> 0xFFFFFFFF.         */
+kd_status kd_query_leaf(const kd_tree *tree, const float *q, uint64_t nq, uint32_t d,
+                        uint64_t ldq, uint32_t *leaf_out, void *stream);
+
+const char *kd_status_string(kd_status s);
+int kd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KDTREE_H */
