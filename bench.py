@@ -1,0 +1,163 @@
+"""Benchmark of the level-by-level k-d tree build on one MI355X.
+
+A step is one complete kd_build (every level of the hot path) over the
+resident synthetic input of the workload.  Prints ONE JSON line on stdout;
+progress goes to stderr.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--rule exact]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+RULES = {"exact": 0, "fourier": 1, "subset": 2}
+KEYS = {"cyclic": 0, "maxvar": 1}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload_arrays(name, rng_seed=None):
+    from paper_2201_08288_amd import synth
+    w = synth.WORKLOADS[name]
+    x = synth.generate(w["gen"], w["n"], w["d"])
+    pool = None
+    if w.get("pool_entries"):
+        pool = synth.dirichlet_pool(w["pool_entries"], w["num_subsets"], w.get("pool_alpha", 0.5))
+    return w, x, pool
+
+
+def tree_kwargs(w, rule):
+    return dict(leaf_size=w["leaf_size"], num_subsets=w["num_subsets"], key_rule=KEYS[w["key"]],
+                split_rule=RULES[rule], fourier_J=15, seed=w.get("seed", 0))
+
+
+def cpu_baseline(w, rule, sample_n):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle
+    from paper_2201_08288_amd import synth
+    x = synth.generate(w["gen"], sample_n, w["d"], stream=1)
+    pool = None
+    if w.get("pool_entries"):
+        pool = synth.dirichlet_pool(w["pool_entries"], w["num_subsets"], w.get("pool_alpha", 0.5))
+    kw = tree_kwargs(w, rule)
+    t0 = time.perf_counter()
+    t = oracle.build_tree(x, pool=pool, **kw)
+    dt = time.perf_counter() - t0
+    return {"value": t["point_levels"] / dt, "unit": "point-levels/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{sample_n} points of the same {w['gen']} recipe (d={w['d']}), "
+                      f"same tree parameters, single-threaded C oracle, {dt:.2f} s, "
+                      f"{t['point_levels']} point-levels"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="scale_n2^24_d8")
+    ap.add_argument("--rule", default="exact", choices=sorted(RULES))
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the build does not shard across GPUs); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2201_08288_amd import kdtree
+    dev = torch.device("cuda:0")
+    log(f"[bench] generating workload {args.workload}")
+    w, x, pool = workload_arrays(args.workload)
+    d, n = x.shape
+    xt = torch.from_numpy(x).to(dev)
+    pool_t = None if pool is None else torch.from_numpy(pool.view(np.int32)).to(dev)
+    kw = tree_kwargs(w, args.rule)
+    tree = kdtree.build(xt, subset_pool=pool_t, **kw)
+    torch.cuda.synchronize()
+    hdr = tree.header()
+    assert hdr["status"] == 0, hdr
+    ws = tree.workspace
+    log(f"[bench] tree: {hdr}")
+
+    for _ in range(args.warmup):
+        kdtree.build(xt, subset_pool=pool_t, workspace=ws, tree=tree, **kw)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        kdtree.build(xt, subset_pool=pool_t, workspace=ws, tree=tree, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1e3 * dt / args.steps
+    pl = hdr["point_levels"]
+    value = pl * args.steps / dt
+
+    # Same steps again with HIP events around every launch (on the build stream).
+    log("[bench] profiled steps")
+    agg = {}
+    for _ in range(args.steps):
+        prof = kdtree.Profile()
+        kdtree.build(xt, subset_pool=pool_t, workspace=ws, tree=tree, profile=prof, **kw)
+        for k, v in prof.to_dict().items():
+            if k == "levels":
+                agg["levels"] = v
+                continue
+            a = agg.setdefault(k, {"ms": 0.0, "launches": 0, "points": 0, "bytes": 0})
+            for f in ("ms", "launches", "points", "bytes"):
+                a[f] += v[f]
+    torch.cuda.synchronize()
+    kernels = {}
+    for k, v in agg.items():
+        if k == "levels" or v["launches"] == 0:
+            continue
+        kernels[k] = {"ms_per_step": v["ms"] / args.steps,
+                      "avg_launch_us": 1e3 * v["ms"] / v["launches"],
+                      "launches_per_step": v["launches"] / args.steps,
+                      "alg_GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
+    byte_kinds = [k for k in ("big_scatter", "small", "select", "count", "ingest") if k in agg
+                  and agg[k]["bytes"] > 0]
+    dom = max(byte_kinds, key=lambda k: agg[k]["ms"])
+    a = agg[dom]
+    achieved = a["bytes"] / (a["ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "kernel": dom, "avg_launch_us": round(1e3 * a["ms"] / a["launches"], 2),
+                "alg_bytes_per_launch": a["bytes"] / a["launches"]}
+    b_alg = 8 * d + 12
+    level_gbps = b_alg * pl / (ms * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline on {args.cpu_sample} points")
+        cpu = cpu_baseline(w, args.rule, args.cpu_sample)
+
+    out = {
+        "metric": "points·levels/s", "value": value, "unit": "point-levels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d, "gen": w["gen"],
+                   "split_rule": args.rule, "key": w["key"], "leaf_size": w["leaf_size"],
+                   "num_subsets": w["num_subsets"], "parallelism": "single-gpu"},
+        "point_levels_per_step": pl, "levels": agg.get("levels"),
+        "whole_build_alg_GBps": round(level_gbps, 1),
+        "whole_build_alg_frac": round(level_gbps / HBM_PEAK_GBPS, 4),
+        "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

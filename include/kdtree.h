@@ -124,6 +124,40 @@ kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
                    const kd_params *params, kd_tree *out, void *workspace,
                    uint64_t ws_bytes, void *stream);
 
+/* Optional instrumentation of one build: HIP events recorded on the build's
+ * stream around every launch, summed per kernel class.  bytes are the
+ * algorithmic bytes of the launches (points x bytes-per-point of the class:
+ * select and count passes read the 4-byte key; scatters read and write d
+ * columns and the permutation, 8d+8 bytes).                                */
+enum {
+    KD_PROF_INGEST = 0,      /* copy in, identity permutation, finiteness check  */
+    KD_PROF_SELECT = 1,      /* large-cell radix-select histogram passes         */
+    KD_PROF_PICK = 2,        /* per-cell digit pick / split solve                */
+    KD_PROF_COUNT = 3,       /* large-cell per-tile left counts and tile scans   */
+    KD_PROF_BIG_SCATTER = 4, /* large-cell stable partition-scatter              */
+    KD_PROF_SMALL = 5,       /* small cells: select + partition in one kernel    */
+    KD_PROF_EMIT = 6,        /* node records and next-level cells                */
+    KD_PROF_OTHER = 7,       /* init, leaf numbering, header                     */
+    KD_PROF_KINDS = 8
+};
+typedef struct kd_kernel_stat {
+    double ms;
+    uint64_t launches;
+    uint64_t points;
+    uint64_t bytes;
+} kd_kernel_stat;
+typedef struct kd_profile {
+    kd_kernel_stat k[KD_PROF_KINDS];
+    uint32_t levels;
+    uint32_t reserved;
+} kd_profile;
+
+/* kd_build with per-kernel timing written to *prof (host struct, zeroed by
+ * the call).  Same results as kd_build; for measurement only.            */
+kd_status kd_build_profiled(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
+                            const kd_params *params, kd_tree *out, void *workspace,
+                            uint64_t ws_bytes, void *stream, kd_profile *prof);
+
 /* One tree of a batch. */
 typedef struct kd_batch_item {
     const float *pts;          /* device [d][ld] */

@@ -51,7 +51,9 @@ struct LevelInfo {
     uint32_t num_leaves;
     unsigned long long point_levels;
     uint32_t splits;       // cells split by the last level
-    uint32_t pad[5];
+    uint32_t points;       // points in the active cells of the level about to run
+    uint32_t big_points;   // ... of which in large cells
+    uint32_t pad[3];
 };
 
 // Order-preserving map of an fp32 bit pattern onto uint32; -0 folds onto +0.

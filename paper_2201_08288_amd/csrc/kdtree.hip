@@ -18,6 +18,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <vector>
+
 #include "kdtree.h"
 #include "kd_device.hpp"
 
@@ -29,6 +31,8 @@ static_assert(PER_THREAD * NT == TILE && SMALL_MAX <= TILE, "tile shape");
 namespace {
 
 constexpr uint32_t NONE = 0xffffffffu;
+constexpr int EMIT_COUNTERS = 5;  // splits, active children, tiles, points, large-cell points
+constexpr int EMIT_STRIDE = 8;
 
 struct Ctx {
     // working buffers (ping-pong by level parity)
@@ -87,7 +91,7 @@ Layout layout_for(uint64_t n, uint32_t d, uint32_t leaf_size, uint64_t cap) {
     L.off_tile_left = take(L.max_tiles * 4);
     L.off_tile_off = take(L.max_tiles * 4);
     L.off_hist = take(L.hist_words * 4);
-    L.off_scan = take((L.scan_blocks + 1) * 4 * 4);
+    L.off_scan = take((L.scan_blocks + 1) * EMIT_STRIDE * 4);
     L.off_info = take(sizeof(LevelInfo));
     L.off_leaf_cnt = take(cap * 4);
     L.off_leaf_first = take(cap * 4);
@@ -119,6 +123,8 @@ __global__ void k_init(Ctx c, uint32_t root_active) {
         z.num_nodes = 1;
         z.num_cells = root_active ? 1u : 0u;
         z.num_tiles = (root_active && c.n > uint32_t(SMALL_MAX)) ? (c.n + TILE - 1) / TILE : 0u;
+        z.points = root_active ? c.n : 0u;
+        z.big_points = z.num_tiles ? c.n : 0u;
         *c.info = z;
         c.node_begin[0] = 0;
         c.node_end[0] = c.n;
@@ -458,10 +464,11 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
     }
 }
 
-// a8 emit, phase 1: per-workgroup totals of (splits, active children, tiles).
+// a8 emit, phase 1: per-workgroup totals of (splits, active children, tiles,
+// active points, large-cell points).
 __device__ __forceinline__ void emit_counts(const Ctx &c, uint32_t level, uint32_t ci,
-                                            uint32_t ncells, uint32_t cnt[3]) {
-    cnt[0] = cnt[1] = cnt[2] = 0;
+                                            uint32_t ncells, uint32_t cnt[EMIT_COUNTERS]) {
+    for (int k = 0; k < EMIT_COUNTERS; k++) cnt[k] = 0;
     if (ci >= ncells) return;
     const Cell cl = c.cells[level & 1][ci];
     const CellRes r = c.res[ci];
@@ -472,31 +479,35 @@ __device__ __forceinline__ void emit_counts(const Ctx &c, uint32_t level, uint32
     for (int s = 0; s < 2; s++) {
         if (leaf[s]) continue;
         cnt[1]++;
-        if (sz[s] > uint32_t(SMALL_MAX)) cnt[2] += (sz[s] + TILE - 1) / TILE;
+        cnt[3] += sz[s];
+        if (sz[s] > uint32_t(SMALL_MAX)) {
+            cnt[2] += (sz[s] + TILE - 1) / TILE;
+            cnt[4] += sz[s];
+        }
     }
 }
 
 __global__ __launch_bounds__(NT) void k_emit_sum(Ctx c, uint32_t level, uint32_t ncells) {
     __shared__ uint32_t sh[NW + 1];
-    uint32_t cnt[3];
+    uint32_t cnt[EMIT_COUNTERS];
     emit_counts(c, level, blockIdx.x * NT + threadIdx.x, ncells, cnt);
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < EMIT_COUNTERS; k++) {
         uint32_t tot;
         block_excl_scan(cnt[k], sh, &tot);
-        if (threadIdx.x == 0) c.scan_tmp[blockIdx.x * 4 + k] = tot;
+        if (threadIdx.x == 0) c.scan_tmp[blockIdx.x * EMIT_STRIDE + k] = tot;
     }
 }
 
 __global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t level, uint32_t nblocks) {
     __shared__ uint32_t sh[NW + 1];
-    uint32_t base[3] = {0, 0, 0};
+    uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0};
     for (uint32_t b0 = 0; b0 < nblocks; b0 += NT) {
         uint32_t b = b0 + threadIdx.x;
-        for (int k = 0; k < 3; k++) {
-            uint32_t v = b < nblocks ? c.scan_tmp[b * 4 + k] : 0u;
+        for (int k = 0; k < EMIT_COUNTERS; k++) {
+            uint32_t v = b < nblocks ? c.scan_tmp[b * EMIT_STRIDE + k] : 0u;
             uint32_t tot;
             uint32_t ex = block_excl_scan(v, sh, &tot);
-            if (b < nblocks) c.scan_tmp[b * 4 + k] = base[k] + ex;
+            if (b < nblocks) c.scan_tmp[b * EMIT_STRIDE + k] = base[k] + ex;
             base[k] += tot;
         }
     }
@@ -509,10 +520,14 @@ __global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t level, uint32_
             in->status = KD_ECAPACITY;
             in->num_cells = 0;
             in->num_tiles = 0;
+            in->points = 0;
+            in->big_points = 0;
         } else {
             in->num_nodes = uint32_t(after);
             in->num_cells = base[1];
             in->num_tiles = base[2];
+            in->points = base[3];
+            in->big_points = base[4];
         }
     }
 }
@@ -521,11 +536,11 @@ __global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level, uint32
     __shared__ uint32_t sh[NW + 1];
     __shared__ unsigned long long sh64[NW];
     const uint32_t ci = blockIdx.x * NT + threadIdx.x;
-    uint32_t cnt[3], pre[3];
+    uint32_t cnt[EMIT_COUNTERS], pre[3];
     emit_counts(c, level, ci, ncells, cnt);
     for (int k = 0; k < 3; k++) {
         uint32_t tot;
-        pre[k] = block_excl_scan(cnt[k], sh, &tot) + c.scan_tmp[blockIdx.x * 4 + k];
+        pre[k] = block_excl_scan(cnt[k], sh, &tot) + c.scan_tmp[blockIdx.x * EMIT_STRIDE + k];
     }
     const LevelInfo in = *c.info;
     unsigned long long pl = 0;
@@ -663,6 +678,53 @@ uint32_t grid_for(uint64_t work, uint32_t cap = 65535u) {
     return uint32_t(work < cap ? work : cap);
 }
 
+// Per-kernel-class timing with HIP events on the build's stream (only when
+// the caller asks for a profile).
+struct Prof {
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+        uint64_t points, bytes;
+    };
+    kd_profile *p;
+    hipStream_t st;
+    std::vector<Rec> recs;
+    Prof(kd_profile *prof, hipStream_t s) : p(prof), st(s) {
+        if (p) memset(p, 0, sizeof(*p));
+    }
+    template <class F>
+    void run(int kind, uint64_t points, uint64_t bytes, F &&launch) {
+        if (!p) {
+            launch();
+            return;
+        }
+        Rec r{kind, nullptr, nullptr, points, bytes};
+        (void)hipEventCreate(&r.a);
+        (void)hipEventCreate(&r.b);
+        (void)hipEventRecord(r.a, st);
+        launch();
+        (void)hipEventRecord(r.b, st);
+        recs.push_back(r);
+    }
+    bool finish(uint32_t levels) {
+        if (!p) return true;
+        bool ok = hipStreamSynchronize(st) == hipSuccess;
+        for (auto &r : recs) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ok = false;
+            kd_kernel_stat &k = p->k[r.kind];
+            k.ms += ms;
+            k.launches += 1;
+            k.points += r.points;
+            k.bytes += r.bytes;
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        p->levels = levels;
+        return ok;
+    }
+};
+
 #define KD_LAUNCH_CHECK()                                   \
     do {                                                    \
         if (hipGetLastError() != hipSuccess) return KD_EDEVICE; \
@@ -701,8 +763,9 @@ kd_status kd_tree_bounds(uint64_t n, uint32_t d, const kd_params *params,
     return KD_OK;
 }
 
-kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const kd_params *p,
-                   kd_tree *out, void *workspace, uint64_t ws_bytes, void *stream) {
+kd_status kd_build_profiled(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
+                            const kd_params *p, kd_tree *out, void *workspace, uint64_t ws_bytes,
+                            void *stream, kd_profile *prof) {
     if (!params_ok(n, d, p) || !pts || !out || ld < n || !workspace) return KD_EINVAL;
     if (!out->perm || !out->node_begin || !out->node_end || !out->node_child || !out->node_dim ||
         !out->node_split || !out->node_split_f || !out->node_leaf || !out->leaf_node ||
@@ -715,6 +778,7 @@ kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const 
     if (ws_bytes < L.total) return KD_ENOMEM;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
+    Prof P(prof, st);
 
     Ctx c{};
     for (int b = 0; b < 2; b++) {
@@ -752,25 +816,33 @@ kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const 
     c.J = p->fourier_J;
     c.S = p->num_subsets;
 
+    const uint64_t scatter_bpp = 8ull * d + 8;  // algorithmic bytes per point of a scatter
     const uint32_t root_active = (n > p->leaf_size && c.max_depth > 0) ? 1u : 0u;
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.hist_words / NT + 1, 4096)), dim3(NT), 0, st,
-                       c.hist, L.hist_words, 0u);
-    hipLaunchKernelGGL(k_init, dim3(grid_for(cap / NT + 1, 4096)), dim3(NT), 0, st, c,
-                       root_active);
-    hipLaunchKernelGGL(k_ingest, dim3(grid_for(n / (NT * 4) + 1, 1024), d), dim3(NT), 0, st, c,
-                       pts, ld);
+    P.run(KD_PROF_OTHER, 0, 0, [&] {
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.hist_words / NT + 1, 4096)), dim3(NT), 0,
+                           st, c.hist, L.hist_words, 0u);
+        hipLaunchKernelGGL(k_init, dim3(grid_for(cap / NT + 1, 4096)), dim3(NT), 0, st, c,
+                           root_active);
+    });
+    P.run(KD_PROF_INGEST, n, n * (8ull * d + 4), [&] {
+        hipLaunchKernelGGL(k_ingest, dim3(grid_for(n / (NT * 4) + 1, 1024), d), dim3(NT), 0, st,
+                           c, pts, ld);
+    });
     KD_LAUNCH_CHECK();
 
-    // level loop; node ids of level l+1 are [level_first[l+1], level_first[l+2])
+    // level loop; node ids of depth l are [level_first[l], level_first[l + 1])
     uint32_t level_first[130];
-    uint32_t nlevels = 1;  // levels holding nodes
+    uint32_t nlevels = 1;  // depths holding nodes
     level_first[0] = 0;
     level_first[1] = 1;
     LevelInfo hi{};
     if (!root_active) {
-        hipLaunchKernelGGL(k_copy_all, dim3(grid_for(n / NT + 1, 4096)), dim3(NT), 0, st, c);
+        P.run(KD_PROF_OTHER, n, 0, [&] {
+            hipLaunchKernelGGL(k_copy_all, dim3(grid_for(n / NT + 1, 4096)), dim3(NT), 0, st, c);
+        });
         KD_LAUNCH_CHECK();
     }
+    uint32_t levels_run = 0;
     for (uint32_t level = 0;; level++) {
         if (hipMemcpyAsync(&hi, c.info, sizeof(hi), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
@@ -780,48 +852,75 @@ kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const 
             nlevels++;
         }
         if (hi.status != KD_OK || hi.num_cells == 0 || level >= 128) break;
+        levels_run++;
         const uint32_t nc = hi.num_cells, ntl = hi.num_tiles;
-        hipLaunchKernelGGL(k_level_init, dim3(grid_for(nc / NT + 1, 4096)), dim3(NT), 0, st, c,
-                           level, nc);
+        const uint64_t bigp = hi.big_points, smallp = hi.points - hi.big_points;
+        P.run(KD_PROF_OTHER, 0, 0, [&] {
+            hipLaunchKernelGGL(k_level_init, dim3(grid_for(nc / NT + 1, 4096)), dim3(NT), 0, st,
+                               c, level, nc);
+        });
         if (ntl > 0) {
             for (uint32_t pass = 0; pass < uint32_t(RPASSES); pass++) {
-                hipLaunchKernelGGL(k_big_hist, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
-                                   level, pass, nc, ntl);
-                hipLaunchKernelGGL(k_big_pick, dim3(grid_for(nc, 65535)), dim3(NT), 0, st, c,
-                                   level, pass, nc);
+                P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
+                    hipLaunchKernelGGL(k_big_hist, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
+                                       level, pass, nc, ntl);
+                });
+                P.run(KD_PROF_PICK, 0, 0, [&] {
+                    hipLaunchKernelGGL(k_big_pick, dim3(grid_for(nc, 65535)), dim3(NT), 0, st, c,
+                                       level, pass, nc);
+                });
             }
-            hipLaunchKernelGGL(k_big_count, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c, level,
-                               nc, ntl);
-            hipLaunchKernelGGL(k_big_tilescan, dim3(grid_for(nc, 65535)), dim3(NT), 0, st, c,
-                               level, nc);
-            hipLaunchKernelGGL(k_big_scatter, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
-                               level, nc, ntl);
+            P.run(KD_PROF_COUNT, bigp, 4 * bigp, [&] {
+                hipLaunchKernelGGL(k_big_count, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
+                                   level, nc, ntl);
+                hipLaunchKernelGGL(k_big_tilescan, dim3(grid_for(nc, 65535)), dim3(NT), 0, st, c,
+                                   level, nc);
+            });
+            P.run(KD_PROF_BIG_SCATTER, bigp, scatter_bpp * bigp, [&] {
+                hipLaunchKernelGGL(k_big_scatter, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
+                                   level, nc, ntl);
+            });
         }
-        hipLaunchKernelGGL(k_small, dim3(grid_for(nc, 1u << 20)), dim3(NT), 0, st, c, level, nc);
+        if (smallp > 0) {
+            P.run(KD_PROF_SMALL, smallp, scatter_bpp * smallp, [&] {
+                hipLaunchKernelGGL(k_small, dim3(grid_for(nc, 1u << 20)), dim3(NT), 0, st, c, level,
+                                   nc);
+            });
+        }
         const uint32_t nb = (nc + NT - 1) / NT;
-        hipLaunchKernelGGL(k_emit_sum, dim3(nb), dim3(NT), 0, st, c, level, nc);
-        hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(NT), 0, st, c, level, nb);
-        hipLaunchKernelGGL(k_emit_write, dim3(nb), dim3(NT), 0, st, c, level, nc);
+        P.run(KD_PROF_EMIT, 0, 0, [&] {
+            hipLaunchKernelGGL(k_emit_sum, dim3(nb), dim3(NT), 0, st, c, level, nc);
+            hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(NT), 0, st, c, level, nb);
+            hipLaunchKernelGGL(k_emit_write, dim3(nb), dim3(NT), 0, st, c, level, nc);
+        });
         KD_LAUNCH_CHECK();
     }
     const uint32_t depth = nlevels - 1;
-    if (hi.status == KD_OK) {
-        for (int l = int(nlevels) - 1; l >= 0; l--) {
-            uint32_t a = level_first[l], b = level_first[l + 1];
-            hipLaunchKernelGGL(k_leaf_count, dim3(grid_for((b - a) / NT + 1, 4096)), dim3(NT), 0,
-                               st, c, a, b);
+    P.run(KD_PROF_OTHER, 0, 0, [&] {
+        if (hi.status == KD_OK) {
+            for (int l = int(nlevels) - 1; l >= 0; l--) {
+                uint32_t a = level_first[l], b = level_first[l + 1];
+                hipLaunchKernelGGL(k_leaf_count, dim3(grid_for((b - a) / NT + 1, 4096)), dim3(NT),
+                                   0, st, c, a, b);
+            }
+            for (uint32_t l = 0; l < nlevels; l++) {
+                uint32_t a = level_first[l], b = level_first[l + 1];
+                hipLaunchKernelGGL(k_leaf_first, dim3(grid_for((b - a) / NT + 1, 4096)), dim3(NT),
+                                   0, st, c, a, b);
+            }
+            hipLaunchKernelGGL(k_leaf_write, dim3(grid_for(hi.num_nodes / NT + 1, 4096)), dim3(NT),
+                               0, st, c, hi.num_nodes);
         }
-        for (uint32_t l = 0; l < nlevels; l++) {
-            uint32_t a = level_first[l], b = level_first[l + 1];
-            hipLaunchKernelGGL(k_leaf_first, dim3(grid_for((b - a) / NT + 1, 4096)), dim3(NT), 0,
-                               st, c, a, b);
-        }
-        hipLaunchKernelGGL(k_leaf_write, dim3(grid_for(hi.num_nodes / NT + 1, 4096)), dim3(NT), 0,
-                           st, c, hi.num_nodes);
-    }
-    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, st, c, depth);
+        hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, st, c, depth);
+    });
     KD_LAUNCH_CHECK();
+    if (!P.finish(levels_run)) return KD_EDEVICE;
     return KD_OK;
+}
+
+kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const kd_params *p,
+                   kd_tree *out, void *workspace, uint64_t ws_bytes, void *stream) {
+    return kd_build_profiled(pts, n, d, ld, p, out, workspace, ws_bytes, stream, nullptr);
 }
 
 kd_status kd_query_leaf(const kd_tree *tree, const float *q, uint64_t nq, uint32_t d,

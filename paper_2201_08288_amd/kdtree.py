@@ -34,6 +34,24 @@ class TreeStruct(ctypes.Structure):
                 ("points_out", _vp), ("node_capacity", _u64)]
 
 
+PROF_KINDS = ("ingest", "select", "pick", "count", "big_scatter", "small", "emit", "other")
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", _u64), ("points", _u64), ("bytes", _u64)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("k", KernelStat * len(PROF_KINDS)), ("levels", _u32), ("reserved", _u32)]
+
+    def to_dict(self):
+        out = {"levels": self.levels}
+        for i, name in enumerate(PROF_KINDS):
+            k = self.k[i]
+            out[name] = {"ms": k.ms, "launches": k.launches, "points": k.points, "bytes": k.bytes}
+        return out
+
+
 class BatchItem(ctypes.Structure):
     _fields_ = [("pts", _vp), ("n", _u64), ("d", _u32), ("reserved", _u32), ("ld", _u64),
                 ("out", TreeStruct)]
@@ -56,6 +74,10 @@ def lib():
         L.kd_build.restype = st
         L.kd_build.argtypes = [_vp, _u64, _u32, _u64, ctypes.POINTER(Params),
                                ctypes.POINTER(TreeStruct), _vp, _u64, _vp]
+        L.kd_build_profiled.restype = st
+        L.kd_build_profiled.argtypes = [_vp, _u64, _u32, _u64, ctypes.POINTER(Params),
+                                        ctypes.POINTER(TreeStruct), _vp, _u64, _vp,
+                                        ctypes.POINTER(Profile)]
         L.kd_batch_bounds.restype = st
         L.kd_batch_bounds.argtypes = [_u32, ctypes.POINTER(BatchItem), ctypes.POINTER(Params),
                                       ctypes.POINTER(_u64)]
@@ -166,8 +188,12 @@ def _stream_ptr(stream):
 
 def build(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
           split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0, node_capacity=0,
-          points_out=True, workspace=None, stream=None):
-    """kd_build on a (d, ld)-strided float32 CUDA tensor of shape (d, n)."""
+          points_out=True, workspace=None, stream=None, tree=None, profile=None):
+    """kd_build on a (d, ld)-strided float32 CUDA tensor of shape (d, n).
+
+    tree: reuse the output arrays of an earlier KDTree of the same shape.
+    profile: a Profile() to fill with per-kernel HIP-event timings.
+    """
     assert points.is_cuda and points.dtype == torch.float32 and points.dim() == 2
     assert points.stride(1) == 1
     d, n = points.shape
@@ -178,10 +204,18 @@ def build(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
     prm.node_capacity = cap
     if workspace is None or workspace.numel() < ws:
         workspace = torch.empty(ws, dtype=torch.uint8, device=points.device)
-    tree = KDTree(n, d, cap, points.device, points_out)
-    _check(lib().kd_build(points.data_ptr(), n, d, ld, ctypes.byref(prm),
-                          ctypes.byref(tree.struct), workspace.data_ptr(), workspace.numel(),
-                          _stream_ptr(stream)), "kd_build")
+    if tree is None or tree.cap < cap or tree.n != n or tree.d != d:
+        tree = KDTree(n, d, cap, points.device, points_out)
+    if profile is None:
+        st = lib().kd_build(points.data_ptr(), n, d, ld, ctypes.byref(prm),
+                            ctypes.byref(tree.struct), workspace.data_ptr(), workspace.numel(),
+                            _stream_ptr(stream))
+    else:
+        st = lib().kd_build_profiled(points.data_ptr(), n, d, ld, ctypes.byref(prm),
+                                     ctypes.byref(tree.struct), workspace.data_ptr(),
+                                     workspace.numel(), _stream_ptr(stream),
+                                     ctypes.byref(profile))
+    _check(st, "kd_build")
     tree.params = prm
     tree.workspace = workspace
     return tree
