@@ -64,8 +64,7 @@ def subset_mean_of_medians(vals, S):
             continue
         med = lower_median_value(vals[lo:hi])
         acc = acc + float(hi - lo) * med
-    mean = float(np.float32(acc / n))
-    return min(max(mean, min(vals)), max(vals))
+    return float(np.float32(acc / n))
 
 
 def build(points, leaf_size, key="cyclic", rule="exact", S=1, max_depth=64):

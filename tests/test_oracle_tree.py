@@ -68,6 +68,29 @@ def test_subset_matches_brute_force(n, S):
     _compare_with_brute(x, 3, "cyclic", "subset", S=S)
 
 
+def test_subset_mean_lies_between_subset_medians():
+    """The fp32-rounded weighted mean never leaves [min, max] of the subset
+    medians, so the tie rule always sees a candidate inside the cell's range."""
+    rng = np.random.default_rng(31)
+    for trial in range(300):
+        n = int(rng.integers(2, 400))
+        S = int(rng.integers(1, 40))
+        kind = trial % 3
+        if kind == 0:
+            vals = rng.standard_normal(n).astype(np.float32)
+        elif kind == 1:
+            vals = np.full(n, np.float32(rng.standard_normal() * 1e3), dtype=np.float32)
+        else:
+            vals = (rng.integers(0, 3, size=n) * np.float32(2.0) ** rng.integers(-20, 20)).astype(np.float32)
+        x = vals[None, :]
+        ok, dim, split, cand = oracle.cell_split(x, np.arange(n), split_rule=oracle.SPLIT_SUBSET,
+                                                 num_subsets=S, leaf_size=1)
+        meds = [brute.lower_median_value([float(v) for v in vals[(r * n) // S:((r + 1) * n) // S]])
+                for r in range(S) if ((r + 1) * n) // S > (r * n) // S]
+        lo, hi = keys_of(np.array([[min(meds), max(meds)]], dtype=np.float32))[0]
+        assert lo <= cand <= hi
+
+
 def test_subset_with_one_subset_is_exact():
     x = synth.gmm(3000, 3, seed=2)
     a = oracle.build_tree(x, leaf_size=16, split_rule=oracle.SPLIT_SUBSET, num_subsets=1)
