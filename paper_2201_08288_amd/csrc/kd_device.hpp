@@ -1,9 +1,11 @@
 // kd_device.hpp -- device-side building blocks of the MI355X k-d tree build:
 // the order-preserving key map, wave64 / workgroup scans and reductions, and
-// the per-level data records shared by the kernels.
+// the per-level records shared by the kernels.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "kdtree.h"
 
 namespace kd {
 
@@ -16,12 +18,20 @@ constexpr int SMALL_MAX = 4096;      // cells up to this size are done by one wo
 constexpr int RBITS = 8;             // radix-select digit width
 constexpr int NBINS = 1 << RBITS;
 constexpr int RPASSES = 32 / RBITS;
+constexpr int MAX_SUBSETS = 4096;
+constexpr int MAX_LEVELS = 128;
+constexpr uint32_t NONE = 0xffffffffu;
 
-// One active cell of the current level: positions [begin, end) of the
-// working buffers, its node id, and the first tile it owns on the
-// large-cell path (cells of <= SMALL_MAX points own no tile).
+// One active cell of the current level.  Cells of all trees of a build form
+// one list ordered by (tree, begin).
 struct Cell {
-    uint32_t begin, end, node, tile0;
+    uint32_t begin, end;  // positions in the tree's working buffers
+    uint32_t node;        // node id in the tree
+    uint32_t tile0;       // first tile on the large-cell path
+    uint32_t big;         // index among the level's large cells, NONE if small
+    uint32_t slot;        // max-variance statistics slot (parent-local index * 2 + side)
+    uint32_t tree;
+    uint32_t pad;
 };
 
 // Per-cell state and result of one level.
@@ -30,30 +40,50 @@ struct CellRes {
     uint32_t split;   // split key: key <= split goes left
     uint32_t nl;      // points going left
     uint32_t flags;   // RES_* bits
-    uint32_t prefix;  // radix-select prefix found so far
+    uint32_t prefix;  // radix-select prefix found so far (large cells)
     uint32_t rank;    // rank still to find below the prefix
-    uint32_t lt;      // keys < candidate
-    uint32_t le;      // keys <= candidate
+    uint32_t cand;    // candidate m of the split rule
+    uint32_t pad;
 };
 constexpr uint32_t RES_SPLIT = 1u;       // the cell is split
 constexpr uint32_t RES_LEFT_LEAF = 2u;   // the left child stops here
 constexpr uint32_t RES_RIGHT_LEAF = 4u;  // the right child stops here
 
-// Device-side counters of the level loop.
-struct LevelInfo {
-    uint32_t num_cells;    // active cells of the level about to run
-    uint32_t num_tiles;    // tiles of its large cells
-    uint32_t num_nodes;    // nodes created so far
-    uint32_t nodes_base;   // num_nodes before the last emit
-    int32_t status;        // KD_OK / KD_ENAN / KD_ECAPACITY
-    uint32_t unsplittable;
-    uint32_t oversize;
-    uint32_t num_leaves;
+// Read-only description of one tree of the build (device memory).
+struct TreeDesc {
+    const uint32_t *pts;  // caller's points as float bits, [d][ld]
+    uint64_t ld;
+    uint32_t *cols[2];    // working copies, [d][n], by level parity
+    uint32_t *perm[2];
+    unsigned long long *stats[2];  // max-variance sums [slot][d][3], by level parity
+    uint32_t *out_perm;
+    uint32_t *pts_out;    // optional permuted points (float bits)
+    uint32_t *node_begin, *node_end;
+    int32_t *node_child;
+    uint32_t *node_dim, *node_split;
+    float *node_split_f;
+    uint32_t *node_leaf, *leaf_node, *leaf_offsets;
+    kd_header *hdr;
+    uint32_t *leaf_cnt, *leaf_first;
+    uint64_t cap;
+    uint32_t n, d;
+};
+
+// Mutable per-tree counters of the level loop (device memory).
+struct TreeState {
+    uint32_t num_nodes, nodes_base, split_base;
+    int32_t status;
+    uint32_t first[2], count[2];   // the tree's cells in the level list of each parity
+    uint32_t maxabs;               // bits of max |x| (max-variance grid)
+    uint32_t depth, unsplittable, oversize;
     unsigned long long point_levels;
-    uint32_t splits;       // cells split by the last level
-    uint32_t points;       // points in the active cells of the level about to run
-    uint32_t big_points;   // ... of which in large cells
-    uint32_t pad[3];
+    uint32_t depth_first[MAX_LEVELS + 2];  // first node id of each depth
+};
+
+// Totals of the level about to run (read back by the host).
+struct LevelInfo {
+    uint32_t num_cells, num_tiles, points, big_points;
+    uint32_t num_big, pad[3];
 };
 
 // Order-preserving map of an fp32 bit pattern onto uint32; -0 folds onto +0.
@@ -79,15 +109,21 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
 #pragma unroll
     for (int o = WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, WAVE);
     return x;
 }
 
-__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, WAVE);
+    for (int o = WAVE / 2; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, WAVE));
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor(x, o, WAVE));
     return x;
 }
 
@@ -114,16 +150,41 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, ui
     return r;
 }
 
-// Workgroup sum of a 64-bit value (result valid in every thread).
-__device__ __forceinline__ unsigned long long block_sum64(unsigned long long v,
-                                                          unsigned long long *sh) {
-    v = wave_sum64(v);
-    if (lane() == 0) sh[wave()] = v;
+// Workgroup sums of N 64-bit values (results valid in every thread).
+// sh: NW * N words of LDS.
+template <int N>
+__device__ __forceinline__ void block_sum64n(unsigned long long *v, unsigned long long *sh) {
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        unsigned long long x = wave_sum64(v[k]);
+        if (lane() == 0) sh[wave() * N + k] = x;
+    }
     __syncthreads();
-    unsigned long long s = 0;
-    for (int i = 0; i < NW; i++) s += sh[i];
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        unsigned long long s = 0;
+        for (int w = 0; w < NW; w++) s += sh[w * N + k];
+        v[k] = s;
+    }
     __syncthreads();
-    return s;
+}
+
+// Workgroup min and max of one value per thread.
+__device__ __forceinline__ void block_minmax(uint32_t &mn, uint32_t &mx, uint32_t *sh) {
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (lane() == 0) {
+        sh[wave()] = mn;
+        sh[NW + wave()] = mx;
+    }
+    __syncthreads();
+    mn = sh[0];
+    mx = sh[NW];
+    for (int w = 1; w < NW; w++) {
+        mn = min(mn, sh[w]);
+        mx = max(mx, sh[NW + w]);
+    }
+    __syncthreads();
 }
 
 // Tie rule shared by every split rule: given the candidate m and the counts
@@ -143,6 +204,34 @@ __device__ __forceinline__ bool tie_rule(uint32_t n, uint32_t lt, uint32_t le, u
         return true;
     }
     return false;
+}
+
+// splitmix64 (Steele, Lea & Flood 2014).
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+    unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Fixed-point grid of the largest-variance key: shift = 30 - E where
+// 2^(E-1) <= max|x| < 2^E (0 when all values are 0).
+__device__ __forceinline__ int maxvar_shift(uint32_t maxabs_bits) {
+    if (maxabs_bits == 0) return 0;
+    const uint32_t eb = maxabs_bits >> 23;
+    int E;
+    if (eb > 0) {
+        E = int(eb) - 126;
+    } else {
+        const uint32_t m = maxabs_bits & 0x7fffffu;
+        E = (32 - __clz(m)) - 149;
+    }
+    return 30 - E;
+}
+
+// q = rint(x * 2^shift) on that grid (|q| <= 2^30).
+__device__ __forceinline__ long long maxvar_q(uint32_t bits, int shift) {
+    return (long long)(int)rintf(ldexpf(__uint_as_float(bits), shift));
 }
 
 }  // namespace kd

@@ -1,0 +1,191 @@
+// kd_fourier.hpp -- the paper's approximate median on one cell's key (§3.1
+// Lemma 3.1, §3.2 Eq. (1)-(2), p = 1), device side.
+//
+// Map step (App. C.2): each point's key is mapped onto [0, 2) by
+// u = (x - min) * 2^(1-e), 2^(e-1) <= max - min < 2^e, so every difference of
+// two mapped values lies in (-2, 2) where the expansion of 1(x < c) holds.
+// In fp32: sin u, cos u by Taylor series (Horner in u^2), then the odd
+// harmonics cos((2j-1)u), sin((2j-1)u) by the angle-addition recurrence with
+// the double angle; each term is quantized as rint(t * 2^24) and summed in
+// int64, so the statistics C_{2j-1}, C_{2j} of the cell are exact and do not
+// depend on how the cell is split into subsets (§3.2).
+// Solve step: the equal-count equation becomes F(v) = 0 with
+//   F(v) = sum_j [C_{2j-1} sin((2j-1)v) - C_{2j} cos((2j-1)v)] / (2j-1),
+// evaluated in fp64; the split is the key reached by bisection over the
+// order-preserving keys between the cell's smallest and largest key.
+// Every multiply and add is a separately rounded IEEE operation (the file is
+// compiled with contraction off).
+#pragma once
+#include "kd_device.hpp"
+
+namespace kd {
+
+constexpr int FOURIER_JMAX = 64;
+constexpr int FCHUNK = 16;  // harmonics accumulated per register chunk
+
+// Series coefficients and weights, filled on the host: term m of the sine
+// series is s[m] * x^(2m+1), of the cosine series c[m] * x^(2m); the values
+// are (-1)^m / (2m+1)! and (-1)^m / (2m)! with the factorial formed by
+// repeated multiplication in double and the quotient rounded to the working
+// precision.  w[j] = 1 / (2j+1).
+struct TrigTables {
+    float s32[9], c32[9];
+    double s64[13], c64[13];
+    double w[FOURIER_JMAX];
+};
+
+__device__ __forceinline__ void sincos32(float x, const TrigTables &T, float &s, float &c) {
+    const float z = x * x;
+    float ps = T.s32[8];
+#pragma unroll
+    for (int m = 7; m >= 0; m--) {
+        ps = ps * z;
+        ps = ps + T.s32[m];
+    }
+    s = x * ps;
+    float pc = T.c32[8];
+#pragma unroll
+    for (int m = 7; m >= 0; m--) {
+        pc = pc * z;
+        pc = pc + T.c32[m];
+    }
+    c = pc;
+}
+
+__device__ __forceinline__ void sincos64(double x, const TrigTables &T, double &s, double &c) {
+    const double z = x * x;
+    double ps = T.s64[12];
+#pragma unroll
+    for (int m = 11; m >= 0; m--) {
+        ps = ps * z;
+        ps = ps + T.s64[m];
+    }
+    s = x * ps;
+    double pc = T.c64[12];
+#pragma unroll
+    for (int m = 11; m >= 0; m--) {
+        pc = pc * z;
+        pc = pc + T.c64[m];
+    }
+    c = pc;
+}
+
+__device__ __forceinline__ double value_of_key(uint32_t u) {
+    return double(__uint_as_float(bits_of_key(u)));
+}
+
+// Exponent e of the cell map: 2^(e-1) <= max - min < 2^e (max > min).
+__device__ __forceinline__ int fourier_exponent(uint32_t lo, uint32_t hi) {
+    const double delta = value_of_key(hi) - value_of_key(lo);
+    const unsigned long long b = __double_as_longlong(delta);
+    return int((b >> 52) & 0x7ff) - 1022;
+}
+
+// Scale 2^(1-e) as an exact double.
+__device__ __forceinline__ double fourier_scale(int e) {
+    return __longlong_as_double((long long)(uint64_t(1023 + 1 - e) << 52));
+}
+
+// Accumulate the quantized harmonics j0 .. j0+FCHUNK-1 of one key into
+// acc[0..FCHUNK) (cosines) and acc[FCHUNK..2*FCHUNK) (sines).
+__device__ __forceinline__ void fourier_terms(uint32_t key, double xmin, double scale, int J,
+                                              int j0, const TrigTables &T, long long *acc) {
+    const double diff = value_of_key(key) - xmin;
+    const float u = float(diff * scale);
+    float s1, c1;
+    sincos32(u, T, s1, c1);
+    const float ss = s1 * s1;
+    const float C2 = 1.0f - 2.0f * ss;
+    const float sc = s1 * c1;
+    const float S2 = 2.0f * sc;
+    float cj = c1, sj = s1;
+    for (int j = 0; j < j0 + FCHUNK && j < J; j++) {
+        if (j >= j0) {
+            acc[j - j0] += (long long)(int)rintf(cj * 16777216.0f);
+            acc[FCHUNK + j - j0] += (long long)(int)rintf(sj * 16777216.0f);
+        }
+        const float a = cj * C2, b = sj * S2;
+        const float g = sj * C2, h = cj * S2;
+        cj = a - b;
+        sj = g + h;
+    }
+}
+
+// F(v) from the summed statistics Cc[j], Cs[j], j = 0..J-1 (harmonic 2j+1).
+__device__ __forceinline__ double fourier_F(const long long *Cc, const long long *Cs, int J,
+                                            double v, const TrigTables &T) {
+    double s1, c1;
+    sincos64(v, T, s1, c1);
+    const double ss = s1 * s1;
+    const double C2 = 1.0 - 2.0 * ss;
+    const double sc = s1 * c1;
+    const double S2 = 2.0 * sc;
+    double cj = c1, sj = s1, F = 0.0;
+    const double q = 1.0 / 16777216.0;
+    for (int j = 0; j < J; j++) {
+        const double a = double(Cc[j]) * q;
+        const double b = double(Cs[j]) * q;
+        const double t1 = a * sj, t2 = b * cj;
+        const double t = t1 - t2;
+        const double wt = T.w[j] * t;
+        F = F + wt;
+        const double p1 = cj * C2, p2 = sj * S2;
+        const double p3 = sj * C2, p4 = cj * S2;
+        cj = p1 - p2;
+        sj = p3 + p4;
+    }
+    return F;
+}
+
+// Bisection for the sign change of F between keys lo < hi, run by one wave64:
+// each round evaluates F at the 63 midpoints of the next six bisection steps
+// in parallel (lane i-1 holds heap node i) and then follows the path the
+// sequential bisection would take, so the result is the sequential one.
+// Returns the key m (lo when F(v(lo)) >= 0).  Every lane gets the result.
+__device__ uint32_t fourier_solve_wave(const long long *Cc, const long long *Cs, int J,
+                                       uint32_t lo, uint32_t hi, int e, const TrigTables &T) {
+    const double xmin = value_of_key(lo);
+    const double scale = fourier_scale(e);
+    const int l = lane();
+    // F at v = 0 (the smallest key)
+    double f0 = 0.0;
+    if (l == 0) f0 = fourier_F(Cc, Cs, J, 0.0, T);
+    f0 = __shfl(f0, 0, WAVE);
+    if (f0 >= 0.0) return lo;
+    while (hi - lo > 1u) {
+        // heap node of this lane and its interval
+        const uint32_t node = uint32_t(l) + 1u;  // 1..64; node 64 unused
+        uint32_t a = lo, b = hi;
+        const int depth = 31 - __clz(node);       // 0..6
+        bool live = node < 64u;
+        for (int t = depth - 1; t >= 0 && live; t--) {
+            if (b - a <= 1u) {
+                live = false;
+                break;
+            }
+            const uint32_t mid = a + (b - a) / 2u;
+            if ((node >> t) & 1u) a = mid;  // right branch: F(mid) < 0
+            else b = mid;                   // left branch: F(mid) >= 0
+        }
+        live = live && (b - a > 1u);
+        const uint32_t mid = a + (b - a) / 2u;
+        double f = 0.0;
+        if (live) f = fourier_F(Cc, Cs, J, (value_of_key(mid) - xmin) * scale, T);
+        const unsigned long long neg = __ballot(live && f < 0.0);
+        // follow the sequential path for up to six steps
+        uint32_t nd = 1;
+        for (int t = 0; t < 6 && hi - lo > 1u; t++) {
+            const uint32_t m2 = lo + (hi - lo) / 2u;
+            if ((neg >> (nd - 1)) & 1ull) {
+                lo = m2;
+                nd = 2 * nd + 1;
+            } else {
+                hi = m2;
+                nd = 2 * nd;
+            }
+        }
+    }
+    return hi;
+}
+
+}  // namespace kd

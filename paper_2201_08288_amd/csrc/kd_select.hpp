@@ -1,0 +1,100 @@
+// kd_select.hpp -- k-th smallest key by radix select (8-bit digits, most
+// significant first) for one workgroup or one wave64, over keys staged in LDS
+// or read from global memory.
+#pragma once
+#include "kd_device.hpp"
+
+namespace kd {
+
+// Memory ordering point for LDS traffic between the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct SelectResult {
+    uint32_t key;  // the k-th smallest key
+    uint32_t lt;   // keys smaller than it
+    uint32_t le;   // keys smaller or equal
+};
+
+// Workgroup radix select.  KEYS(i) yields key i of n; h: NBINS words of LDS;
+// sh: NW+1 words; s3: 3 words.  Every thread gets the result.
+template <class KEYS>
+__device__ SelectResult block_select(KEYS keys, uint32_t n, uint32_t k, uint32_t *h,
+                                     uint32_t *sh, uint32_t *s3) {
+    uint32_t prefix = 0, lt = 0, cnt = 0;
+    for (int pass = 0; pass < RPASSES; pass++) {
+        const int shift = 32 - RBITS * (pass + 1);
+        const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
+        for (int b = threadIdx.x; b < NBINS; b += NT) h[b] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n; i += NT) {
+            uint32_t u = keys(i);
+            if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & (NBINS - 1)], 1u);
+        }
+        __syncthreads();
+        uint32_t hv = h[threadIdx.x], tot;
+        uint32_t ex = block_excl_scan(hv, sh, &tot);
+        if (ex <= k && k < ex + hv) {
+            s3[0] = threadIdx.x;
+            s3[1] = ex;
+            s3[2] = hv;
+        }
+        __syncthreads();
+        prefix |= s3[0] << shift;
+        k -= s3[1];
+        lt += s3[1];
+        cnt = s3[2];
+        __syncthreads();
+    }
+    return SelectResult{prefix, lt, lt + cnt};
+}
+
+// Wave radix select over keys[0..n) in LDS; h: this wave's NBINS words.
+__device__ uint32_t wave_select(const uint32_t *keys, uint32_t n, uint32_t k, uint32_t *h) {
+    uint32_t prefix = 0;
+    const int l = lane();
+    for (int pass = 0; pass < RPASSES; pass++) {
+        const int shift = 32 - RBITS * (pass + 1);
+        const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
+        for (int b = l; b < NBINS; b += WAVE) h[b] = 0;
+        wave_sync();
+        for (uint32_t i = l; i < n; i += WAVE) {
+            uint32_t u = keys[i];
+            if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & (NBINS - 1)], 1u);
+        }
+        wave_sync();
+        // lane l owns bins 4l .. 4l+3
+        uint32_t c[4], local = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            c[j] = h[4 * l + j];
+            local += c[j];
+        }
+        uint32_t ex = wave_incl_scan(local) - local;
+        const bool mine = ex <= k && k < ex + local;
+        const unsigned long long m = __ballot(mine);
+        const int src = __builtin_ctzll(m);  // exactly one lane holds rank k
+        uint32_t bin = 0, below = ex;
+        bool found = false;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (!found && k < below + c[j]) {
+                bin = 4 * l + j;
+                found = true;
+            } else if (!found) {
+                below += c[j];
+            }
+        }
+        bin = __shfl(bin, src, WAVE);
+        below = __shfl(below, src, WAVE);
+        prefix |= bin << shift;
+        k -= below;
+        wave_sync();
+    }
+    return prefix;
+}
+
+}  // namespace kd

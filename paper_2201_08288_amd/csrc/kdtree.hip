@@ -1,19 +1,26 @@
 // kdtree.hip -- MI355X (gfx950) level-by-level k-d tree build behind the C ABI
 // declared in include/kdtree.h.
 //
-// One level (§2: every cell of a level is split along its key at an
-// approximate median, producing the next level's cells):
-//   large cells (> SMALL_MAX points), tile-parallel over TILE-point tiles:
-//     radix-select histograms per tile, added into per-cell histograms
-//     (the "map" and "reduce by +" of App. C.2; tiles are the subsets),
-//     one pick per cell and digit, then a per-tile count, a per-cell scan of
-//     the tile counts and a stable scatter of every column and the perm;
-//   small cells, one workgroup per cell: keys staged in LDS, radix select in
-//     LDS, stable ranks from a workgroup scan, then the same scatter;
-//   emit: node records and the next level's cells (device-wide scan).
+// A build works on one or more trees at once.  The active cells of all trees
+// at the current level form one list, ordered by (tree, position); every
+// kernel below runs over that list, so a batch of trees shares each level's
+// launches.  One level (§2: every cell is split along its key at an
+// (approximate) median into the next level's cells):
+//   a2  key choice: cyclic, or the coordinate of largest variance from exact
+//       fixed-point sums accumulated by the previous level's scatter;
+//   a4/a5 statistic and candidate, by split rule --
+//       EXACT: radix select of the lower median; large cells (> SMALL_MAX
+//         points) add per-tile digit histograms into the cell's histogram
+//         (map per subset, reduce by +, App. C.2), small cells select in LDS;
+//       FOURIER: min/max, int64 sums of quantized harmonics (§3.2 Eq. (1)),
+//         fp64 solve of the equal-count equation (Eq. (2));
+//       SUBSET: lower median of every subset, fp64 mean weighted by subset
+//         size in subset order (not from the paper);
+//   a6  counts below / at the candidate and the tie rule;
+//   a7  stable partition-scatter of every column and the permutation;
+//   a8  emit: breadth-first node records and the next level's cells.
 // Children that stop being split are written straight to their final place
-// in the output permutation (and the optional permuted points), so no
-// separate gather is needed at the end.
+// in the output permutation (and the optional permuted points).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -22,84 +29,46 @@
 
 #include "kdtree.h"
 #include "kd_device.hpp"
+#include "kd_fourier.hpp"
+#include "kd_select.hpp"
 
 using namespace kd;
 
 static_assert(NBINS == NT, "one histogram bin per thread");
 static_assert(PER_THREAD * NT == TILE && SMALL_MAX <= TILE, "tile shape");
+static_assert(2 * FCHUNK <= NT, "moment chunk fits one workgroup");
 
 namespace {
 
-constexpr uint32_t NONE = 0xffffffffu;
-constexpr int EMIT_COUNTERS = 5;  // splits, active children, tiles, points, large-cell points
+constexpr int EMIT_COUNTERS = 8;
 constexpr int EMIT_STRIDE = 8;
+// emit counters: splits, active children, tiles, points, large-cell points,
+// large cells, points of split cells, unsplittable cells
 
 struct Ctx {
-    // working buffers (ping-pong by level parity)
-    uint32_t *cols[2];
-    uint32_t *perm[2];
+    TreeDesc *trees;
+    TreeState *ts;
+    uint32_t ntrees;
     Cell *cells[2];
     CellRes *res;
-    uint32_t *tile_left;
-    uint32_t *tile_off;
+    uint32_t *big_list;
+    uint32_t *tile_lt, *tile_le, *tile_off;
     uint32_t *hist;
+    uint32_t *mm;
+    long long *mom;
+    uint32_t *bounds;
+    uint32_t *med;
+    uint32_t *pre;
     uint32_t *scan_tmp;
     LevelInfo *info;
-    uint32_t *leaf_cnt;
-    uint32_t *leaf_first;
-    // outputs
-    uint32_t *out_perm;
-    uint32_t *pts_out;  // float bits, may be null
-    uint32_t *node_begin, *node_end;
-    int32_t *node_child;
-    uint32_t *node_dim, *node_split;
-    float *node_split_f;
-    uint32_t *node_leaf, *leaf_node, *leaf_offsets;
-    kd_header *hdr;
-    // sizes and parameters
-    uint64_t cap;
-    uint32_t n, d, leaf_size, max_depth;
-    uint32_t key_rule, split_rule, J, S;
+    const uint32_t *pool;
+    uint32_t pool_entries;
+    unsigned long long seed;
+    uint32_t leaf_size, max_depth, key_rule, split_rule, J, S;
+    TrigTables trig;
 };
 
-// ------------------------------------------------------------ sizing
-
-struct Layout {
-    uint64_t off_cols[2], off_perm[2], off_cells[2], off_res, off_tile_left, off_tile_off,
-        off_hist, off_scan, off_info, off_leaf_cnt, off_leaf_first, total;
-    uint64_t max_cells, max_tiles, hist_words, scan_blocks;
-};
-
-uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
-
-Layout layout_for(uint64_t n, uint32_t d, uint32_t leaf_size, uint64_t cap) {
-    Layout L{};
-    L.max_cells = n / (uint64_t(leaf_size) + 1) + 1;
-    L.max_tiles = n / TILE + n / (SMALL_MAX + 1) + 2;
-    L.hist_words = L.max_tiles * NBINS;
-    L.scan_blocks = (L.max_cells + NT - 1) / NT;
-    uint64_t o = 0;
-    auto take = [&](uint64_t bytes) {
-        uint64_t r = o;
-        o = align256(o + bytes);
-        return r;
-    };
-    for (int b = 0; b < 2; b++) L.off_cols[b] = take(uint64_t(d) * n * 4);
-    for (int b = 0; b < 2; b++) L.off_perm[b] = take(n * 4);
-    for (int b = 0; b < 2; b++) L.off_cells[b] = take(L.max_cells * sizeof(Cell));
-    L.off_res = take(L.max_cells * sizeof(CellRes));
-    L.off_tile_left = take(L.max_tiles * 4);
-    L.off_tile_off = take(L.max_tiles * 4);
-    L.off_hist = take(L.hist_words * 4);
-    L.off_scan = take((L.scan_blocks + 1) * EMIT_STRIDE * 4);
-    L.off_info = take(sizeof(LevelInfo));
-    L.off_leaf_cnt = take(cap * 4);
-    L.off_leaf_first = take(cap * 4);
-    L.total = o;
-    return L;
-}
-
-// ------------------------------------------------------------ kernels
+// ------------------------------------------------------------ kernels: setup
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t v) {
     for (uint64_t i = blockIdx.x * uint64_t(NT) + threadIdx.x; i < count;
@@ -107,89 +76,217 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t v) {
         p[i] = v;
 }
 
-__global__ void k_init(Ctx c, uint32_t root_active) {
-    for (uint64_t i = blockIdx.x * uint64_t(NT) + threadIdx.x; i < c.cap;
+__global__ __launch_bounds__(NT) void k_init(Ctx c) {
+    const uint32_t t = blockIdx.y;
+    const TreeDesc T = c.trees[t];
+    for (uint64_t i = blockIdx.x * uint64_t(NT) + threadIdx.x; i < T.cap;
          i += uint64_t(gridDim.x) * NT) {
-        c.node_begin[i] = 0;
-        c.node_end[i] = 0;
-        c.node_child[i] = -1;
-        c.node_dim[i] = 0;
-        c.node_split[i] = 0;
-        c.node_split_f[i] = 0.0f;
-        c.node_leaf[i] = NONE;
+        T.node_begin[i] = 0;
+        T.node_end[i] = 0;
+        T.node_child[i] = -1;
+        T.node_dim[i] = 0;
+        T.node_split[i] = 0;
+        T.node_split_f[i] = 0.0f;
+        T.node_leaf[i] = NONE;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        LevelInfo z{};
-        z.num_nodes = 1;
-        z.num_cells = root_active ? 1u : 0u;
-        z.num_tiles = (root_active && c.n > uint32_t(SMALL_MAX)) ? (c.n + TILE - 1) / TILE : 0u;
-        z.points = root_active ? c.n : 0u;
-        z.big_points = z.num_tiles ? c.n : 0u;
-        *c.info = z;
-        c.node_begin[0] = 0;
-        c.node_end[0] = c.n;
-        Cell root{0u, c.n, 0u, 0u};
-        c.cells[0][0] = root;
+    if (blockIdx.x == 0) {
+        TreeState &S = c.ts[t];
+        for (int k = threadIdx.x; k < MAX_LEVELS + 2; k += NT) S.depth_first[k] = k == 1 ? 1u : 0u;
+        if (c.key_rule == KD_KEY_MAXVAR)
+            for (uint32_t k = threadIdx.x; k < 3 * T.d; k += NT) T.stats[0][k] = 0;
+        if (threadIdx.x == 0) {
+            S.num_nodes = 1;
+            S.nodes_base = 0;
+            S.split_base = 0;
+            S.status = KD_OK;
+            S.first[0] = S.first[1] = 0;
+            S.count[0] = S.count[1] = 0;
+            S.maxabs = 0;
+            S.depth = 0;
+            S.unsplittable = 0;
+            S.oversize = 0;
+            S.point_levels = 0;
+            T.node_begin[0] = 0;
+            T.node_end[0] = T.n;
+        }
     }
 }
 
 // a1: copy the caller's points into working buffer 0 (float bits), identity
-// permutation, reject NaN / Inf.
-__global__ void k_ingest(Ctx c, const float *pts, uint64_t ld) {
-    const uint32_t col = blockIdx.y;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(pts) + uint64_t(col) * ld;
-    uint32_t *dst = c.cols[0] + uint64_t(col) * c.n;
+// permutation, reject NaN / Inf; max |x| for the largest-variance grid.
+__global__ __launch_bounds__(NT) void k_ingest(Ctx c) {
+    const uint32_t t = blockIdx.y;
+    const TreeDesc T = c.trees[t];
     bool bad = false;
-    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < c.n; i += gridDim.x * NT) {
-        uint32_t b = src[i];
-        bad |= (b & 0x7f800000u) == 0x7f800000u;
-        dst[i] = b;
-        if (col == 0) c.perm[0][i] = i;
+    uint32_t mx = 0;
+    for (uint32_t col = 0; col < T.d; col++) {
+        const uint32_t *src = T.pts + uint64_t(col) * T.ld;
+        uint32_t *dst = T.cols[0] + uint64_t(col) * T.n;
+        for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < T.n; i += gridDim.x * NT) {
+            const uint32_t b = src[i];
+            const bool nf = (b & 0x7f800000u) == 0x7f800000u;
+            bad |= nf;
+            if (!nf) mx = max(mx, b & 0x7fffffffu);
+            dst[i] = b;
+            if (col == 0) T.perm[0][i] = i;
+        }
     }
-    if (__any(bad) && lane() == 0) atomicExch(&c.info->status, int32_t(KD_ENAN));
+    if (__any(bad) && lane() == 0) atomicExch(&c.ts[t].status, int32_t(KD_ENAN));
+    if (c.key_rule == KD_KEY_MAXVAR) {
+        mx = wave_max(mx);
+        if (lane() == 0 && mx) atomicMax(&c.ts[t].maxabs, mx);
+    }
 }
 
-// Root that is already a leaf: everything goes straight to the outputs.
-__global__ void k_copy_all(Ctx c) {
-    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < c.n; i += gridDim.x * NT) {
-        c.out_perm[i] = c.perm[0][i];
-        if (c.pts_out)
-            for (uint32_t k = 0; k < c.d; k++)
-                c.pts_out[uint64_t(k) * c.n + i] = c.cols[0][uint64_t(k) * c.n + i];
+// Root cells of all trees whose root is split (one workgroup).
+__global__ __launch_bounds__(NT) void k_roots(Ctx c) {
+    __shared__ uint32_t sh[NW + 1];
+    uint32_t base[5] = {0, 0, 0, 0, 0};  // cells, tiles, points, big points, big cells
+    for (uint32_t t0 = 0; t0 < c.ntrees; t0 += NT) {
+        const uint32_t t = t0 + threadIdx.x;
+        uint32_t v[5] = {0, 0, 0, 0, 0};
+        uint32_t n = 0;
+        if (t < c.ntrees) {
+            n = c.trees[t].n;
+            const bool active = c.ts[t].status == KD_OK && n > c.leaf_size && c.max_depth > 0;
+            if (active) {
+                const bool big = n > uint32_t(SMALL_MAX);
+                v[0] = 1;
+                v[1] = big ? (n + TILE - 1) / TILE : 0u;
+                v[2] = n;
+                v[3] = big ? n : 0u;
+                v[4] = big ? 1u : 0u;
+            }
+        }
+        uint32_t pre[5];
+        for (int k = 0; k < 5; k++) {
+            uint32_t tot;
+            pre[k] = base[k] + block_excl_scan(v[k], sh, &tot);
+            base[k] += tot;
+        }
+        if (t < c.ntrees) {
+            TreeState &S = c.ts[t];
+            S.first[0] = pre[0];
+            S.count[0] = v[0];
+            if (v[0]) {
+                Cell cl{0u, n, 0u, pre[1], v[4] ? pre[4] : NONE, 0u, t, 0u};
+                c.cells[0][pre[0]] = cl;
+                if (v[4]) c.big_list[pre[4]] = pre[0];
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        LevelInfo in{};
+        in.num_cells = base[0];
+        in.num_tiles = base[1];
+        in.points = base[2];
+        in.big_points = base[3];
+        in.num_big = base[4];
+        *c.info = in;
     }
 }
 
-// Per-level cell state: key coordinate and radix-select start.
-__global__ void k_level_init(Ctx c, uint32_t level, uint32_t ncells) {
-    const uint32_t cur = level & 1;
-    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < ncells; i += gridDim.x * NT) {
-        Cell cl = c.cells[cur][i];
+// Largest-variance sums of the root cells (slot 0 of parity 0).
+__global__ __launch_bounds__(NT) void k_root_stats(Ctx c) {
+    __shared__ unsigned long long sh64[NW * 3];
+    const uint32_t t = blockIdx.y;
+    const TreeState &S = c.ts[t];
+    if (S.count[0] == 0) return;
+    const TreeDesc T = c.trees[t];
+    const int shift = maxvar_shift(S.maxabs);
+    for (uint32_t col = 0; col < T.d; col++) {
+        const uint32_t *src = T.cols[0] + uint64_t(col) * T.n;
+        unsigned long long v[3] = {0, 0, 0};
+        for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < T.n; i += gridDim.x * NT) {
+            const long long q = maxvar_q(src[i], shift);
+            const unsigned long long q2 = (unsigned long long)(q * q);
+            v[0] += (unsigned long long)q;
+            v[1] += q2 >> 32;
+            v[2] += q2 & 0xffffffffull;
+        }
+        block_sum64n<3>(v, sh64);
+        if (threadIdx.x < 3) atomicAdd(&T.stats[0][col * 3 + threadIdx.x], v[threadIdx.x]);
+    }
+}
+
+// Trees whose root is a leaf: everything goes straight to the outputs.
+__global__ __launch_bounds__(NT) void k_copy_leafroots(Ctx c) {
+    const uint32_t t = blockIdx.y;
+    const TreeState &S = c.ts[t];
+    if (S.count[0] != 0 || S.status != KD_OK) return;
+    const TreeDesc T = c.trees[t];
+    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < T.n; i += gridDim.x * NT) {
+        T.out_perm[i] = i;
+        if (T.pts_out)
+            for (uint32_t k = 0; k < T.d; k++)
+                T.pts_out[uint64_t(k) * T.n + i] = T.cols[0][uint64_t(k) * T.n + i];
+    }
+}
+
+// ------------------------------------------------------------ kernels: per level
+
+// a2 and per-level state: key coordinate, select start, zeroed accumulators.
+__global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level, uint32_t ncells) {
+    const uint32_t cur = level & 1, nxt = cur ^ 1;
+    for (uint32_t ci = blockIdx.x * NT + threadIdx.x; ci < ncells; ci += gridDim.x * NT) {
+        const Cell cl = c.cells[cur][ci];
+        const TreeDesc &T = c.trees[cl.tree];
         CellRes r{};
-        r.dim = level % c.d;
+        if (c.key_rule == KD_KEY_MAXVAR) {
+            const unsigned long long *st = T.stats[cur] + uint64_t(cl.slot) * T.d * 3;
+            const __int128 n_c = cl.end - cl.begin;
+            __int128 best = -1;
+            uint32_t bd = 0;
+            for (uint32_t k = 0; k < T.d; k++) {
+                const long long s1 = (long long)st[3 * k];
+                const __int128 s2 = ((__int128)st[3 * k + 1] << 32) + (__int128)st[3 * k + 2];
+                const __int128 V = n_c * s2 - (__int128)s1 * (__int128)s1;
+                if (V > best) {
+                    best = V;
+                    bd = k;
+                }
+            }
+            r.dim = bd;
+        } else {
+            r.dim = level % T.d;
+        }
         r.rank = (cl.end - cl.begin - 1) / 2;
-        r.split = 0;
-        c.res[i] = r;
+        c.res[ci] = r;
+        if (cl.big != NONE) {
+            if (c.split_rule == KD_SPLIT_FOURIER) {
+                c.mm[2 * cl.big] = NONE;
+                c.mm[2 * cl.big + 1] = 0;
+                long long *m = c.mom + uint64_t(cl.big) * 2 * FOURIER_JMAX;
+                for (int j = 0; j < 2 * FOURIER_JMAX; j++) m[j] = 0;
+            }
+            if (c.key_rule == KD_KEY_MAXVAR) {
+                const uint32_t li = ci - c.ts[cl.tree].first[cur];
+                unsigned long long *st = T.stats[nxt] + uint64_t(2 * li) * T.d * 3;
+                for (uint32_t k = 0; k < 6 * T.d; k++) st[k] = 0;
+            }
+        }
     }
 }
 
 __device__ __forceinline__ uint32_t find_tile_cell(const Cell *cells, uint32_t ncells, uint32_t t) {
     uint32_t lo = 0, hi = ncells;
     while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
+        const uint32_t mid = (lo + hi) >> 1;
         if (cells[mid].tile0 <= t) lo = mid;
         else hi = mid;
     }
     return lo;
 }
 
-// After the candidate m and its counts are known: tie rule and leaf flags.
+// Tie rule and leaf flags once the candidate and its counts are known.
 __device__ __forceinline__ void finish_cell(const Ctx &c, uint32_t level, uint32_t n_c, CellRes &r,
-                                            uint32_t m) {
+                                            uint32_t m, uint32_t lt, uint32_t le) {
     uint32_t split, nl;
-    if (tie_rule(n_c, r.lt, r.le, m, &split, &nl)) {
+    r.cand = m;
+    if (tie_rule(n_c, lt, le, m, &split, &nl)) {
         r.split = split;
         r.nl = nl;
-        bool deep = level + 1 >= c.max_depth;
+        const bool deep = level + 1 >= c.max_depth;
         r.flags = RES_SPLIT | ((nl <= c.leaf_size || deep) ? RES_LEFT_LEAF : 0u) |
                   ((n_c - nl <= c.leaf_size || deep) ? RES_RIGHT_LEAF : 0u);
     } else {
@@ -200,8 +297,25 @@ __device__ __forceinline__ void finish_cell(const Ctx &c, uint32_t level, uint32
     }
 }
 
-// a4 (EXACT, large cells): one radix-select digit histogram per tile, added
-// into the cell's histogram.
+// Tile t of the level's large cells: its cell and position range.
+struct TileView {
+    uint32_t ci, tb, te;
+    Cell cl;
+};
+
+__device__ __forceinline__ TileView tile_view(const Ctx &c, uint32_t cur, uint32_t ncells,
+                                              uint32_t t, uint32_t *s_cell) {
+    if (threadIdx.x == 0) *s_cell = find_tile_cell(c.cells[cur], ncells, t);
+    __syncthreads();
+    TileView v;
+    v.ci = *s_cell;
+    v.cl = c.cells[cur][v.ci];
+    v.tb = v.cl.begin + (t - v.cl.tile0) * TILE;
+    v.te = min(v.tb + TILE, v.cl.end);
+    return v;
+}
+
+// EXACT, large cells: one digit histogram per tile added into the cell's.
 __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t pass,
                                                  uint32_t ncells, uint32_t ntiles) {
     __shared__ uint32_t h[NBINS];
@@ -210,239 +324,494 @@ __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t
     const int shift = 32 - RBITS * (pass + 1);
     const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        if (threadIdx.x == 0) s_cell = find_tile_cell(c.cells[cur], ncells, t);
         for (int b = threadIdx.x; b < NBINS; b += NT) h[b] = 0;
-        __syncthreads();
-        const uint32_t ci = s_cell;
-        const Cell cl = c.cells[cur][ci];
-        const CellRes r = c.res[ci];
-        const uint32_t tb = cl.begin + (t - cl.tile0) * TILE;
-        const uint32_t te = min(tb + TILE, cl.end);
-        const uint32_t *col = c.cols[cur] + uint64_t(r.dim) * c.n;
-        for (uint32_t i = tb + threadIdx.x; i < te; i += NT) {
-            uint32_t u = key_of_bits(col[i]);
+        const TileView v = tile_view(c, cur, ncells, t, &s_cell);
+        const CellRes r = c.res[v.ci];
+        const TreeDesc &T = c.trees[v.cl.tree];
+        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n;
+        for (uint32_t i = v.tb + threadIdx.x; i < v.te; i += NT) {
+            const uint32_t u = key_of_bits(col[i]);
             if ((u & mask) == r.prefix) atomicAdd(&h[(u >> shift) & (NBINS - 1)], 1u);
         }
         __syncthreads();
-        uint32_t *gh = c.hist + uint64_t(cl.tile0) * NBINS;
+        uint32_t *gh = c.hist + uint64_t(v.cl.big) * NBINS;
         for (int b = threadIdx.x; b < NBINS; b += NT)
             if (h[b]) atomicAdd(&gh[b], h[b]);
         __syncthreads();
     }
 }
 
-// a5 (EXACT, large cells): pick the digit holding the target rank.
+// EXACT, large cells: pick the digit that holds the target rank.
 __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t pass,
-                                                 uint32_t ncells) {
+                                                 uint32_t nbig) {
     __shared__ uint32_t sh[NW + 1];
-    __shared__ uint32_t s_bin, s_below, s_cnt;
-    const uint32_t cur = level & 1;
+    __shared__ uint32_t s_bin, s_below;
     const int shift = 32 - RBITS * (pass + 1);
-    for (uint32_t ci = blockIdx.x; ci < ncells; ci += gridDim.x) {
-        const Cell cl = c.cells[cur][ci];
-        const uint32_t n_c = cl.end - cl.begin;
-        if (n_c <= uint32_t(SMALL_MAX)) continue;
+    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const uint32_t ci = c.big_list[b];
         CellRes r = c.res[ci];
-        uint32_t *gh = c.hist + uint64_t(cl.tile0) * NBINS;
-        uint32_t hv = gh[threadIdx.x];
+        uint32_t *gh = c.hist + uint64_t(b) * NBINS;
+        const uint32_t hv = gh[threadIdx.x];
         gh[threadIdx.x] = 0;
         uint32_t tot;
-        uint32_t ex = block_excl_scan(hv, sh, &tot);
+        const uint32_t ex = block_excl_scan(hv, sh, &tot);
         if (ex <= r.rank && r.rank < ex + hv) {
             s_bin = threadIdx.x;
             s_below = ex;
-            s_cnt = hv;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             r.prefix |= s_bin << shift;
             r.rank -= s_below;
-            r.lt += s_below;
-            if (pass == RPASSES - 1) {
-                r.le = r.lt + s_cnt;
-                finish_cell(c, level, n_c, r, r.prefix);
-            }
+            if (pass == RPASSES - 1) r.cand = r.prefix;
             c.res[ci] = r;
         }
         __syncthreads();
     }
 }
 
-// a6/a7 (large cells): left count of every tile.
+// FOURIER, large cells: smallest and largest key of every cell.
+__global__ __launch_bounds__(NT) void k_big_minmax(Ctx c, uint32_t level, uint32_t ncells,
+                                                   uint32_t ntiles) {
+    __shared__ uint32_t s_cell;
+    __shared__ uint32_t sh[2 * NW];
+    const uint32_t cur = level & 1;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const TileView v = tile_view(c, cur, ncells, t, &s_cell);
+        const CellRes r = c.res[v.ci];
+        const TreeDesc &T = c.trees[v.cl.tree];
+        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n;
+        uint32_t mn = NONE, mx = 0;
+        for (uint32_t i = v.tb + threadIdx.x; i < v.te; i += NT) {
+            const uint32_t u = key_of_bits(col[i]);
+            mn = min(mn, u);
+            mx = max(mx, u);
+        }
+        block_minmax(mn, mx, sh);
+        if (threadIdx.x == 0) {
+            atomicMin(&c.mm[2 * v.cl.big], mn);
+            atomicMax(&c.mm[2 * v.cl.big + 1], mx);
+        }
+    }
+}
+
+// Sum one chunk of per-thread moment accumulators over the workgroup into
+// dst[j0 + k] (cosines) and dst[FOURIER_JMAX + j0 + k] (sines), atomically
+// when several workgroups share the cell.
+__device__ __forceinline__ void reduce_moments(long long *acc, unsigned long long *sh64, int j0,
+                                               int J, long long *dst, bool atomic) {
+#pragma unroll
+    for (int k = 0; k < 2 * FCHUNK; k++) {
+        const unsigned long long x = wave_sum64((unsigned long long)acc[k]);
+        if (lane() == 0) sh64[wave() * 2 * FCHUNK + k] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * FCHUNK) {
+        const int k = threadIdx.x, j = j0 + (k % FCHUNK);
+        if (j < J) {
+            unsigned long long s = 0;
+            for (int w = 0; w < NW; w++) s += sh64[w * 2 * FCHUNK + k];
+            long long *d = dst + (k < FCHUNK ? 0 : FOURIER_JMAX) + j;
+            if (atomic) atomicAdd((unsigned long long *)d, s);
+            else *d = (long long)s;
+        }
+    }
+    __syncthreads();
+}
+
+// FOURIER, large cells: the map step (quantized harmonics summed per cell).
+__global__ __launch_bounds__(NT) void k_big_moments(Ctx c, uint32_t level, uint32_t ncells,
+                                                    uint32_t ntiles) {
+    __shared__ uint32_t s_cell;
+    __shared__ unsigned long long sh64[NW * 2 * FCHUNK];
+    const uint32_t cur = level & 1;
+    const int J = int(c.J);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const TileView v = tile_view(c, cur, ncells, t, &s_cell);
+        const uint32_t lo = c.mm[2 * v.cl.big], hi = c.mm[2 * v.cl.big + 1];
+        if (lo == hi) {
+            __syncthreads();
+            continue;
+        }
+        const CellRes r = c.res[v.ci];
+        const TreeDesc &T = c.trees[v.cl.tree];
+        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n;
+        const int e = fourier_exponent(lo, hi);
+        const double xmin = value_of_key(lo), scale = fourier_scale(e);
+        long long *dst = c.mom + uint64_t(v.cl.big) * 2 * FOURIER_JMAX;
+        for (int j0 = 0; j0 < J; j0 += FCHUNK) {
+            long long acc[2 * FCHUNK];
+#pragma unroll
+            for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
+            for (uint32_t i = v.tb + threadIdx.x; i < v.te; i += NT)
+                fourier_terms(key_of_bits(col[i]), xmin, scale, J, j0, c.trig, acc);
+            reduce_moments(acc, sh64, j0, J, dst, true);
+        }
+    }
+}
+
+// FOURIER, large cells: solve Eq. (2) for the candidate (one wave per cell).
+__global__ __launch_bounds__(NT) void k_big_fsolve(Ctx c, uint32_t level, uint32_t nbig) {
+    const uint32_t b = blockIdx.x * NW + wave();
+    if (b >= nbig) return;
+    const uint32_t ci = c.big_list[b];
+    const uint32_t lo = c.mm[2 * b], hi = c.mm[2 * b + 1];
+    uint32_t m = lo;
+    if (lo != hi) {
+        const long long *mom = c.mom + uint64_t(b) * 2 * FOURIER_JMAX;
+        m = fourier_solve_wave(mom, mom + FOURIER_JMAX, int(c.J), lo, hi,
+                               fourier_exponent(lo, hi), c.trig);
+    }
+    if (lane() == 0) c.res[ci].cand = m;
+}
+
+// Subset boundaries of a cell (§3.2: any partition; App. C.2: {r, X_r}).
+// Equal: floor(r * n / S).  Pool: row splitmix64(seed ^ depth << 32 ^ rank)
+// mod P of cumulative 32-bit weights, bounds[r] = max(bounds[r-1], n*W_r >> 32).
+__device__ __forceinline__ void subset_bounds(const Ctx &c, uint32_t n, uint32_t level,
+                                              uint32_t rank, uint32_t *B) {
+    const uint32_t S = c.S;
+    if (!c.pool) {
+        for (uint32_t r = 0; r <= S; r++) B[r] = uint32_t((uint64_t(r) * n) / S);
+        return;
+    }
+    const unsigned long long k =
+        splitmix64(c.seed ^ ((unsigned long long)level << 32) ^ (unsigned long long)rank) %
+        c.pool_entries;
+    const uint32_t *W = c.pool + k * S;
+    B[0] = 0;
+    for (uint32_t r = 1; r < S; r++) {
+        const uint32_t b = uint32_t((uint64_t(n) * W[r]) >> 32);
+        B[r] = max(b, B[r - 1]);
+    }
+    B[S] = n;
+}
+
+// Size-weighted mean of the subset lower medians, in subset order (fp64),
+// rounded to fp32 and mapped to a key.
+__device__ __forceinline__ uint32_t subset_mean(const uint32_t *B, const uint32_t *med,
+                                                uint32_t S, uint32_t n_c) {
+    double acc = 0.0;
+    for (uint32_t r = 0; r < S; r++) {
+        const uint32_t ns = B[r + 1] - B[r];
+        if (ns == 0) continue;
+        const double prod = double(ns) * value_of_key(med[r]);
+        acc = acc + prod;
+    }
+    const double mean = acc / double(n_c);
+    return key_of_bits(__float_as_uint(float(mean)));
+}
+
+// SUBSET, large cells: subset bounds of every cell.
+__global__ __launch_bounds__(NT) void k_big_bounds(Ctx c, uint32_t level, uint32_t nbig) {
+    const uint32_t cur = level & 1;
+    for (uint32_t b = blockIdx.x * NT + threadIdx.x; b < nbig; b += gridDim.x * NT) {
+        const uint32_t ci = c.big_list[b];
+        const Cell cl = c.cells[cur][ci];
+        subset_bounds(c, cl.end - cl.begin, level, ci - c.ts[cl.tree].first[cur],
+                      c.bounds + uint64_t(b) * (c.S + 1));
+    }
+}
+
+// SUBSET, large cells: lower median of one subset per workgroup.
+__global__ __launch_bounds__(NT) void k_subset_select(Ctx c, uint32_t level, uint32_t nbig) {
+    __shared__ uint32_t keys[SMALL_MAX];
+    __shared__ uint32_t h[NBINS];
+    __shared__ uint32_t sh[NW + 1], s3[3];
+    const uint32_t cur = level & 1;
+    const uint64_t jobs = uint64_t(nbig) * c.S;
+    for (uint64_t job = blockIdx.x; job < jobs; job += gridDim.x) {
+        const uint32_t b = uint32_t(job / c.S), s = uint32_t(job % c.S);
+        const uint32_t ci = c.big_list[b];
+        const Cell cl = c.cells[cur][ci];
+        const CellRes r = c.res[ci];
+        const TreeDesc &T = c.trees[cl.tree];
+        const uint32_t *B = c.bounds + uint64_t(b) * (c.S + 1);
+        const uint32_t sb = cl.begin + B[s], ns = B[s + 1] - B[s];
+        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n + sb;
+        uint32_t m = NONE;
+        if (ns > 0 && ns <= uint32_t(SMALL_MAX)) {
+            for (uint32_t i = threadIdx.x; i < ns; i += NT) keys[i] = key_of_bits(col[i]);
+            __syncthreads();
+            m = block_select([&](uint32_t i) { return keys[i]; }, ns, (ns - 1) / 2, h, sh, s3).key;
+        } else if (ns > 0) {
+            m = block_select([&](uint32_t i) { return key_of_bits(col[i]); }, ns, (ns - 1) / 2, h,
+                             sh, s3).key;
+        }
+        if (threadIdx.x == 0) c.med[uint64_t(b) * c.S + s] = m;
+        __syncthreads();
+    }
+}
+
+// SUBSET, large cells: the weighted mean (one thread per cell).
+__global__ __launch_bounds__(NT) void k_subset_mean(Ctx c, uint32_t level, uint32_t nbig) {
+    const uint32_t cur = level & 1;
+    for (uint32_t b = blockIdx.x * NT + threadIdx.x; b < nbig; b += gridDim.x * NT) {
+        const uint32_t ci = c.big_list[b];
+        const Cell cl = c.cells[cur][ci];
+        c.res[ci].cand = subset_mean(c.bounds + uint64_t(b) * (c.S + 1),
+                                     c.med + uint64_t(b) * c.S, c.S, cl.end - cl.begin);
+    }
+}
+
+// a6, large cells: per tile, keys below and at the candidate.
 __global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level, uint32_t ncells,
                                                   uint32_t ntiles) {
     __shared__ uint32_t s_cell;
     __shared__ uint32_t sh[NW + 1];
     const uint32_t cur = level & 1;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        if (threadIdx.x == 0) s_cell = find_tile_cell(c.cells[cur], ncells, t);
-        __syncthreads();
-        const uint32_t ci = s_cell;
-        const Cell cl = c.cells[cur][ci];
-        const CellRes r = c.res[ci];
-        const uint32_t tb = cl.begin + (t - cl.tile0) * TILE;
-        const uint32_t te = min(tb + TILE, cl.end);
-        uint32_t cnt = 0;
-        if (r.flags & RES_SPLIT) {
-            const uint32_t *col = c.cols[cur] + uint64_t(r.dim) * c.n;
-            for (uint32_t i = tb + threadIdx.x; i < te; i += NT)
-                cnt += key_of_bits(col[i]) <= r.split;
+        const TileView v = tile_view(c, cur, ncells, t, &s_cell);
+        const CellRes r = c.res[v.ci];
+        const TreeDesc &T = c.trees[v.cl.tree];
+        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n;
+        uint32_t lt = 0, le = 0;
+        for (uint32_t i = v.tb + threadIdx.x; i < v.te; i += NT) {
+            const uint32_t u = key_of_bits(col[i]);
+            lt += u < r.cand;
+            le += u <= r.cand;
         }
-        uint32_t tot;
-        block_excl_scan(cnt, sh, &tot);
-        if (threadIdx.x == 0) c.tile_left[t] = tot;
+        uint32_t tlt, tle;
+        block_excl_scan(lt, sh, &tlt);
+        block_excl_scan(le, sh, &tle);
+        if (threadIdx.x == 0) {
+            c.tile_lt[t] = tlt;
+            c.tile_le[t] = tle;
+        }
     }
 }
 
-// Exclusive scan of the tile left counts inside each large cell.
-__global__ __launch_bounds__(NT) void k_big_tilescan(Ctx c, uint32_t level, uint32_t ncells) {
+// a6, large cells: tie rule, then the exclusive scan of the chosen tile counts.
+__global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level, uint32_t nbig) {
     __shared__ uint32_t sh[NW + 1];
     const uint32_t cur = level & 1;
-    for (uint32_t ci = blockIdx.x; ci < ncells; ci += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const uint32_t ci = c.big_list[b];
         const Cell cl = c.cells[cur][ci];
         const uint32_t n_c = cl.end - cl.begin;
-        if (n_c <= uint32_t(SMALL_MAX)) continue;
         const uint32_t nt = (n_c + TILE - 1) / TILE;
+        uint32_t lt = 0, le = 0;
+        for (uint32_t k0 = 0; k0 < nt; k0 += NT) {
+            const uint32_t k = k0 + threadIdx.x;
+            const uint32_t a = k < nt ? c.tile_lt[cl.tile0 + k] : 0u;
+            const uint32_t e = k < nt ? c.tile_le[cl.tile0 + k] : 0u;
+            uint32_t ta, te;
+            block_excl_scan(a, sh, &ta);
+            block_excl_scan(e, sh, &te);
+            lt += ta;
+            le += te;
+        }
+        CellRes r = c.res[ci];
+        finish_cell(c, level, n_c, r, r.cand, lt, le);
+        const bool use_le = (r.flags & RES_SPLIT) && r.split == r.cand;
         uint32_t base = 0;
         for (uint32_t k0 = 0; k0 < nt; k0 += NT) {
-            uint32_t k = k0 + threadIdx.x;
-            uint32_t v = k < nt ? c.tile_left[cl.tile0 + k] : 0u;
+            const uint32_t k = k0 + threadIdx.x;
+            uint32_t v = 0;
+            if (k < nt) v = use_le ? c.tile_le[cl.tile0 + k] : c.tile_lt[cl.tile0 + k];
             uint32_t tot;
-            uint32_t ex = block_excl_scan(v, sh, &tot);
+            const uint32_t ex = block_excl_scan(v, sh, &tot);
             if (k < nt) c.tile_off[cl.tile0 + k] = base + ex;
             base += tot;
         }
+        if (threadIdx.x == 0) c.res[ci] = r;
+        __syncthreads();
     }
 }
 
-// Move every column and the permutation of positions [tb, tb+cnt) of cell
-// cl to cell-relative destinations dest[] (LDS).  Children that stop here
-// go to the outputs, the others to the next working buffer.
+// a7: move every column and the permutation of positions [tb, tb+cnt) of cell
+// cl to cell-relative destinations dest[] (LDS).  Children that stop here go
+// to the outputs, the others to the next working buffer.  With the
+// largest-variance key, the children's fixed-point sums are accumulated on
+// the way (atomically when several tiles share the cell).
 __device__ __forceinline__ void move_columns(const Ctx &c, uint32_t cur, const Cell &cl,
-                                             const CellRes &r, uint32_t tb, uint32_t cnt,
-                                             const uint32_t *dest) {
+                                             const CellRes &r, uint32_t li, uint32_t tb,
+                                             uint32_t cnt, const uint32_t *dest,
+                                             unsigned long long *sh64, bool atomic) {
     const uint32_t nxt = cur ^ 1;
+    const TreeDesc &T = c.trees[cl.tree];
     const uint32_t n_c = cl.end - cl.begin;
     const bool lleaf = r.flags & RES_LEFT_LEAF, rleaf = r.flags & RES_RIGHT_LEAF;
-    for (uint32_t k = 0; k <= c.d; k++) {
-        const bool is_perm = k == c.d;
-        const uint32_t *src = is_perm ? c.perm[cur] : c.cols[cur] + uint64_t(k) * c.n;
-        uint32_t *dnext = is_perm ? c.perm[nxt] : c.cols[nxt] + uint64_t(k) * c.n;
-        uint32_t *dout = is_perm ? c.out_perm : (c.pts_out ? c.pts_out + uint64_t(k) * c.n : nullptr);
+    const bool stats = c.key_rule == KD_KEY_MAXVAR && (r.flags & RES_SPLIT) && !(lleaf && rleaf);
+    const int shift = stats ? maxvar_shift(c.ts[cl.tree].maxabs) : 0;
+    for (uint32_t k = 0; k <= T.d; k++) {
+        const bool is_perm = k == T.d;
+        const uint32_t *src = is_perm ? T.perm[cur] : T.cols[cur] + uint64_t(k) * T.n;
+        uint32_t *dnext = is_perm ? T.perm[nxt] : T.cols[nxt] + uint64_t(k) * T.n;
+        uint32_t *dout =
+            is_perm ? T.out_perm : (T.pts_out ? T.pts_out + uint64_t(k) * T.n : nullptr);
         uint32_t v[PER_THREAD];
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
-            uint32_t i = j * NT + threadIdx.x;
+            const uint32_t i = j * NT + threadIdx.x;
             if (i < cnt) v[j] = src[tb + i];
         }
+        unsigned long long acc[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
-            uint32_t i = j * NT + threadIdx.x;
+            const uint32_t i = j * NT + threadIdx.x;
             if (i < cnt) {
-                uint32_t dr = dest[i];
-                bool leaf = dr < r.nl ? lleaf : rleaf;
+                const uint32_t dr = dest[i];
+                const bool right = dr >= r.nl;
+                const bool leaf = right ? rleaf : lleaf;
                 uint32_t *dst = leaf ? dout : dnext;
                 if (dst && dr < n_c) dst[cl.begin + dr] = v[j];
+                if (stats && !is_perm && !leaf) {
+                    const long long q = maxvar_q(v[j], shift);
+                    const unsigned long long q2 = (unsigned long long)(q * q);
+                    const int o = right ? 3 : 0;
+                    acc[o] += (unsigned long long)q;
+                    acc[o + 1] += q2 >> 32;
+                    acc[o + 2] += q2 & 0xffffffffull;
+                }
+            }
+        }
+        if (stats && !is_perm) {
+            block_sum64n<6>(acc, sh64);
+            if (threadIdx.x < 6) {
+                const int side = threadIdx.x / 3, j = threadIdx.x % 3;
+                if (!(side ? rleaf : lleaf)) {
+                    unsigned long long *st =
+                        T.stats[nxt] + (uint64_t(2 * li + side) * T.d + k) * 3 + j;
+                    if (atomic) atomicAdd(st, acc[threadIdx.x]);
+                    else *st = acc[threadIdx.x];
+                }
             }
         }
     }
 }
 
-// a7 (large cells): stable partition-scatter of one tile.
+// a7, large cells: stable partition-scatter of one tile.
 __global__ __launch_bounds__(NT) void k_big_scatter(Ctx c, uint32_t level, uint32_t ncells,
                                                     uint32_t ntiles) {
     __shared__ uint32_t dest[TILE];
     __shared__ uint32_t sh[NW + 1];
     __shared__ uint32_t s_cell;
+    __shared__ unsigned long long sh64[NW * 6];
     const uint32_t cur = level & 1;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        if (threadIdx.x == 0) s_cell = find_tile_cell(c.cells[cur], ncells, t);
-        __syncthreads();
-        const uint32_t ci = s_cell;
-        const Cell cl = c.cells[cur][ci];
-        const CellRes r = c.res[ci];
-        const uint32_t tb = cl.begin + (t - cl.tile0) * TILE;
-        const uint32_t te = min(tb + TILE, cl.end);
-        const uint32_t cnt = te - tb;
+        const TileView v = tile_view(c, cur, ncells, t, &s_cell);
+        const CellRes r = c.res[v.ci];
+        const TreeDesc &T = c.trees[v.cl.tree];
+        const uint32_t cnt = v.te - v.tb;
         if (r.flags & RES_SPLIT) {
-            const uint32_t *col = c.cols[cur] + uint64_t(r.dim) * c.n;
+            const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n;
             // stage keys (coalesced), then each thread ranks PER_THREAD consecutive ones
-            for (uint32_t i = threadIdx.x; i < cnt; i += NT) dest[i] = key_of_bits(col[tb + i]);
+            for (uint32_t i = threadIdx.x; i < cnt; i += NT) dest[i] = key_of_bits(col[v.tb + i]);
             __syncthreads();
             const uint32_t i0 = threadIdx.x * PER_THREAD;
             uint32_t f = 0, nleft = 0;
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
-                uint32_t i = i0 + j;
-                bool l = i < cnt && dest[i] <= r.split;
+                const uint32_t i = i0 + j;
+                const bool l = i < cnt && dest[i] <= r.split;
                 f |= uint32_t(l) << j;
                 nleft += l;
             }
             uint32_t tot;
-            uint32_t lpre = block_excl_scan(nleft, sh, &tot);
+            const uint32_t lpre = block_excl_scan(nleft, sh, &tot);
             const uint32_t lbase = c.tile_off[t];
-            const uint32_t rbase = r.nl + (tb - cl.begin) - lbase;
+            const uint32_t rbase = r.nl + (v.tb - v.cl.begin) - lbase;
             uint32_t lo = lbase + lpre, ro = rbase + (i0 - lpre);
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
-                uint32_t i = i0 + j;
-                if (i < cnt) {
-                    if ((f >> j) & 1u) dest[i] = lo++;
-                    else dest[i] = ro++;
-                }
+                const uint32_t i = i0 + j;
+                if (i < cnt) dest[i] = ((f >> j) & 1u) ? lo++ : ro++;
             }
         } else {
-            for (uint32_t i = threadIdx.x; i < cnt; i += NT) dest[i] = tb - cl.begin + i;
+            for (uint32_t i = threadIdx.x; i < cnt; i += NT) dest[i] = v.tb - v.cl.begin + i;
         }
         __syncthreads();
-        move_columns(c, cur, cl, r, tb, cnt, dest);
+        move_columns(c, cur, v.cl, r, v.ci - c.ts[v.cl.tree].first[cur], v.tb, cnt, dest, sh64,
+                     true);
         __syncthreads();
     }
 }
 
-// Small cells: the whole cell in one workgroup (select, rank, scatter).
+// Small cells: the whole level step of one cell in one workgroup.
 __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t ncells) {
     __shared__ uint32_t keys[SMALL_MAX];
-    __shared__ uint32_t h[NBINS];
-    __shared__ uint32_t sh[NW + 1];
-    __shared__ uint32_t s_bin, s_below, s_cnt;
+    __shared__ uint32_t h[NW][NBINS];
+    __shared__ uint32_t sh[2 * NW + 1], s3[4];
+    __shared__ unsigned long long sh64[NW * 2 * FCHUNK];
+    __shared__ long long mom[2 * FOURIER_JMAX];
+    extern __shared__ uint32_t dyn[];  // SUBSET: bounds[S + 1], medians[S]
     const uint32_t cur = level & 1;
+    const int J = int(c.J);
     for (uint32_t ci = blockIdx.x; ci < ncells; ci += gridDim.x) {
         const Cell cl = c.cells[cur][ci];
+        if (cl.big != NONE) continue;
+        const TreeDesc &T = c.trees[cl.tree];
         const uint32_t n_c = cl.end - cl.begin;
-        if (n_c > uint32_t(SMALL_MAX)) continue;
+        const uint32_t li = ci - c.ts[cl.tree].first[cur];
         CellRes r = c.res[ci];
-        const uint32_t *col = c.cols[cur] + uint64_t(r.dim) * c.n;
-        for (uint32_t i = threadIdx.x; i < n_c; i += NT) keys[i] = key_of_bits(col[cl.begin + i]);
-        // radix select of rank floor((n_c - 1) / 2) in LDS
-        uint32_t prefix = 0, rank = r.rank, lt = 0, cnt_eq = 0;
-        for (int pass = 0; pass < RPASSES; pass++) {
-            const int shift = 32 - RBITS * (pass + 1);
-            const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
-            for (int b = threadIdx.x; b < NBINS; b += NT) h[b] = 0;
-            __syncthreads();
+        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n + cl.begin;
+        for (uint32_t i = threadIdx.x; i < n_c; i += NT) keys[i] = key_of_bits(col[i]);
+        __syncthreads();
+        uint32_t m = 0, lt = 0, le = 0;
+        bool counted = false;
+        if (c.split_rule == KD_SPLIT_EXACT) {
+            const SelectResult sel =
+                block_select([&](uint32_t i) { return keys[i]; }, n_c, r.rank, h[0], sh, s3);
+            m = sel.key;
+            lt = sel.lt;
+            le = sel.le;
+            counted = true;
+        } else if (c.split_rule == KD_SPLIT_FOURIER) {
+            uint32_t mn = NONE, mx = 0;
             for (uint32_t i = threadIdx.x; i < n_c; i += NT) {
-                uint32_t u = keys[i];
-                if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & (NBINS - 1)], 1u);
+                mn = min(mn, keys[i]);
+                mx = max(mx, keys[i]);
+            }
+            block_minmax(mn, mx, sh);
+            m = mn;
+            if (mn != mx) {
+                const int e = fourier_exponent(mn, mx);
+                const double xmin = value_of_key(mn), scale = fourier_scale(e);
+                for (int j0 = 0; j0 < J; j0 += FCHUNK) {
+                    long long acc[2 * FCHUNK];
+#pragma unroll
+                    for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
+                    for (uint32_t i = threadIdx.x; i < n_c; i += NT)
+                        fourier_terms(keys[i], xmin, scale, J, j0, c.trig, acc);
+                    reduce_moments(acc, sh64, j0, J, mom, false);
+                }
+                if (wave() == 0) {
+                    const uint32_t mm = fourier_solve_wave(mom, mom + FOURIER_JMAX, J, mn, mx, e,
+                                                           c.trig);
+                    if (lane() == 0) s3[0] = mm;
+                }
+                __syncthreads();
+                m = s3[0];
+                __syncthreads();
+            }
+        } else {
+            uint32_t *B = dyn, *med = dyn + c.S + 1;
+            if (threadIdx.x == 0) subset_bounds(c, n_c, level, li, B);
+            __syncthreads();
+            for (uint32_t s = wave(); s < c.S; s += NW) {
+                const uint32_t ns = B[s + 1] - B[s];
+                uint32_t v = NONE;
+                if (ns > 0) v = wave_select(keys + B[s], ns, (ns - 1) / 2, h[wave()]);
+                if (lane() == 0) med[s] = v;
             }
             __syncthreads();
-            uint32_t hv = h[threadIdx.x], tot;
-            uint32_t ex = block_excl_scan(hv, sh, &tot);
-            if (ex <= rank && rank < ex + hv) {
-                s_bin = threadIdx.x;
-                s_below = ex;
-                s_cnt = hv;
-            }
+            if (threadIdx.x == 0) s3[0] = subset_mean(B, med, c.S, n_c);
             __syncthreads();
-            prefix |= s_bin << shift;
-            rank -= s_below;
-            lt += s_below;
-            cnt_eq = s_cnt;
+            m = s3[0];
             __syncthreads();
         }
-        r.lt = lt;
-        r.le = lt + cnt_eq;
-        finish_cell(c, level, n_c, r, prefix);
+        if (!counted) {
+            unsigned long long cnt2[2] = {0, 0};
+            for (uint32_t i = threadIdx.x; i < n_c; i += NT) {
+                cnt2[0] += keys[i] < m;
+                cnt2[1] += keys[i] <= m;
+            }
+            block_sum64n<2>(cnt2, sh64);
+            lt = uint32_t(cnt2[0]);
+            le = uint32_t(cnt2[1]);
+        }
+        finish_cell(c, level, n_c, r, m, lt, le);
         // ranks: thread t owns E consecutive positions
         const uint32_t E = (n_c + NT - 1) / NT;
         const uint32_t i0 = min(threadIdx.x * E, n_c), i1 = min(i0 + E, n_c);
@@ -450,30 +819,33 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
             uint32_t nleft = 0;
             for (uint32_t i = i0; i < i1; i++) nleft += keys[i] <= r.split;
             uint32_t tot;
-            uint32_t lpre = block_excl_scan(nleft, sh, &tot);
+            const uint32_t lpre = block_excl_scan(nleft, sh, &tot);
             uint32_t lo = lpre, ro = r.nl + (i0 - lpre);
             for (uint32_t i = i0; i < i1; i++) keys[i] = keys[i] <= r.split ? lo++ : ro++;
         } else {
-            __syncthreads();
             for (uint32_t i = i0; i < i1; i++) keys[i] = i;
         }
         __syncthreads();
-        move_columns(c, cur, cl, r, cl.begin, n_c, keys);
+        move_columns(c, cur, cl, r, li, cl.begin, n_c, keys, sh64, false);
         if (threadIdx.x == 0) c.res[ci] = r;
         __syncthreads();
     }
 }
 
-// a8 emit, phase 1: per-workgroup totals of (splits, active children, tiles,
-// active points, large-cell points).
+// ------------------------------------------------------------ kernels: emit
+
 __device__ __forceinline__ void emit_counts(const Ctx &c, uint32_t level, uint32_t ci,
                                             uint32_t ncells, uint32_t cnt[EMIT_COUNTERS]) {
     for (int k = 0; k < EMIT_COUNTERS; k++) cnt[k] = 0;
     if (ci >= ncells) return;
     const Cell cl = c.cells[level & 1][ci];
     const CellRes r = c.res[ci];
-    if (!(r.flags & RES_SPLIT)) return;
+    if (!(r.flags & RES_SPLIT)) {
+        cnt[7] = 1;
+        return;
+    }
     cnt[0] = 1;
+    cnt[6] = cl.end - cl.begin;
     const uint32_t sz[2] = {r.nl, cl.end - cl.begin - r.nl};
     const uint32_t leaf[2] = {r.flags & RES_LEFT_LEAF, r.flags & RES_RIGHT_LEAF};
     for (int s = 0; s < 2; s++) {
@@ -483,6 +855,7 @@ __device__ __forceinline__ void emit_counts(const Ctx &c, uint32_t level, uint32
         if (sz[s] > uint32_t(SMALL_MAX)) {
             cnt[2] += (sz[s] + TILE - 1) / TILE;
             cnt[4] += sz[s];
+            cnt[5]++;
         }
     }
 }
@@ -498,141 +871,185 @@ __global__ __launch_bounds__(NT) void k_emit_sum(Ctx c, uint32_t level, uint32_t
     }
 }
 
-__global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t level, uint32_t nblocks) {
+__global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t ncells, uint32_t nblocks) {
     __shared__ uint32_t sh[NW + 1];
-    uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0};
+    uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t b0 = 0; b0 < nblocks; b0 += NT) {
-        uint32_t b = b0 + threadIdx.x;
+        const uint32_t b = b0 + threadIdx.x;
         for (int k = 0; k < EMIT_COUNTERS; k++) {
-            uint32_t v = b < nblocks ? c.scan_tmp[b * EMIT_STRIDE + k] : 0u;
+            const uint32_t v = b < nblocks ? c.scan_tmp[b * EMIT_STRIDE + k] : 0u;
             uint32_t tot;
-            uint32_t ex = block_excl_scan(v, sh, &tot);
+            const uint32_t ex = block_excl_scan(v, sh, &tot);
             if (b < nblocks) c.scan_tmp[b * EMIT_STRIDE + k] = base[k] + ex;
             base[k] += tot;
         }
     }
+    if (threadIdx.x < EMIT_COUNTERS)
+        c.pre[uint64_t(ncells) * EMIT_STRIDE + threadIdx.x] = base[threadIdx.x];
     if (threadIdx.x == 0) {
-        LevelInfo *in = c.info;
-        in->nodes_base = in->num_nodes;
-        in->splits = base[0];
-        uint64_t after = uint64_t(in->num_nodes) + 2ull * base[0];
-        if (after > c.cap) {
-            in->status = KD_ECAPACITY;
-            in->num_cells = 0;
-            in->num_tiles = 0;
-            in->points = 0;
-            in->big_points = 0;
+        LevelInfo in{};
+        in.num_cells = base[1];
+        in.num_tiles = base[2];
+        in.points = base[3];
+        in.big_points = base[4];
+        in.num_big = base[5];
+        *c.info = in;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_emit_prefix(Ctx c, uint32_t level, uint32_t ncells) {
+    __shared__ uint32_t sh[NW + 1];
+    const uint32_t ci = blockIdx.x * NT + threadIdx.x;
+    uint32_t cnt[EMIT_COUNTERS];
+    emit_counts(c, level, ci, ncells, cnt);
+    for (int k = 0; k < EMIT_COUNTERS; k++) {
+        uint32_t tot;
+        const uint32_t p =
+            block_excl_scan(cnt[k], sh, &tot) + c.scan_tmp[blockIdx.x * EMIT_STRIDE + k];
+        if (ci < ncells) c.pre[uint64_t(ci) * EMIT_STRIDE + k] = p;
+    }
+}
+
+// Per tree: node-id base of the new children, next level's cell range and
+// the tree's counters.
+__global__ void k_emit_trees(Ctx c, uint32_t level) {
+    const uint32_t cur = level & 1, nxt = cur ^ 1;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < c.ntrees;
+         t += gridDim.x * blockDim.x) {
+        TreeState &S = c.ts[t];
+        const uint32_t f = S.first[cur], n = S.count[cur];
+        S.nodes_base = S.num_nodes;
+        if (n > 0) {
+            const uint32_t *pf = c.pre + uint64_t(f) * EMIT_STRIDE;
+            const uint32_t *pe = c.pre + uint64_t(f + n) * EMIT_STRIDE;
+            const uint32_t splits = pe[0] - pf[0];
+            S.split_base = pf[0];
+            if (uint64_t(S.num_nodes) + 2ull * splits > c.trees[t].cap) S.status = KD_ECAPACITY;
+            S.num_nodes += 2 * splits;
+            S.first[nxt] = pf[1];
+            S.count[nxt] = pe[1] - pf[1];
+            S.point_levels += pe[6] - pf[6];
+            S.unsplittable += pe[7] - pf[7];
+            if (splits > 0) S.depth = level + 1;
         } else {
-            in->num_nodes = uint32_t(after);
-            in->num_cells = base[1];
-            in->num_tiles = base[2];
-            in->points = base[3];
-            in->big_points = base[4];
+            S.count[nxt] = 0;
         }
+        S.depth_first[level + 2] = S.num_nodes;
     }
 }
 
 __global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level, uint32_t ncells) {
-    __shared__ uint32_t sh[NW + 1];
-    __shared__ unsigned long long sh64[NW];
+    const uint32_t cur = level & 1, nxt = cur ^ 1;
     const uint32_t ci = blockIdx.x * NT + threadIdx.x;
-    uint32_t cnt[EMIT_COUNTERS], pre[3];
-    emit_counts(c, level, ci, ncells, cnt);
-    for (int k = 0; k < 3; k++) {
-        uint32_t tot;
-        pre[k] = block_excl_scan(cnt[k], sh, &tot) + c.scan_tmp[blockIdx.x * EMIT_STRIDE + k];
+    if (ci >= ncells) return;
+    const CellRes r = c.res[ci];
+    if (!(r.flags & RES_SPLIT)) return;
+    const Cell cl = c.cells[cur][ci];
+    const TreeDesc &T = c.trees[cl.tree];
+    const TreeState &S = c.ts[cl.tree];
+    const uint32_t *pre = c.pre + uint64_t(ci) * EMIT_STRIDE;
+    const uint32_t left = S.nodes_base + 2 * (pre[0] - S.split_base);
+    const uint32_t li = ci - S.first[cur];
+    const uint32_t mid = cl.begin + r.nl;
+    if (cl.node < T.cap) {
+        T.node_child[cl.node] = int32_t(left);
+        T.node_dim[cl.node] = r.dim;
+        T.node_split[cl.node] = r.split;
+        T.node_split_f[cl.node] = __uint_as_float(bits_of_key(r.split));
     }
-    const LevelInfo in = *c.info;
-    unsigned long long pl = 0;
-    uint32_t unsplit = 0;
-    if (ci < ncells && in.status != KD_ECAPACITY) {
-        const Cell cl = c.cells[level & 1][ci];
-        const CellRes r = c.res[ci];
-        if (r.flags & RES_SPLIT) {
-            const uint32_t left = in.nodes_base + 2 * pre[0];
-            pl = cl.end - cl.begin;
-            c.node_child[cl.node] = int32_t(left);
-            c.node_dim[cl.node] = r.dim;
-            c.node_split[cl.node] = r.split;
-            c.node_split_f[cl.node] = __uint_as_float(bits_of_key(r.split));
-            const uint32_t mid = cl.begin + r.nl;
-            c.node_begin[left] = cl.begin;
-            c.node_end[left] = mid;
-            c.node_begin[left + 1] = mid;
-            c.node_end[left + 1] = cl.end;
-            uint32_t slot = pre[1], tile = pre[2];
-            Cell *nx = c.cells[(level + 1) & 1];
-            const uint32_t b[2] = {cl.begin, mid}, e[2] = {mid, cl.end};
-            const uint32_t leaf[2] = {r.flags & RES_LEFT_LEAF, r.flags & RES_RIGHT_LEAF};
-            for (int s = 0; s < 2; s++) {
-                if (leaf[s]) continue;
-                nx[slot++] = Cell{b[s], e[s], left + s, tile};
-                uint32_t sz = e[s] - b[s];
-                if (sz > uint32_t(SMALL_MAX)) tile += (sz + TILE - 1) / TILE;
-            }
-        } else {
-            unsplit = 1;
+    if (uint64_t(left) + 1 < T.cap) {
+        T.node_begin[left] = cl.begin;
+        T.node_end[left] = mid;
+        T.node_begin[left + 1] = mid;
+        T.node_end[left + 1] = cl.end;
+    }
+    uint32_t slot = pre[1], tile = pre[2], big = pre[5];
+    const uint32_t b[2] = {cl.begin, mid}, e[2] = {mid, cl.end};
+    const uint32_t leaf[2] = {r.flags & RES_LEFT_LEAF, r.flags & RES_RIGHT_LEAF};
+    for (int s = 0; s < 2; s++) {
+        if (leaf[s]) continue;
+        const uint32_t sz = e[s] - b[s];
+        const bool isbig = sz > uint32_t(SMALL_MAX);
+        c.cells[nxt][slot] = Cell{b[s], e[s], left + s, tile, isbig ? big : NONE, 2 * li + s,
+                                  cl.tree, 0u};
+        if (isbig) {
+            c.big_list[big] = slot;
+            big++;
+            tile += (sz + TILE - 1) / TILE;
         }
-    }
-    unsigned long long s_pl = block_sum64(pl, sh64);
-    unsigned long long s_un = block_sum64(unsplit, sh64);
-    if (threadIdx.x == 0) {
-        if (s_pl) atomicAdd(&c.info->point_levels, s_pl);
-        if (s_un) atomicAdd(&c.info->unsplittable, uint32_t(s_un));
+        slot++;
     }
 }
+
+// ------------------------------------------------------------ kernels: leaves
 
 // Leaves in position order: subtree leaf counts bottom-up, first leaf index
-// top-down, both one tree level per launch over its node-id range.
-__global__ void k_leaf_count(Ctx c, uint32_t a, uint32_t b) {
+// top-down, one depth per launch over each tree's node-id range.
+__global__ void k_leaf_count(Ctx c, uint32_t depth) {
+    const uint32_t t = blockIdx.y;
+    const TreeState &S = c.ts[t];
+    if (S.status != KD_OK || depth > S.depth) return;
+    const TreeDesc &T = c.trees[t];
+    const uint32_t a = S.depth_first[depth], b = S.depth_first[depth + 1];
     for (uint32_t k = a + blockIdx.x * NT + threadIdx.x; k < b; k += gridDim.x * NT) {
-        int32_t ch = c.node_child[k];
-        c.leaf_cnt[k] = ch < 0 ? 1u : c.leaf_cnt[ch] + c.leaf_cnt[ch + 1];
+        const int32_t ch = T.node_child[k];
+        T.leaf_cnt[k] = ch < 0 ? 1u : T.leaf_cnt[ch] + T.leaf_cnt[ch + 1];
     }
 }
 
-__global__ void k_leaf_first(Ctx c, uint32_t a, uint32_t b) {
+__global__ void k_leaf_first(Ctx c, uint32_t depth) {
+    const uint32_t t = blockIdx.y;
+    const TreeState &S = c.ts[t];
+    if (S.status != KD_OK || depth > S.depth) return;
+    const TreeDesc &T = c.trees[t];
+    const uint32_t a = S.depth_first[depth], b = S.depth_first[depth + 1];
     for (uint32_t k = a + blockIdx.x * NT + threadIdx.x; k < b; k += gridDim.x * NT) {
-        if (k == 0) c.leaf_first[0] = 0;
-        int32_t ch = c.node_child[k];
+        const int32_t ch = T.node_child[k];
         if (ch >= 0) {
-            uint32_t f = k == 0 ? 0u : c.leaf_first[k];
-            c.leaf_first[ch] = f;
-            c.leaf_first[ch + 1] = f + c.leaf_cnt[ch];
+            const uint32_t f = k == 0 ? 0u : T.leaf_first[k];
+            T.leaf_first[ch] = f;
+            T.leaf_first[ch + 1] = f + T.leaf_cnt[ch];
         }
     }
 }
 
-__global__ __launch_bounds__(NT) void k_leaf_write(Ctx c, uint32_t num_nodes) {
+__global__ __launch_bounds__(NT) void k_leaf_write(Ctx c) {
     __shared__ unsigned long long sh64[NW];
-    uint32_t over = 0;
-    for (uint32_t k = blockIdx.x * NT + threadIdx.x; k < num_nodes; k += gridDim.x * NT) {
-        if (c.node_child[k] < 0) {
-            uint32_t f = k == 0 ? 0u : c.leaf_first[k];
-            c.leaf_node[f] = k;
-            c.leaf_offsets[f] = c.node_begin[k];
-            c.node_leaf[k] = f;
-            over += (c.node_end[k] - c.node_begin[k]) > c.leaf_size;
+    const uint32_t t = blockIdx.y;
+    const TreeState &S = c.ts[t];
+    if (S.status != KD_OK) return;
+    const TreeDesc &T = c.trees[t];
+    unsigned long long over = 0;
+    for (uint32_t k = blockIdx.x * NT + threadIdx.x; k < S.num_nodes; k += gridDim.x * NT) {
+        if (T.node_child[k] < 0) {
+            const uint32_t f = k == 0 ? 0u : T.leaf_first[k];
+            T.leaf_node[f] = k;
+            T.leaf_offsets[f] = T.node_begin[k];
+            T.node_leaf[k] = f;
+            over += (T.node_end[k] - T.node_begin[k]) > c.leaf_size;
         }
     }
-    unsigned long long s = block_sum64(over, sh64);
-    if (threadIdx.x == 0 && s) atomicAdd(&c.info->oversize, uint32_t(s));
+    block_sum64n<1>(&over, sh64);
+    if (threadIdx.x == 0 && over) atomicAdd(&c.ts[t].oversize, uint32_t(over));
 }
 
-__global__ void k_header(Ctx c, uint32_t depth) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const LevelInfo in = *c.info;
-    const uint32_t leaves = in.status == KD_OK ? c.leaf_cnt[0] : 0u;
-    if (in.status == KD_OK) c.leaf_offsets[leaves] = c.n;
-    kd_header h{};
-    h.num_nodes = in.num_nodes;
-    h.num_leaves = leaves;
-    h.depth = depth;
-    h.status = in.status;
-    h.point_levels = in.point_levels;
-    h.unsplittable = in.unsplittable;
-    h.oversize = in.oversize;
-    *c.hdr = h;
+__global__ void k_header(Ctx c) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < c.ntrees;
+         t += gridDim.x * blockDim.x) {
+        const TreeState &S = c.ts[t];
+        const TreeDesc &T = c.trees[t];
+        const uint32_t leaves = S.status == KD_OK ? T.leaf_cnt[0] : 0u;
+        if (S.status == KD_OK) T.leaf_offsets[leaves] = T.n;
+        kd_header h{};
+        h.num_nodes = S.num_nodes;
+        h.num_leaves = leaves;
+        h.depth = S.depth;
+        h.status = S.status;
+        h.point_levels = S.point_levels;
+        h.unsplittable = S.unsplittable;
+        h.oversize = S.oversize;
+        *T.hdr = h;
+    }
 }
 
 // a9: leaf of each query by descent.
@@ -641,37 +1058,131 @@ __global__ void k_query(const int32_t *child, const uint32_t *dim, const uint32_
                         uint32_t *out) {
     for (uint64_t i = blockIdx.x * uint64_t(NT) + threadIdx.x; i < nq;
          i += uint64_t(gridDim.x) * NT) {
-        uint32_t node = 0, res = 0;
+        uint32_t node = 0;
         bool nan = false;
-        // a valid tree is at most 128 levels deep; the bound also ends the
+        // a valid tree is at most MAX_LEVELS deep; the bound also ends the
         // walk on a corrupt node array
-        for (int step = 0; step < 256; step++) {
-            int32_t ch = child[node];
+        for (int step = 0; step <= MAX_LEVELS; step++) {
+            const int32_t ch = child[node];
             if (ch < 0) break;
-            uint32_t b = __float_as_uint(q[uint64_t(dim[node]) * ldq + i]);
+            const uint32_t b = __float_as_uint(q[uint64_t(dim[node]) * ldq + i]);
             if ((b & 0x7fffffffu) > 0x7f800000u) {
                 nan = true;
                 break;
             }
             node = uint32_t(ch) + (key_of_bits(b) > split[node] ? 1u : 0u);
         }
-        res = nan ? NONE : node_leaf[node];
-        out[i] = res;
+        out[i] = nan ? NONE : node_leaf[node];
     }
 }
 
-// ------------------------------------------------------------ host helpers
+// ------------------------------------------------------------ host side
 
-bool params_ok(uint64_t n, uint32_t d, const kd_params *p) {
-    if (!p || n == 0 || n > 0xffffffffull - TILE || d == 0 || d > 4096) return false;
-    if (p->leaf_size == 0 || p->num_subsets == 0 || p->num_subsets > 65536) return false;
+bool params_ok(const kd_params *p) {
+    if (!p || p->leaf_size == 0 || p->num_subsets == 0 || p->num_subsets > MAX_SUBSETS)
+        return false;
     if (p->key_rule > KD_KEY_MAXVAR || p->split_rule > KD_SPLIT_SUBSET) return false;
-    if (p->split_rule == KD_SPLIT_FOURIER && (p->fourier_J == 0 || p->fourier_J > 64)) return false;
+    if (p->split_rule == KD_SPLIT_FOURIER && (p->fourier_J == 0 || p->fourier_J > FOURIER_JMAX))
+        return false;
     if (p->subset_pool && p->pool_entries == 0) return false;
+    if (p->max_depth > MAX_LEVELS) return false;
     return true;
 }
 
+bool shape_ok(uint64_t n, uint32_t d) { return n > 0 && n <= 0xffffff00ull && d > 0 && d <= 4096; }
+
 uint64_t default_capacity(uint64_t n, uint32_t leaf) { return 4 * ((n + leaf - 1) / leaf) + 64; }
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+struct Bump {
+    uint64_t o = 0;
+    uint64_t take(uint64_t bytes) {
+        const uint64_t r = o;
+        o = align256(o + bytes);
+        return r;
+    }
+};
+
+struct TreeLayout {
+    uint64_t cols[2], perm[2], stats[2], leaf_cnt, leaf_first;
+    uint64_t max_cells;
+};
+
+struct Layout {
+    uint64_t trees, ts, cells[2], res, big_list, tile_lt, tile_le, tile_off, hist, mm, mom,
+        bounds, med, pre, scan, info, total;
+    uint64_t max_cells, max_tiles, max_big, scan_blocks;
+    std::vector<TreeLayout> per_tree;
+};
+
+Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *cap,
+            const kd_params *p) {
+    Layout L{};
+    for (uint32_t t = 0; t < T; t++) {
+        L.max_cells += n[t] / (uint64_t(p->leaf_size) + 1) + 1;
+        L.max_tiles += n[t] / TILE + n[t] / (SMALL_MAX + 1) + 2;
+        L.max_big += n[t] / (SMALL_MAX + 1) + 1;
+    }
+    L.scan_blocks = (L.max_cells + NT - 1) / NT;
+    Bump B;
+    L.trees = B.take(sizeof(TreeDesc) * T);
+    L.ts = B.take(sizeof(TreeState) * T);
+    for (int b = 0; b < 2; b++) L.cells[b] = B.take(L.max_cells * sizeof(Cell));
+    L.res = B.take(L.max_cells * sizeof(CellRes));
+    L.big_list = B.take(L.max_big * 4);
+    L.tile_lt = B.take(L.max_tiles * 4);
+    L.tile_le = B.take(L.max_tiles * 4);
+    L.tile_off = B.take(L.max_tiles * 4);
+    L.hist = B.take(L.max_big * NBINS * 4);
+    const bool fourier = p->split_rule == KD_SPLIT_FOURIER;
+    const bool subset = p->split_rule == KD_SPLIT_SUBSET;
+    L.mm = B.take(fourier ? L.max_big * 8 : 0);
+    L.mom = B.take(fourier ? L.max_big * 2 * FOURIER_JMAX * 8 : 0);
+    L.bounds = B.take(subset ? L.max_big * (p->num_subsets + 1) * 4 : 0);
+    L.med = B.take(subset ? L.max_big * p->num_subsets * 4 : 0);
+    L.pre = B.take((L.max_cells + 1) * EMIT_STRIDE * 4);
+    L.scan = B.take((L.scan_blocks + 1) * EMIT_STRIDE * 4);
+    L.info = B.take(sizeof(LevelInfo));
+    L.per_tree.resize(T);
+    for (uint32_t t = 0; t < T; t++) {
+        TreeLayout &tl = L.per_tree[t];
+        tl.max_cells = n[t] / (uint64_t(p->leaf_size) + 1) + 1;
+        for (int b = 0; b < 2; b++) tl.cols[b] = B.take(uint64_t(d[t]) * n[t] * 4);
+        for (int b = 0; b < 2; b++) tl.perm[b] = B.take(n[t] * 4);
+        for (int b = 0; b < 2; b++)
+            tl.stats[b] = B.take(p->key_rule == KD_KEY_MAXVAR
+                                     ? 2 * tl.max_cells * uint64_t(d[t]) * 3 * 8
+                                     : 0);
+        tl.leaf_cnt = B.take(cap[t] * 4);
+        tl.leaf_first = B.take(cap[t] * 4);
+    }
+    L.total = B.o;
+    return L;
+}
+
+TrigTables make_trig() {
+    TrigTables T{};
+    double f[26];
+    f[0] = 1.0;
+    for (int k = 1; k < 26; k++) {
+        double v = 1.0;
+        for (int i = 2; i <= k; i++) v *= double(i);
+        f[k] = v;
+    }
+    for (int m = 0; m < 9; m++) {
+        const float sg = (m % 2) ? -1.0f : 1.0f;
+        T.s32[m] = sg * float(1.0 / f[2 * m + 1]);
+        T.c32[m] = sg * float(1.0 / f[2 * m]);
+    }
+    for (int m = 0; m < 13; m++) {
+        const double sg = (m % 2) ? -1.0 : 1.0;
+        T.s64[m] = sg * (1.0 / f[2 * m + 1]);
+        T.c64[m] = sg * (1.0 / f[2 * m]);
+    }
+    for (int j = 0; j < FOURIER_JMAX; j++) T.w[j] = 1.0 / double(2 * j + 1);
+    return T;
+}
 
 uint32_t grid_for(uint64_t work, uint32_t cap = 65535u) {
     if (work == 0) return 1;
@@ -725,10 +1236,224 @@ struct Prof {
     }
 };
 
-#define KD_LAUNCH_CHECK()                                   \
-    do {                                                    \
+#define KD_LAUNCH_CHECK()                                       \
+    do {                                                        \
         if (hipGetLastError() != hipSuccess) return KD_EDEVICE; \
     } while (0)
+
+struct HostTree {
+    const float *pts;
+    uint64_t n, ld;
+    uint32_t d;
+    const kd_tree *out;
+};
+
+// The level loop over every tree of the build.
+kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, void *workspace,
+                    uint64_t ws_bytes, hipStream_t st, kd_profile *prof) {
+    std::vector<uint64_t> n(ntrees), cap(ntrees);
+    std::vector<uint32_t> d(ntrees);
+    uint64_t total_points = 0, sum_d = 0;
+    for (uint32_t t = 0; t < ntrees; t++) {
+        n[t] = ht[t].n;
+        d[t] = ht[t].d;
+        cap[t] = ht[t].out->node_capacity;
+        total_points += n[t];
+        sum_d += uint64_t(d[t]) * n[t];
+    }
+    if (total_points > 0xffffff00ull) return KD_EINVAL;
+    const Layout L = plan(ntrees, n.data(), d.data(), cap.data(), p);
+    if (ws_bytes < L.total) return KD_ENOMEM;
+    char *ws = static_cast<char *>(workspace);
+    Prof P(prof, st);
+
+    std::vector<TreeDesc> desc(ntrees);
+    for (uint32_t t = 0; t < ntrees; t++) {
+        const TreeLayout &tl = L.per_tree[t];
+        const kd_tree *o = ht[t].out;
+        TreeDesc &D = desc[t];
+        D.pts = reinterpret_cast<const uint32_t *>(ht[t].pts);
+        D.ld = ht[t].ld;
+        for (int b = 0; b < 2; b++) {
+            D.cols[b] = reinterpret_cast<uint32_t *>(ws + tl.cols[b]);
+            D.perm[b] = reinterpret_cast<uint32_t *>(ws + tl.perm[b]);
+            D.stats[b] = reinterpret_cast<unsigned long long *>(ws + tl.stats[b]);
+        }
+        D.out_perm = o->perm;
+        D.pts_out = reinterpret_cast<uint32_t *>(o->points_out);
+        D.node_begin = o->node_begin;
+        D.node_end = o->node_end;
+        D.node_child = o->node_child;
+        D.node_dim = o->node_dim;
+        D.node_split = o->node_split;
+        D.node_split_f = o->node_split_f;
+        D.node_leaf = o->node_leaf;
+        D.leaf_node = o->leaf_node;
+        D.leaf_offsets = o->leaf_offsets;
+        D.hdr = o->hdr;
+        D.leaf_cnt = reinterpret_cast<uint32_t *>(ws + tl.leaf_cnt);
+        D.leaf_first = reinterpret_cast<uint32_t *>(ws + tl.leaf_first);
+        D.cap = cap[t];
+        D.n = uint32_t(n[t]);
+        D.d = d[t];
+    }
+    if (hipMemcpyAsync(ws + L.trees, desc.data(), sizeof(TreeDesc) * ntrees,
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        return KD_EDEVICE;
+
+    Ctx c{};
+    c.trees = reinterpret_cast<TreeDesc *>(ws + L.trees);
+    c.ts = reinterpret_cast<TreeState *>(ws + L.ts);
+    c.ntrees = ntrees;
+    for (int b = 0; b < 2; b++) c.cells[b] = reinterpret_cast<Cell *>(ws + L.cells[b]);
+    c.res = reinterpret_cast<CellRes *>(ws + L.res);
+    c.big_list = reinterpret_cast<uint32_t *>(ws + L.big_list);
+    c.tile_lt = reinterpret_cast<uint32_t *>(ws + L.tile_lt);
+    c.tile_le = reinterpret_cast<uint32_t *>(ws + L.tile_le);
+    c.tile_off = reinterpret_cast<uint32_t *>(ws + L.tile_off);
+    c.hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    c.mm = reinterpret_cast<uint32_t *>(ws + L.mm);
+    c.mom = reinterpret_cast<long long *>(ws + L.mom);
+    c.bounds = reinterpret_cast<uint32_t *>(ws + L.bounds);
+    c.med = reinterpret_cast<uint32_t *>(ws + L.med);
+    c.pre = reinterpret_cast<uint32_t *>(ws + L.pre);
+    c.scan_tmp = reinterpret_cast<uint32_t *>(ws + L.scan);
+    c.info = reinterpret_cast<LevelInfo *>(ws + L.info);
+    c.pool = p->subset_pool;
+    c.pool_entries = p->pool_entries;
+    c.seed = p->seed;
+    c.leaf_size = p->leaf_size;
+    c.max_depth = p->max_depth ? p->max_depth : 64;
+    c.key_rule = p->key_rule;
+    c.split_rule = p->split_rule;
+    c.J = p->fourier_J;
+    c.S = p->num_subsets;
+    c.trig = make_trig();
+
+    uint64_t maxcap = 0, maxn = 0;
+    for (uint32_t t = 0; t < ntrees; t++) {
+        maxcap = cap[t] > maxcap ? cap[t] : maxcap;
+        maxn = n[t] > maxn ? n[t] : maxn;
+    }
+    const dim3 per_tree_nodes(grid_for(maxcap / NT + 1, 1024), ntrees);
+    const dim3 per_tree_points(grid_for(maxn / NT + 1, 1024), ntrees);
+    P.run(KD_PROF_OTHER, 0, 0, [&] {
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.max_big, 4096)), dim3(NT), 0, st, c.hist,
+                           L.max_big * NBINS, 0u);
+        hipLaunchKernelGGL(k_init, per_tree_nodes, dim3(NT), 0, st, c);
+    });
+    P.run(KD_PROF_INGEST, total_points, 8 * sum_d + 4 * total_points, [&] {
+        hipLaunchKernelGGL(k_ingest, dim3(grid_for(maxn / (NT * 4) + 1, 1024), ntrees), dim3(NT),
+                           0, st, c);
+    });
+    P.run(KD_PROF_OTHER, 0, 0, [&] {
+        hipLaunchKernelGGL(k_roots, dim3(1), dim3(NT), 0, st, c);
+        if (p->key_rule == KD_KEY_MAXVAR)
+            hipLaunchKernelGGL(k_root_stats, per_tree_points, dim3(NT), 0, st, c);
+        hipLaunchKernelGGL(k_copy_leafroots, per_tree_points, dim3(NT), 0, st, c);
+    });
+    KD_LAUNCH_CHECK();
+
+    const uint64_t scatter_avg_bpp = (8 * sum_d + 8 * total_points) / total_points;
+    const size_t small_dyn = p->split_rule == KD_SPLIT_SUBSET ? (2 * size_t(c.S) + 1) * 4 : 0;
+    LevelInfo hi{};
+    uint32_t levels_run = 0;
+    for (uint32_t level = 0;; level++) {
+        if (hipMemcpyAsync(&hi, c.info, sizeof(hi), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return KD_EDEVICE;
+        if (hi.num_cells == 0 || level >= MAX_LEVELS) break;
+        levels_run++;
+        const uint32_t nc = hi.num_cells, ntl = hi.num_tiles, nbig = hi.num_big;
+        const uint64_t bigp = hi.big_points, smallp = hi.points - hi.big_points;
+        P.run(KD_PROF_OTHER, 0, 0, [&] {
+            hipLaunchKernelGGL(k_level_init, dim3(grid_for(nc / NT + 1, 4096)), dim3(NT), 0, st,
+                               c, level, nc);
+        });
+        if (ntl > 0) {
+            if (p->split_rule == KD_SPLIT_EXACT) {
+                for (uint32_t pass = 0; pass < uint32_t(RPASSES); pass++) {
+                    P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
+                        hipLaunchKernelGGL(k_big_hist, dim3(grid_for(ntl, 65535)), dim3(NT), 0,
+                                           st, c, level, pass, nc, ntl);
+                    });
+                    P.run(KD_PROF_PICK, 0, 0, [&] {
+                        hipLaunchKernelGGL(k_big_pick, dim3(grid_for(nbig, 65535)), dim3(NT), 0,
+                                           st, c, level, pass, nbig);
+                    });
+                }
+            } else if (p->split_rule == KD_SPLIT_FOURIER) {
+                P.run(KD_PROF_SELECT, bigp, 8 * bigp, [&] {
+                    hipLaunchKernelGGL(k_big_minmax, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st,
+                                       c, level, nc, ntl);
+                    hipLaunchKernelGGL(k_big_moments, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st,
+                                       c, level, nc, ntl);
+                });
+                P.run(KD_PROF_PICK, 0, 0, [&] {
+                    hipLaunchKernelGGL(k_big_fsolve, dim3((nbig + NW - 1) / NW), dim3(NT), 0, st,
+                                       c, level, nbig);
+                });
+            } else {
+                P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
+                    hipLaunchKernelGGL(k_big_bounds, dim3(grid_for(nbig / NT + 1, 4096)), dim3(NT),
+                                       0, st, c, level, nbig);
+                    hipLaunchKernelGGL(k_subset_select,
+                                       dim3(grid_for(uint64_t(nbig) * c.S, 65535)), dim3(NT), 0,
+                                       st, c, level, nbig);
+                });
+                P.run(KD_PROF_PICK, 0, 0, [&] {
+                    hipLaunchKernelGGL(k_subset_mean, dim3(grid_for(nbig / NT + 1, 4096)),
+                                       dim3(NT), 0, st, c, level, nbig);
+                });
+            }
+            P.run(KD_PROF_COUNT, bigp, 4 * bigp, [&] {
+                hipLaunchKernelGGL(k_big_count, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
+                                   level, nc, ntl);
+                hipLaunchKernelGGL(k_big_decide, dim3(grid_for(nbig, 65535)), dim3(NT), 0, st, c,
+                                   level, nbig);
+            });
+            P.run(KD_PROF_BIG_SCATTER, bigp, scatter_avg_bpp * bigp, [&] {
+                hipLaunchKernelGGL(k_big_scatter, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
+                                   level, nc, ntl);
+            });
+        }
+        if (smallp > 0) {
+            P.run(KD_PROF_SMALL, smallp, scatter_avg_bpp * smallp, [&] {
+                hipLaunchKernelGGL(k_small, dim3(grid_for(nc, 1u << 20)), dim3(NT), small_dyn, st,
+                                   c, level, nc);
+            });
+        }
+        const uint32_t nb = (nc + NT - 1) / NT;
+        P.run(KD_PROF_EMIT, 0, 0, [&] {
+            hipLaunchKernelGGL(k_emit_sum, dim3(nb), dim3(NT), 0, st, c, level, nc);
+            hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(NT), 0, st, c, nc, nb);
+            hipLaunchKernelGGL(k_emit_prefix, dim3(nb), dim3(NT), 0, st, c, level, nc);
+            hipLaunchKernelGGL(k_emit_trees, dim3(grid_for(ntrees / NT + 1, 1024)), dim3(NT), 0,
+                               st, c, level);
+            hipLaunchKernelGGL(k_emit_write, dim3(nb), dim3(NT), 0, st, c, level, nc);
+        });
+        KD_LAUNCH_CHECK();
+    }
+    P.run(KD_PROF_OTHER, 0, 0, [&] {
+        for (int l = int(levels_run); l >= 0; l--)
+            hipLaunchKernelGGL(k_leaf_count, per_tree_nodes, dim3(NT), 0, st, c, uint32_t(l));
+        for (uint32_t l = 0; l <= levels_run; l++)
+            hipLaunchKernelGGL(k_leaf_first, per_tree_nodes, dim3(NT), 0, st, c, l);
+        hipLaunchKernelGGL(k_leaf_write, per_tree_nodes, dim3(NT), 0, st, c);
+        hipLaunchKernelGGL(k_header, dim3(grid_for(ntrees / NT + 1, 1024)), dim3(NT), 0, st, c);
+    });
+    KD_LAUNCH_CHECK();
+    if (!P.finish(levels_run)) return KD_EDEVICE;
+    // the tree descriptors were copied from `desc`: wait before it goes away
+    if (hipStreamSynchronize(st) != hipSuccess) return KD_EDEVICE;
+    return KD_OK;
+}
+
+bool tree_ok(const kd_tree *o) {
+    return o && o->perm && o->node_begin && o->node_end && o->node_child && o->node_dim &&
+           o->node_split && o->node_split_f && o->node_leaf && o->leaf_node && o->leaf_offsets &&
+           o->hdr && o->node_capacity > 0 && o->node_capacity <= 0xfffffff0ull;
+}
 
 }  // namespace
 
@@ -736,7 +1461,7 @@ struct Prof {
 
 extern "C" {
 
-int kd_version(void) { return 1; }
+int kd_version(void) { return 2; }
 
 const char *kd_status_string(kd_status s) {
     switch (s) {
@@ -753,11 +1478,11 @@ const char *kd_status_string(kd_status s) {
 
 kd_status kd_tree_bounds(uint64_t n, uint32_t d, const kd_params *params,
                          uint64_t *node_capacity, uint64_t *workspace_bytes) {
-    if (!params_ok(n, d, params)) return KD_EINVAL;
-    uint64_t cap = params->node_capacity ? params->node_capacity
-                                         : default_capacity(n, params->leaf_size);
+    if (!params_ok(params) || !shape_ok(n, d)) return KD_EINVAL;
+    const uint64_t cap = params->node_capacity ? params->node_capacity
+                                               : default_capacity(n, params->leaf_size);
     if (cap > 0xfffffff0ull) return KD_EINVAL;
-    Layout L = layout_for(n, d, params->leaf_size, cap);
+    const Layout L = plan(1, &n, &d, &cap, params);
     if (node_capacity) *node_capacity = cap;
     if (workspace_bytes) *workspace_bytes = L.total;
     return KD_OK;
@@ -766,156 +1491,10 @@ kd_status kd_tree_bounds(uint64_t n, uint32_t d, const kd_params *params,
 kd_status kd_build_profiled(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
                             const kd_params *p, kd_tree *out, void *workspace, uint64_t ws_bytes,
                             void *stream, kd_profile *prof) {
-    if (!params_ok(n, d, p) || !pts || !out || ld < n || !workspace) return KD_EINVAL;
-    if (!out->perm || !out->node_begin || !out->node_end || !out->node_child || !out->node_dim ||
-        !out->node_split || !out->node_split_f || !out->node_leaf || !out->leaf_node ||
-        !out->leaf_offsets || !out->hdr || out->node_capacity == 0)
+    if (!params_ok(p) || !shape_ok(n, d) || !pts || ld < n || !workspace || !tree_ok(out))
         return KD_EINVAL;
-    if (p->key_rule != KD_KEY_CYCLIC || p->split_rule != KD_SPLIT_EXACT) return KD_EINVAL;
-    const uint64_t cap = out->node_capacity;
-    if (cap > 0xfffffff0ull) return KD_EINVAL;
-    Layout L = layout_for(n, d, p->leaf_size, cap);
-    if (ws_bytes < L.total) return KD_ENOMEM;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    char *ws = static_cast<char *>(workspace);
-    Prof P(prof, st);
-
-    Ctx c{};
-    for (int b = 0; b < 2; b++) {
-        c.cols[b] = reinterpret_cast<uint32_t *>(ws + L.off_cols[b]);
-        c.perm[b] = reinterpret_cast<uint32_t *>(ws + L.off_perm[b]);
-        c.cells[b] = reinterpret_cast<Cell *>(ws + L.off_cells[b]);
-    }
-    c.res = reinterpret_cast<CellRes *>(ws + L.off_res);
-    c.tile_left = reinterpret_cast<uint32_t *>(ws + L.off_tile_left);
-    c.tile_off = reinterpret_cast<uint32_t *>(ws + L.off_tile_off);
-    c.hist = reinterpret_cast<uint32_t *>(ws + L.off_hist);
-    c.scan_tmp = reinterpret_cast<uint32_t *>(ws + L.off_scan);
-    c.info = reinterpret_cast<LevelInfo *>(ws + L.off_info);
-    c.leaf_cnt = reinterpret_cast<uint32_t *>(ws + L.off_leaf_cnt);
-    c.leaf_first = reinterpret_cast<uint32_t *>(ws + L.off_leaf_first);
-    c.out_perm = out->perm;
-    c.pts_out = reinterpret_cast<uint32_t *>(out->points_out);
-    c.node_begin = out->node_begin;
-    c.node_end = out->node_end;
-    c.node_child = out->node_child;
-    c.node_dim = out->node_dim;
-    c.node_split = out->node_split;
-    c.node_split_f = out->node_split_f;
-    c.node_leaf = out->node_leaf;
-    c.leaf_node = out->leaf_node;
-    c.leaf_offsets = out->leaf_offsets;
-    c.hdr = out->hdr;
-    c.cap = cap;
-    c.n = uint32_t(n);
-    c.d = d;
-    c.leaf_size = p->leaf_size;
-    c.max_depth = p->max_depth ? p->max_depth : 64;
-    c.key_rule = p->key_rule;
-    c.split_rule = p->split_rule;
-    c.J = p->fourier_J;
-    c.S = p->num_subsets;
-
-    const uint64_t scatter_bpp = 8ull * d + 8;  // algorithmic bytes per point of a scatter
-    const uint32_t root_active = (n > p->leaf_size && c.max_depth > 0) ? 1u : 0u;
-    P.run(KD_PROF_OTHER, 0, 0, [&] {
-        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.hist_words / NT + 1, 4096)), dim3(NT), 0,
-                           st, c.hist, L.hist_words, 0u);
-        hipLaunchKernelGGL(k_init, dim3(grid_for(cap / NT + 1, 4096)), dim3(NT), 0, st, c,
-                           root_active);
-    });
-    P.run(KD_PROF_INGEST, n, n * (8ull * d + 4), [&] {
-        hipLaunchKernelGGL(k_ingest, dim3(grid_for(n / (NT * 4) + 1, 1024), d), dim3(NT), 0, st,
-                           c, pts, ld);
-    });
-    KD_LAUNCH_CHECK();
-
-    // level loop; node ids of depth l are [level_first[l], level_first[l + 1])
-    uint32_t level_first[130];
-    uint32_t nlevels = 1;  // depths holding nodes
-    level_first[0] = 0;
-    level_first[1] = 1;
-    LevelInfo hi{};
-    if (!root_active) {
-        P.run(KD_PROF_OTHER, n, 0, [&] {
-            hipLaunchKernelGGL(k_copy_all, dim3(grid_for(n / NT + 1, 4096)), dim3(NT), 0, st, c);
-        });
-        KD_LAUNCH_CHECK();
-    }
-    uint32_t levels_run = 0;
-    for (uint32_t level = 0;; level++) {
-        if (hipMemcpyAsync(&hi, c.info, sizeof(hi), hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return KD_EDEVICE;
-        if (level > 0 && hi.splits > 0) {
-            level_first[nlevels + 1] = hi.num_nodes;
-            nlevels++;
-        }
-        if (hi.status != KD_OK || hi.num_cells == 0 || level >= 128) break;
-        levels_run++;
-        const uint32_t nc = hi.num_cells, ntl = hi.num_tiles;
-        const uint64_t bigp = hi.big_points, smallp = hi.points - hi.big_points;
-        P.run(KD_PROF_OTHER, 0, 0, [&] {
-            hipLaunchKernelGGL(k_level_init, dim3(grid_for(nc / NT + 1, 4096)), dim3(NT), 0, st,
-                               c, level, nc);
-        });
-        if (ntl > 0) {
-            for (uint32_t pass = 0; pass < uint32_t(RPASSES); pass++) {
-                P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
-                    hipLaunchKernelGGL(k_big_hist, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
-                                       level, pass, nc, ntl);
-                });
-                P.run(KD_PROF_PICK, 0, 0, [&] {
-                    hipLaunchKernelGGL(k_big_pick, dim3(grid_for(nc, 65535)), dim3(NT), 0, st, c,
-                                       level, pass, nc);
-                });
-            }
-            P.run(KD_PROF_COUNT, bigp, 4 * bigp, [&] {
-                hipLaunchKernelGGL(k_big_count, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
-                                   level, nc, ntl);
-                hipLaunchKernelGGL(k_big_tilescan, dim3(grid_for(nc, 65535)), dim3(NT), 0, st, c,
-                                   level, nc);
-            });
-            P.run(KD_PROF_BIG_SCATTER, bigp, scatter_bpp * bigp, [&] {
-                hipLaunchKernelGGL(k_big_scatter, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
-                                   level, nc, ntl);
-            });
-        }
-        if (smallp > 0) {
-            P.run(KD_PROF_SMALL, smallp, scatter_bpp * smallp, [&] {
-                hipLaunchKernelGGL(k_small, dim3(grid_for(nc, 1u << 20)), dim3(NT), 0, st, c, level,
-                                   nc);
-            });
-        }
-        const uint32_t nb = (nc + NT - 1) / NT;
-        P.run(KD_PROF_EMIT, 0, 0, [&] {
-            hipLaunchKernelGGL(k_emit_sum, dim3(nb), dim3(NT), 0, st, c, level, nc);
-            hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(NT), 0, st, c, level, nb);
-            hipLaunchKernelGGL(k_emit_write, dim3(nb), dim3(NT), 0, st, c, level, nc);
-        });
-        KD_LAUNCH_CHECK();
-    }
-    const uint32_t depth = nlevels - 1;
-    P.run(KD_PROF_OTHER, 0, 0, [&] {
-        if (hi.status == KD_OK) {
-            for (int l = int(nlevels) - 1; l >= 0; l--) {
-                uint32_t a = level_first[l], b = level_first[l + 1];
-                hipLaunchKernelGGL(k_leaf_count, dim3(grid_for((b - a) / NT + 1, 4096)), dim3(NT),
-                                   0, st, c, a, b);
-            }
-            for (uint32_t l = 0; l < nlevels; l++) {
-                uint32_t a = level_first[l], b = level_first[l + 1];
-                hipLaunchKernelGGL(k_leaf_first, dim3(grid_for((b - a) / NT + 1, 4096)), dim3(NT),
-                                   0, st, c, a, b);
-            }
-            hipLaunchKernelGGL(k_leaf_write, dim3(grid_for(hi.num_nodes / NT + 1, 4096)), dim3(NT),
-                               0, st, c, hi.num_nodes);
-        }
-        hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, st, c, depth);
-    });
-    KD_LAUNCH_CHECK();
-    if (!P.finish(levels_run)) return KD_EDEVICE;
-    return KD_OK;
+    const HostTree ht{pts, n, ld, d, out};
+    return run_build(1, &ht, p, workspace, ws_bytes, reinterpret_cast<hipStream_t>(stream), prof);
 }
 
 kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const kd_params *p,
@@ -939,28 +1518,33 @@ kd_status kd_query_leaf(const kd_tree *tree, const float *q, uint64_t nq, uint32
 
 kd_status kd_batch_bounds(uint32_t count, const kd_batch_item *items, const kd_params *params,
                           uint64_t *workspace_bytes) {
-    if (count == 0 || !items || !params || !workspace_bytes) return KD_EINVAL;
-    uint64_t mx = 0;
+    if (count == 0 || !items || !params || !workspace_bytes || !params_ok(params))
+        return KD_EINVAL;
+    std::vector<uint64_t> n(count), cap(count);
+    std::vector<uint32_t> d(count);
     for (uint32_t t = 0; t < count; t++) {
-        uint64_t cap, ws;
-        kd_status s = kd_tree_bounds(items[t].n, items[t].d, params, &cap, &ws);
-        if (s != KD_OK) return s;
-        if (ws > mx) mx = ws;
+        if (!shape_ok(items[t].n, items[t].d)) return KD_EINVAL;
+        n[t] = items[t].n;
+        d[t] = items[t].d;
+        cap[t] = items[t].out.node_capacity ? items[t].out.node_capacity
+                                            : default_capacity(n[t], params->leaf_size);
     }
-    *workspace_bytes = mx;
+    *workspace_bytes = plan(count, n.data(), d.data(), cap.data(), params).total;
     return KD_OK;
 }
 
 kd_status kd_build_batched(uint32_t count, const kd_batch_item *items, const kd_params *params,
                            void *workspace, uint64_t ws_bytes, void *stream) {
-    if (count == 0 || !items || !params) return KD_EINVAL;
+    if (count == 0 || !items || !params_ok(params) || !workspace) return KD_EINVAL;
+    std::vector<HostTree> ht(count);
     for (uint32_t t = 0; t < count; t++) {
-        kd_tree o = items[t].out;
-        kd_status s = kd_build(items[t].pts, items[t].n, items[t].d, items[t].ld, params, &o,
-                               workspace, ws_bytes, stream);
-        if (s != KD_OK) return s;
+        const kd_batch_item &it = items[t];
+        if (!shape_ok(it.n, it.d) || !it.pts || it.ld < it.n || !tree_ok(&it.out))
+            return KD_EINVAL;
+        ht[t] = HostTree{it.pts, it.n, it.ld, it.d, &it.out};
     }
-    return KD_OK;
+    return run_build(count, ht.data(), params, workspace, ws_bytes,
+                     reinterpret_cast<hipStream_t>(stream), nullptr);
 }
 
 }  // extern "C"
