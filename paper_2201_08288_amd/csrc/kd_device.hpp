@@ -15,9 +15,14 @@ constexpr int NW = NT / WAVE;
 constexpr int TILE = 4096;           // positions per tile on the large-cell path
 constexpr int PER_THREAD = TILE / NT;
 constexpr int SMALL_MAX = 4096;      // cells up to this size are done by one workgroup
-constexpr int RBITS = 8;             // radix-select digit width
+constexpr int RBITS = 8;             // radix-select digit width inside one workgroup
 constexpr int NBINS = 1 << RBITS;
 constexpr int RPASSES = 32 / RBITS;
+// large cells: three device-wide passes of 11, 11 and 10 bits
+constexpr int BIG_PASSES = 3;
+constexpr int BIG_BINS = 2048;
+__host__ __device__ constexpr int big_bits(int pass) { return pass < 2 ? 11 : 10; }
+__host__ __device__ constexpr int big_shift(int pass) { return pass == 0 ? 21 : (pass == 1 ? 10 : 0); }
 constexpr int MAX_SUBSETS = 4096;
 constexpr int MAX_LEVELS = 128;
 constexpr uint32_t NONE = 0xffffffffu;
@@ -43,11 +48,23 @@ struct CellRes {
     uint32_t prefix;  // radix-select prefix found so far (large cells)
     uint32_t rank;    // rank still to find below the prefix
     uint32_t cand;    // candidate m of the split rule
-    uint32_t pad;
+    uint32_t lt;      // large cells, EXACT: keys below the selected prefix
+    uint32_t le;      // ... and at or below the candidate once known
+    uint32_t pad[2];
 };
 constexpr uint32_t RES_SPLIT = 1u;       // the cell is split
 constexpr uint32_t RES_LEFT_LEAF = 2u;   // the left child stops here
 constexpr uint32_t RES_RIGHT_LEAF = 4u;  // the right child stops here
+
+// One tile of a large cell, ready for the scatter (written once the cell's
+// split is known): positions of the tile and of its left and right runs.
+struct TileDesc {
+    uint32_t tb, cnt;      // first position and size of the tile
+    uint32_t lpos, rpos;   // first position of the tile's left / right run
+    uint32_t split, flags; // the cell's split key and RES_* flags
+    uint32_t dim, tree;
+    uint32_t li, pad[3];   // the cell's index within its tree's level list
+};
 
 // Read-only description of one tree of the build (device memory).
 struct TreeDesc {
@@ -83,8 +100,28 @@ struct TreeState {
 // Totals of the level about to run (read back by the host).
 struct LevelInfo {
     uint32_t num_cells, num_tiles, points, big_points;
-    uint32_t num_big, pad[3];
+    uint32_t num_big, mid_cells, pad[2];  // mid: small cells above the wave-kernel size
 };
+
+// Pointers read from device-side descriptors are generic; accesses through
+// these views compile to global (not flat) memory instructions.
+#define KD_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ KD_GLOBAL T *gp(T *p) {
+    return (KD_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ const KD_GLOBAL T *gp(const T *p) {
+    return (const KD_GLOBAL T *)p;
+}
+
+// Read-only views for data no kernel writes while it runs (tree descriptors,
+// the current level's cell list): loads become scalar when uniform.
+#define KD_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const KD_CONST T &cref(const T *p) {
+    return *(const KD_CONST T *)p;
+}
 
 // Order-preserving map of an fp32 bit pattern onto uint32; -0 folds onto +0.
 __device__ __forceinline__ uint32_t key_of_bits(uint32_t b) {

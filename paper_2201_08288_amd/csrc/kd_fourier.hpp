@@ -99,10 +99,17 @@ __device__ __forceinline__ void fourier_terms(uint32_t key, double xmin, double 
     const float sc = s1 * c1;
     const float S2 = 2.0f * sc;
     float cj = c1, sj = s1;
-    for (int j = 0; j < j0 + FCHUNK && j < J; j++) {
-        if (j >= j0) {
-            acc[j - j0] += (long long)(int)rintf(cj * 16777216.0f);
-            acc[FCHUNK + j - j0] += (long long)(int)rintf(sj * 16777216.0f);
+    for (int j = 0; j < j0; j++) {  // advance the recurrence to harmonic j0
+        const float a = cj * C2, b = sj * S2;
+        const float g = sj * C2, h = cj * S2;
+        cj = a - b;
+        sj = g + h;
+    }
+#pragma unroll
+    for (int k = 0; k < FCHUNK; k++) {
+        if (j0 + k < J) {
+            acc[k] += (long long)(int)rintf(cj * 16777216.0f);
+            acc[FCHUNK + k] += (long long)(int)rintf(sj * 16777216.0f);
         }
         const float a = cj * C2, b = sj * S2;
         const float g = sj * C2, h = cj * S2;

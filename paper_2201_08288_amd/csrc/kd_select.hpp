@@ -52,8 +52,10 @@ __device__ SelectResult block_select(KEYS keys, uint32_t n, uint32_t k, uint32_t
     return SelectResult{prefix, lt, lt + cnt};
 }
 
-// Wave radix select over keys[0..n) in LDS; h: this wave's NBINS words.
-__device__ uint32_t wave_select(const uint32_t *keys, uint32_t n, uint32_t k, uint32_t *h) {
+// Wave radix select over keys[off .. off+n) of an LDS array stored with one
+// pad word per 32 (element i at i + i / 32); h: this wave's NBINS words.
+__device__ uint32_t wave_select(const uint32_t *keys, uint32_t off, uint32_t n, uint32_t k,
+                                uint32_t *h) {
     uint32_t prefix = 0;
     const int l = lane();
     for (int pass = 0; pass < RPASSES; pass++) {
@@ -62,7 +64,8 @@ __device__ uint32_t wave_select(const uint32_t *keys, uint32_t n, uint32_t k, ui
         for (int b = l; b < NBINS; b += WAVE) h[b] = 0;
         wave_sync();
         for (uint32_t i = l; i < n; i += WAVE) {
-            uint32_t u = keys[i];
+            const uint32_t g = off + i;
+            uint32_t u = keys[g + (g >> 5)];
             if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & (NBINS - 1)], 1u);
         }
         wave_sync();

@@ -40,10 +40,12 @@ static_assert(2 * FCHUNK <= NT, "moment chunk fits one workgroup");
 
 namespace {
 
-constexpr int EMIT_COUNTERS = 8;
-constexpr int EMIT_STRIDE = 8;
+constexpr int EMIT_COUNTERS = 9;
+constexpr int EMIT_STRIDE = 12;
+constexpr uint32_t WAVE_CELL_MAX = 1024;  // small cells up to this size: one wave per cell
 // emit counters: splits, active children, tiles, points, large-cell points,
-// large cells, points of split cells, unsplittable cells
+// large cells, points of split cells, unsplittable cells, small cells above
+// WAVE_CELL_MAX
 
 struct Ctx {
     TreeDesc *trees;
@@ -53,6 +55,8 @@ struct Ctx {
     CellRes *res;
     uint32_t *big_list;
     uint32_t *tile_lt, *tile_le, *tile_off;
+    uint32_t *tile_cell;
+    TileDesc *tiles;
     uint32_t *hist;
     uint32_t *mm;
     long long *mom;
@@ -78,7 +82,7 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t v) {
 
 __global__ __launch_bounds__(NT) void k_init(Ctx c) {
     const uint32_t t = blockIdx.y;
-    const TreeDesc T = c.trees[t];
+    const KD_CONST TreeDesc &T = cref(&c.trees[t]);
     for (uint64_t i = blockIdx.x * uint64_t(NT) + threadIdx.x; i < T.cap;
          i += uint64_t(gridDim.x) * NT) {
         T.node_begin[i] = 0;
@@ -115,20 +119,32 @@ __global__ __launch_bounds__(NT) void k_init(Ctx c) {
 // a1: copy the caller's points into working buffer 0 (float bits), identity
 // permutation, reject NaN / Inf; max |x| for the largest-variance grid.
 __global__ __launch_bounds__(NT) void k_ingest(Ctx c) {
-    const uint32_t t = blockIdx.y;
-    const TreeDesc T = c.trees[t];
+    const uint32_t t = blockIdx.z, col = blockIdx.y;
+    const KD_CONST TreeDesc &T = cref(&c.trees[t]);
+    if (col >= T.d) return;
+    const KD_GLOBAL uint32_t *src = gp(T.pts + uint64_t(col) * T.ld);
+    KD_GLOBAL uint32_t *dst = gp(T.cols[0] + uint64_t(col) * T.n);
+    KD_GLOBAL uint32_t *perm = gp(T.perm[0]);
+    const uint32_t n = T.n;
     bool bad = false;
     uint32_t mx = 0;
-    for (uint32_t col = 0; col < T.d; col++) {
-        const uint32_t *src = T.pts + uint64_t(col) * T.ld;
-        uint32_t *dst = T.cols[0] + uint64_t(col) * T.n;
-        for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < T.n; i += gridDim.x * NT) {
-            const uint32_t b = src[i];
-            const bool nf = (b & 0x7f800000u) == 0x7f800000u;
-            bad |= nf;
-            if (!nf) mx = max(mx, b & 0x7fffffffu);
-            dst[i] = b;
-            if (col == 0) T.perm[0][i] = i;
+    for (uint32_t i0 = blockIdx.x * NT * 4 + threadIdx.x; i0 < n; i0 += gridDim.x * NT * 4) {
+        uint32_t b[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t i = i0 + j * NT;
+            b[j] = i < n ? src[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t i = i0 + j * NT;
+            if (i < n) {
+                const bool nf = (b[j] & 0x7f800000u) == 0x7f800000u;
+                bad |= nf;
+                if (!nf) mx = max(mx, b[j] & 0x7fffffffu);
+                dst[i] = b[j];
+                if (col == 0) perm[i] = i;
+            }
         }
     }
     if (__any(bad) && lane() == 0) atomicExch(&c.ts[t].status, int32_t(KD_ENAN));
@@ -141,10 +157,10 @@ __global__ __launch_bounds__(NT) void k_ingest(Ctx c) {
 // Root cells of all trees whose root is split (one workgroup).
 __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
     __shared__ uint32_t sh[NW + 1];
-    uint32_t base[5] = {0, 0, 0, 0, 0};  // cells, tiles, points, big points, big cells
+    uint32_t base[6] = {0, 0, 0, 0, 0, 0};  // cells, tiles, points, big points, big cells, mid
     for (uint32_t t0 = 0; t0 < c.ntrees; t0 += NT) {
         const uint32_t t = t0 + threadIdx.x;
-        uint32_t v[5] = {0, 0, 0, 0, 0};
+        uint32_t v[6] = {0, 0, 0, 0, 0, 0};
         uint32_t n = 0;
         if (t < c.ntrees) {
             n = c.trees[t].n;
@@ -156,10 +172,11 @@ __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
                 v[2] = n;
                 v[3] = big ? n : 0u;
                 v[4] = big ? 1u : 0u;
+                v[5] = (!big && n > WAVE_CELL_MAX) ? 1u : 0u;
             }
         }
-        uint32_t pre[5];
-        for (int k = 0; k < 5; k++) {
+        uint32_t pre[6];
+        for (int k = 0; k < 6; k++) {
             uint32_t tot;
             pre[k] = base[k] + block_excl_scan(v[k], sh, &tot);
             base[k] += tot;
@@ -182,6 +199,7 @@ __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
         in.points = base[2];
         in.big_points = base[3];
         in.num_big = base[4];
+        in.mid_cells = base[5];
         *c.info = in;
     }
 }
@@ -192,7 +210,7 @@ __global__ __launch_bounds__(NT) void k_root_stats(Ctx c) {
     const uint32_t t = blockIdx.y;
     const TreeState &S = c.ts[t];
     if (S.count[0] == 0) return;
-    const TreeDesc T = c.trees[t];
+    const KD_CONST TreeDesc &T = cref(&c.trees[t]);
     const int shift = maxvar_shift(S.maxabs);
     for (uint32_t col = 0; col < T.d; col++) {
         const uint32_t *src = T.cols[0] + uint64_t(col) * T.n;
@@ -214,7 +232,7 @@ __global__ __launch_bounds__(NT) void k_copy_leafroots(Ctx c) {
     const uint32_t t = blockIdx.y;
     const TreeState &S = c.ts[t];
     if (S.count[0] != 0 || S.status != KD_OK) return;
-    const TreeDesc T = c.trees[t];
+    const KD_CONST TreeDesc &T = cref(&c.trees[t]);
     for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < T.n; i += gridDim.x * NT) {
         T.out_perm[i] = i;
         if (T.pts_out)
@@ -230,7 +248,7 @@ __global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level, uint32
     const uint32_t cur = level & 1, nxt = cur ^ 1;
     for (uint32_t ci = blockIdx.x * NT + threadIdx.x; ci < ncells; ci += gridDim.x * NT) {
         const Cell cl = c.cells[cur][ci];
-        const TreeDesc &T = c.trees[cl.tree];
+        const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
         CellRes r{};
         if (c.key_rule == KD_KEY_MAXVAR) {
             const unsigned long long *st = T.stats[cur] + uint64_t(cl.slot) * T.d * 3;
@@ -297,6 +315,11 @@ __device__ __forceinline__ void finish_cell(const Ctx &c, uint32_t level, uint32
     }
 }
 
+// LDS index of staged element i: one pad word per 32 keeps a thread's run of
+// consecutive elements on distinct banks.
+__device__ __forceinline__ uint32_t px(uint32_t i) { return i + (i >> 5); }
+constexpr int PADDED = TILE + TILE / 32;
+
 // Tile t of the level's large cells: its cell and position range.
 struct TileView {
     uint32_t ci, tb, te;
@@ -305,65 +328,113 @@ struct TileView {
 
 __device__ __forceinline__ TileView tile_view(const Ctx &c, uint32_t cur, uint32_t ncells,
                                               uint32_t t, uint32_t *s_cell) {
-    if (threadIdx.x == 0) *s_cell = find_tile_cell(c.cells[cur], ncells, t);
-    __syncthreads();
     TileView v;
-    v.ci = *s_cell;
+    v.ci = __builtin_amdgcn_readfirstlane(c.tile_cell[t]);  // uniform: scalar loads below
     v.cl = c.cells[cur][v.ci];
     v.tb = v.cl.begin + (t - v.cl.tile0) * TILE;
     v.te = min(v.tb + TILE, v.cl.end);
     return v;
 }
 
-// EXACT, large cells: one digit histogram per tile added into the cell's.
+// Cell of every tile of the level's large cells.
+__global__ __launch_bounds__(NT) void k_tile_map(Ctx c, uint32_t level, uint32_t ncells,
+                                                 uint32_t ntiles) {
+    const uint32_t cur = level & 1;
+    for (uint32_t t = blockIdx.x * NT + threadIdx.x; t < ntiles; t += gridDim.x * NT)
+        c.tile_cell[t] = find_tile_cell(c.cells[cur], ncells, t);
+}
+
+// EXACT, large cells: digit histograms of a run of consecutive tiles in LDS,
+// added into the cell's histogram whenever the run moves to another cell.
 __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t pass,
                                                  uint32_t ncells, uint32_t ntiles) {
-    __shared__ uint32_t h[NBINS];
+    __shared__ uint32_t h[BIG_BINS];
     __shared__ uint32_t s_cell;
     const uint32_t cur = level & 1;
-    const int shift = 32 - RBITS * (pass + 1);
-    const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        for (int b = threadIdx.x; b < NBINS; b += NT) h[b] = 0;
+    const int shift = big_shift(pass);
+    const uint32_t dmask = (1u << big_bits(pass)) - 1u;
+    const uint32_t pmask = pass == 0 ? 0u : (~0u << (shift + big_bits(pass)));
+    const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = blockIdx.x * per, t1 = min(t0 + per, ntiles);
+    for (int b = threadIdx.x; b < BIG_BINS; b += NT) h[b] = 0;
+    uint32_t big = NONE;
+    for (uint32_t t = t0; t < t1; t++) {
         const TileView v = tile_view(c, cur, ncells, t, &s_cell);
+        if (v.cl.big != big) {
+            if (big != NONE) {
+                uint32_t *gh = c.hist + uint64_t(big) * BIG_BINS;
+                for (int b = threadIdx.x; b < BIG_BINS; b += NT) {
+                    if (h[b]) atomicAdd(&gh[b], h[b]);
+                    h[b] = 0;
+                }
+            }
+            big = v.cl.big;
+            __syncthreads();
+        }
         const CellRes r = c.res[v.ci];
-        const TreeDesc &T = c.trees[v.cl.tree];
-        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n;
-        for (uint32_t i = v.tb + threadIdx.x; i < v.te; i += NT) {
-            const uint32_t u = key_of_bits(col[i]);
-            if ((u & mask) == r.prefix) atomicAdd(&h[(u >> shift) & (NBINS - 1)], 1u);
+        const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
+        const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
+        uint32_t u[PER_THREAD];
+#pragma unroll
+        for (int j = 0; j < PER_THREAD; j++) {
+            const uint32_t i = v.tb + j * NT + threadIdx.x;
+            u[j] = i < v.te ? key_of_bits(col[i]) : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < PER_THREAD; j++) {
+            const uint32_t i = v.tb + j * NT + threadIdx.x;
+            if (i < v.te && (u[j] & pmask) == r.prefix) atomicAdd(&h[(u[j] >> shift) & dmask], 1u);
         }
         __syncthreads();
-        uint32_t *gh = c.hist + uint64_t(v.cl.big) * NBINS;
-        for (int b = threadIdx.x; b < NBINS; b += NT)
+    }
+    if (big != NONE) {
+        uint32_t *gh = c.hist + uint64_t(big) * BIG_BINS;
+        for (int b = threadIdx.x; b < BIG_BINS; b += NT)
             if (h[b]) atomicAdd(&gh[b], h[b]);
-        __syncthreads();
     }
 }
 
-// EXACT, large cells: pick the digit that holds the target rank.
+// EXACT, large cells: pick the digit that holds the target rank.  After the
+// last pass the candidate is the lower median and lt / le are exact.
 __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t pass,
                                                  uint32_t nbig) {
+    constexpr int PER = BIG_BINS / NT;
     __shared__ uint32_t sh[NW + 1];
-    __shared__ uint32_t s_bin, s_below;
-    const int shift = 32 - RBITS * (pass + 1);
+    __shared__ uint32_t s_bin, s_below, s_cnt;
+    const int shift = big_shift(pass);
+    const uint32_t nb = 1u << big_bits(pass);
     for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
         const uint32_t ci = c.big_list[b];
         CellRes r = c.res[ci];
-        uint32_t *gh = c.hist + uint64_t(b) * NBINS;
-        const uint32_t hv = gh[threadIdx.x];
-        gh[threadIdx.x] = 0;
+        uint32_t *gh = c.hist + uint64_t(b) * BIG_BINS;
+        uint32_t hv[PER], local = 0;
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            const uint32_t bin = threadIdx.x * PER + j;
+            hv[j] = bin < nb ? gh[bin] : 0u;
+            local += hv[j];
+            gh[bin] = 0;
+        }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan(hv, sh, &tot);
-        if (ex <= r.rank && r.rank < ex + hv) {
-            s_bin = threadIdx.x;
-            s_below = ex;
+        uint32_t ex = block_excl_scan(local, sh, &tot);
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            if (ex <= r.rank && r.rank < ex + hv[j]) {
+                s_bin = threadIdx.x * PER + j;
+                s_below = ex;
+                s_cnt = hv[j];
+            }
+            ex += hv[j];
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             r.prefix |= s_bin << shift;
             r.rank -= s_below;
-            if (pass == RPASSES - 1) r.cand = r.prefix;
+            r.lt += s_below;  // keys below the selected digit
+            if (pass == BIG_PASSES - 1) {
+                r.cand = r.prefix;
+                r.le = r.lt + s_cnt;
+            }
             c.res[ci] = r;
         }
         __syncthreads();
@@ -379,8 +450,8 @@ __global__ __launch_bounds__(NT) void k_big_minmax(Ctx c, uint32_t level, uint32
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileView v = tile_view(c, cur, ncells, t, &s_cell);
         const CellRes r = c.res[v.ci];
-        const TreeDesc &T = c.trees[v.cl.tree];
-        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n;
+        const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
+        const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
         uint32_t mn = NONE, mx = 0;
         for (uint32_t i = v.tb + threadIdx.x; i < v.te; i += NT) {
             const uint32_t u = key_of_bits(col[i]);
@@ -434,8 +505,8 @@ __global__ __launch_bounds__(NT) void k_big_moments(Ctx c, uint32_t level, uint3
             continue;
         }
         const CellRes r = c.res[v.ci];
-        const TreeDesc &T = c.trees[v.cl.tree];
-        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n;
+        const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
+        const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
         const int e = fourier_exponent(lo, hi);
         const double xmin = value_of_key(lo), scale = fourier_scale(e);
         long long *dst = c.mom + uint64_t(v.cl.big) * 2 * FOURIER_JMAX;
@@ -525,7 +596,7 @@ __global__ __launch_bounds__(NT) void k_subset_select(Ctx c, uint32_t level, uin
         const uint32_t ci = c.big_list[b];
         const Cell cl = c.cells[cur][ci];
         const CellRes r = c.res[ci];
-        const TreeDesc &T = c.trees[cl.tree];
+        const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
         const uint32_t *B = c.bounds + uint64_t(b) * (c.S + 1);
         const uint32_t sb = cl.begin + B[s], ns = B[s + 1] - B[s];
         const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n + sb;
@@ -563,13 +634,21 @@ __global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level, uint32_
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileView v = tile_view(c, cur, ncells, t, &s_cell);
         const CellRes r = c.res[v.ci];
-        const TreeDesc &T = c.trees[v.cl.tree];
-        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n;
-        uint32_t lt = 0, le = 0;
-        for (uint32_t i = v.tb + threadIdx.x; i < v.te; i += NT) {
-            const uint32_t u = key_of_bits(col[i]);
-            lt += u < r.cand;
-            le += u <= r.cand;
+        const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
+        const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
+        uint32_t lt = 0, le = 0, u[PER_THREAD];
+#pragma unroll
+        for (int j = 0; j < PER_THREAD; j++) {
+            const uint32_t i = v.tb + j * NT + threadIdx.x;
+            u[j] = i < v.te ? key_of_bits(col[i]) : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < PER_THREAD; j++) {
+            const uint32_t i = v.tb + j * NT + threadIdx.x;
+            if (i < v.te) {
+                lt += u[j] < r.cand;
+                le += u[j] <= r.cand;
+            }
         }
         uint32_t tlt, tle;
         block_excl_scan(lt, sh, &tlt);
@@ -604,6 +683,7 @@ __global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level, uint32
         CellRes r = c.res[ci];
         finish_cell(c, level, n_c, r, r.cand, lt, le);
         const bool use_le = (r.flags & RES_SPLIT) && r.split == r.cand;
+        const uint32_t li = ci - c.ts[cl.tree].first[cur];
         uint32_t base = 0;
         for (uint32_t k0 = 0; k0 < nt; k0 += NT) {
             const uint32_t k = k0 + threadIdx.x;
@@ -611,7 +691,26 @@ __global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level, uint32
             if (k < nt) v = use_le ? c.tile_le[cl.tile0 + k] : c.tile_lt[cl.tile0 + k];
             uint32_t tot;
             const uint32_t ex = block_excl_scan(v, sh, &tot);
-            if (k < nt) c.tile_off[cl.tile0 + k] = base + ex;
+            if (k < nt) {
+                const uint32_t loff = base + ex;  // left points of the cell before this tile
+                TileDesc D;
+                D.tb = cl.begin + k * TILE;
+                D.cnt = min(uint32_t(TILE), cl.end - D.tb);
+                if (r.flags & RES_SPLIT) {
+                    D.lpos = cl.begin + loff;
+                    D.rpos = cl.begin + r.nl + (k * TILE - loff);
+                } else {  // unsplittable: the tile stays where it is (one "left" run)
+                    D.lpos = D.tb;
+                    D.rpos = D.tb + D.cnt;
+                }
+                D.split = r.split;
+                D.flags = r.flags;
+                D.dim = r.dim;
+                D.tree = cl.tree;
+                D.li = li;
+                D.pad[0] = D.pad[1] = D.pad[2] = 0;
+                c.tiles[cl.tile0 + k] = D;
+            }
             base += tot;
         }
         if (threadIdx.x == 0) c.res[ci] = r;
@@ -619,118 +718,144 @@ __global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level, uint32
     }
 }
 
-// a7: move every column and the permutation of positions [tb, tb+cnt) of cell
-// cl to cell-relative destinations dest[] (LDS).  Children that stop here go
-// to the outputs, the others to the next working buffer.  With the
-// largest-variance key, the children's fixed-point sums are accumulated on
-// the way (atomically when several tiles share the cell).
-__device__ __forceinline__ void move_columns(const Ctx &c, uint32_t cur, const Cell &cl,
-                                             const CellRes &r, uint32_t li, uint32_t tb,
-                                             uint32_t cnt, const uint32_t *dest,
-                                             unsigned long long *sh64, bool atomic) {
-    const uint32_t nxt = cur ^ 1;
-    const TreeDesc &T = c.trees[cl.tree];
-    const uint32_t n_c = cl.end - cl.begin;
-    const bool lleaf = r.flags & RES_LEFT_LEAF, rleaf = r.flags & RES_RIGHT_LEAF;
-    const bool stats = c.key_rule == KD_KEY_MAXVAR && (r.flags & RES_SPLIT) && !(lleaf && rleaf);
-    const int shift = stats ? maxvar_shift(c.ts[cl.tree].maxabs) : 0;
-    for (uint32_t k = 0; k <= T.d; k++) {
-        const bool is_perm = k == T.d;
-        const uint32_t *src = is_perm ? T.perm[cur] : T.cols[cur] + uint64_t(k) * T.n;
-        uint32_t *dnext = is_perm ? T.perm[nxt] : T.cols[nxt] + uint64_t(k) * T.n;
-        uint32_t *dout =
-            is_perm ? T.out_perm : (T.pts_out ? T.pts_out + uint64_t(k) * T.n : nullptr);
-        uint32_t v[PER_THREAD];
-#pragma unroll
-        for (int j = 0; j < PER_THREAD; j++) {
-            const uint32_t i = j * NT + threadIdx.x;
-            if (i < cnt) v[j] = src[tb + i];
-        }
-        unsigned long long acc[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int j = 0; j < PER_THREAD; j++) {
-            const uint32_t i = j * NT + threadIdx.x;
-            if (i < cnt) {
-                const uint32_t dr = dest[i];
-                const bool right = dr >= r.nl;
-                const bool leaf = right ? rleaf : lleaf;
-                uint32_t *dst = leaf ? dout : dnext;
-                if (dst && dr < n_c) dst[cl.begin + dr] = v[j];
-                if (stats && !is_perm && !leaf) {
-                    const long long q = maxvar_q(v[j], shift);
-                    const unsigned long long q2 = (unsigned long long)(q * q);
-                    const int o = right ? 3 : 0;
-                    acc[o] += (unsigned long long)q;
-                    acc[o + 1] += q2 >> 32;
-                    acc[o + 2] += q2 & 0xffffffffull;
-                }
-            }
-        }
-        if (stats && !is_perm) {
-            block_sum64n<6>(acc, sh64);
-            if (threadIdx.x < 6) {
-                const int side = threadIdx.x / 3, j = threadIdx.x % 3;
-                if (!(side ? rleaf : lleaf)) {
-                    unsigned long long *st =
-                        T.stats[nxt] + (uint64_t(2 * li + side) * T.d + k) * 3 + j;
-                    if (atomic) atomicAdd(st, acc[threadIdx.x]);
-                    else *st = acc[threadIdx.x];
-                }
-            }
+// Largest-variance sums of one column's values for both children, added into
+// the children's statistics slots (atomically when several tiles share them).
+__device__ __forceinline__ void flush_stats(const KD_CONST TreeDesc &T, uint32_t nxt, uint32_t li,
+                                            uint32_t k, unsigned long long *acc, bool lleaf,
+                                            bool rleaf, unsigned long long *sh64, bool atomic) {
+    block_sum64n<6>(acc, sh64);
+    if (threadIdx.x < 6) {
+        const int side = threadIdx.x / 3, j = threadIdx.x % 3;
+        if (!(side ? rleaf : lleaf)) {
+            unsigned long long *st = T.stats[nxt] + (uint64_t(2 * li + side) * T.d + k) * 3 + j;
+            if (atomic) atomicAdd(st, acc[threadIdx.x]);
+            else *st = acc[threadIdx.x];
         }
     }
 }
 
-// a7, large cells: stable partition-scatter of one tile.
-__global__ __launch_bounds__(NT) void k_big_scatter(Ctx c, uint32_t level, uint32_t ncells,
-                                                    uint32_t ntiles) {
-    __shared__ uint32_t dest[TILE];
+__device__ __forceinline__ void add_stats(unsigned long long *acc, uint32_t bits, int shift,
+                                          bool right) {
+    const long long q = maxvar_q(bits, shift);
+    const unsigned long long q2 = (unsigned long long)(q * q);
+    const int o = right ? 3 : 0;
+    acc[o] += (unsigned long long)q;
+    acc[o + 1] += q2 >> 32;
+    acc[o + 2] += q2 & 0xffffffffull;
+}
+
+// a7, large cells: stable partition-scatter of one tile.  Ranks come from the
+// staged key column; each column (and the permutation) is then permuted in
+// LDS and written as two contiguous runs, the left and right children's.
+template <bool MAXVAR>
+__global__ __launch_bounds__(NT) void k_big_scatter(Ctx c, uint32_t level, uint32_t ntiles) {
+    __shared__ uint32_t stage0[PADDED];  // staged keys / ranks, then a column buffer
+    __shared__ uint32_t stage1[TILE];
     __shared__ uint32_t sh[NW + 1];
-    __shared__ uint32_t s_cell;
     __shared__ unsigned long long sh64[NW * 6];
-    const uint32_t cur = level & 1;
+    const uint32_t cur = level & 1, nxt = cur ^ 1;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const TileView v = tile_view(c, cur, ncells, t, &s_cell);
-        const CellRes r = c.res[v.ci];
-        const TreeDesc &T = c.trees[v.cl.tree];
-        const uint32_t cnt = v.te - v.tb;
-        if (r.flags & RES_SPLIT) {
-            const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n;
-            // stage keys (coalesced), then each thread ranks PER_THREAD consecutive ones
-            for (uint32_t i = threadIdx.x; i < cnt; i += NT) dest[i] = key_of_bits(col[v.tb + i]);
+        const TileDesc D = c.tiles[__builtin_amdgcn_readfirstlane(t)];
+        const KD_CONST TreeDesc &T = cref(&c.trees[D.tree]);
+        const uint32_t cnt = D.cnt, d = T.d, n = T.n;
+        const bool lleaf = D.flags & RES_LEFT_LEAF, rleaf = D.flags & RES_RIGHT_LEAF;
+        uint32_t dr[PER_THREAD];
+        uint32_t nleft_tile = 0;
+        if (D.flags & RES_SPLIT) {
+            const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(D.dim) * n + D.tb);
+            uint32_t u[PER_THREAD];
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) {
+                const uint32_t i = j * NT + threadIdx.x;
+                u[j] = i < cnt ? key_of_bits(col[i]) : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) {
+                const uint32_t i = j * NT + threadIdx.x;
+                if (i < cnt) stage0[px(i)] = u[j];
+            }
             __syncthreads();
             const uint32_t i0 = threadIdx.x * PER_THREAD;
             uint32_t f = 0, nleft = 0;
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
                 const uint32_t i = i0 + j;
-                const bool l = i < cnt && dest[i] <= r.split;
+                const bool l = i < cnt && stage0[px(i)] <= D.split;
                 f |= uint32_t(l) << j;
                 nleft += l;
             }
-            uint32_t tot;
-            const uint32_t lpre = block_excl_scan(nleft, sh, &tot);
-            const uint32_t lbase = c.tile_off[t];
-            const uint32_t rbase = r.nl + (v.tb - v.cl.begin) - lbase;
-            uint32_t lo = lbase + lpre, ro = rbase + (i0 - lpre);
+            const uint32_t lpre = block_excl_scan(nleft, sh, &nleft_tile);
+            uint32_t lo = lpre, ro = nleft_tile + (i0 - lpre);
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
                 const uint32_t i = i0 + j;
-                if (i < cnt) dest[i] = ((f >> j) & 1u) ? lo++ : ro++;
+                if (i < cnt) stage0[px(i)] = ((f >> j) & 1u) ? lo++ : ro++;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) {
+                const uint32_t i = j * NT + threadIdx.x;
+                dr[j] = i < cnt ? stage0[px(i)] : 0u;
             }
         } else {
-            for (uint32_t i = threadIdx.x; i < cnt; i += NT) dest[i] = v.tb - v.cl.begin + i;
+            // all keys equal: the cell is a leaf, its points go to the outputs in place
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) dr[j] = j * NT + threadIdx.x;
+            nleft_tile = cnt;
         }
         __syncthreads();
-        move_columns(c, cur, v.cl, r, v.ci - c.ts[v.cl.tree].first[cur], v.tb, cnt, dest, sh64,
-                     true);
+        const int shift = MAXVAR ? maxvar_shift(c.ts[D.tree].maxabs) : 0;
+        const bool stats = MAXVAR && (D.flags & RES_SPLIT) && !(lleaf && rleaf);
+        for (uint32_t k = 0; k <= d; k++) {
+            const bool is_perm = k == d;
+            const KD_GLOBAL uint32_t *src =
+                gp(is_perm ? T.perm[cur] + D.tb : T.cols[cur] + uint64_t(k) * n + D.tb);
+            uint32_t *sg = (k & 1) ? stage1 : stage0;
+            uint32_t v[PER_THREAD];
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) {
+                const uint32_t i = j * NT + threadIdx.x;
+                if (i < cnt) v[j] = src[i];
+            }
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) {
+                const uint32_t i = j * NT + threadIdx.x;
+                if (i < cnt) sg[dr[j]] = v[j];
+            }
+            __syncthreads();
+            KD_GLOBAL uint32_t *lnext =
+                gp(is_perm ? T.perm[nxt] : T.cols[nxt] + uint64_t(k) * n);
+            KD_GLOBAL uint32_t *lout =
+                gp(is_perm ? T.out_perm : (T.pts_out ? T.pts_out + uint64_t(k) * n : nullptr));
+            unsigned long long acc[6] = {0, 0, 0, 0, 0, 0};
+            // left run: staged [0, nleft_tile) -> D.lpos; right run -> D.rpos
+            KD_GLOBAL uint32_t *ldst = lleaf ? lout : lnext;
+            if (ldst) ldst += D.lpos;
+            for (uint32_t i = threadIdx.x; i < nleft_tile; i += NT) {
+                const uint32_t val = sg[i];
+                if (ldst) ldst[i] = val;
+                if (stats && !is_perm && !lleaf) add_stats(acc, val, shift, false);
+            }
+            KD_GLOBAL uint32_t *rdst = rleaf ? lout : lnext;
+            if (rdst) rdst += D.rpos;
+            for (uint32_t i = nleft_tile + threadIdx.x; i < cnt; i += NT) {
+                const uint32_t val = sg[i];
+                if (rdst) rdst[i - nleft_tile] = val;
+                if (stats && !is_perm && !rleaf) add_stats(acc, val, shift, true);
+            }
+            if (stats && !is_perm) flush_stats(T, nxt, D.li, k, acc, lleaf, rleaf, sh64, true);
+        }
         __syncthreads();
     }
 }
 
 // Small cells: the whole level step of one cell in one workgroup.
-__global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t ncells) {
-    __shared__ uint32_t keys[SMALL_MAX];
+
+template <int RULE, bool MAXVAR>
+__global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t ncells,
+                                              uint32_t skip_le) {
+    __shared__ uint32_t keys[SMALL_MAX + SMALL_MAX / 32];
+    __shared__ uint32_t stage[SMALL_MAX];
     __shared__ uint32_t h[NW][NBINS];
     __shared__ uint32_t sh[2 * NW + 1], s3[4];
     __shared__ unsigned long long sh64[NW * 2 * FCHUNK];
@@ -740,28 +865,28 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
     const int J = int(c.J);
     for (uint32_t ci = blockIdx.x; ci < ncells; ci += gridDim.x) {
         const Cell cl = c.cells[cur][ci];
-        if (cl.big != NONE) continue;
-        const TreeDesc &T = c.trees[cl.tree];
+        if (cl.big != NONE || cl.end - cl.begin <= skip_le) continue;
+        const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
         const uint32_t n_c = cl.end - cl.begin;
         const uint32_t li = ci - c.ts[cl.tree].first[cur];
         CellRes r = c.res[ci];
-        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n + cl.begin;
-        for (uint32_t i = threadIdx.x; i < n_c; i += NT) keys[i] = key_of_bits(col[i]);
+        const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n + cl.begin);
+        for (uint32_t i = threadIdx.x; i < n_c; i += NT) keys[px(i)] = key_of_bits(col[i]);
         __syncthreads();
         uint32_t m = 0, lt = 0, le = 0;
         bool counted = false;
-        if (c.split_rule == KD_SPLIT_EXACT) {
+        if (RULE == KD_SPLIT_EXACT) {
             const SelectResult sel =
-                block_select([&](uint32_t i) { return keys[i]; }, n_c, r.rank, h[0], sh, s3);
+                block_select([&](uint32_t i) { return keys[px(i)]; }, n_c, r.rank, h[0], sh, s3);
             m = sel.key;
             lt = sel.lt;
             le = sel.le;
             counted = true;
-        } else if (c.split_rule == KD_SPLIT_FOURIER) {
+        } else if (RULE == KD_SPLIT_FOURIER) {
             uint32_t mn = NONE, mx = 0;
             for (uint32_t i = threadIdx.x; i < n_c; i += NT) {
-                mn = min(mn, keys[i]);
-                mx = max(mx, keys[i]);
+                mn = min(mn, keys[px(i)]);
+                mx = max(mx, keys[px(i)]);
             }
             block_minmax(mn, mx, sh);
             m = mn;
@@ -773,7 +898,7 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
 #pragma unroll
                     for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
                     for (uint32_t i = threadIdx.x; i < n_c; i += NT)
-                        fourier_terms(keys[i], xmin, scale, J, j0, c.trig, acc);
+                        fourier_terms(keys[px(i)], xmin, scale, J, j0, c.trig, acc);
                     reduce_moments(acc, sh64, j0, J, mom, false);
                 }
                 if (wave() == 0) {
@@ -792,7 +917,7 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
             for (uint32_t s = wave(); s < c.S; s += NW) {
                 const uint32_t ns = B[s + 1] - B[s];
                 uint32_t v = NONE;
-                if (ns > 0) v = wave_select(keys + B[s], ns, (ns - 1) / 2, h[wave()]);
+                if (ns > 0) v = wave_select(keys, B[s], ns, (ns - 1) / 2, h[wave()]);
                 if (lane() == 0) med[s] = v;
             }
             __syncthreads();
@@ -804,8 +929,8 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
         if (!counted) {
             unsigned long long cnt2[2] = {0, 0};
             for (uint32_t i = threadIdx.x; i < n_c; i += NT) {
-                cnt2[0] += keys[i] < m;
-                cnt2[1] += keys[i] <= m;
+                cnt2[0] += keys[px(i)] < m;
+                cnt2[1] += keys[px(i)] <= m;
             }
             block_sum64n<2>(cnt2, sh64);
             lt = uint32_t(cnt2[0]);
@@ -817,18 +942,247 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
         const uint32_t i0 = min(threadIdx.x * E, n_c), i1 = min(i0 + E, n_c);
         if (r.flags & RES_SPLIT) {
             uint32_t nleft = 0;
-            for (uint32_t i = i0; i < i1; i++) nleft += keys[i] <= r.split;
+            for (uint32_t i = i0; i < i1; i++) nleft += keys[px(i)] <= r.split;
             uint32_t tot;
             const uint32_t lpre = block_excl_scan(nleft, sh, &tot);
             uint32_t lo = lpre, ro = r.nl + (i0 - lpre);
-            for (uint32_t i = i0; i < i1; i++) keys[i] = keys[i] <= r.split ? lo++ : ro++;
+            for (uint32_t i = i0; i < i1; i++) keys[px(i)] = keys[px(i)] <= r.split ? lo++ : ro++;
         } else {
-            for (uint32_t i = i0; i < i1; i++) keys[i] = i;
+            for (uint32_t i = i0; i < i1; i++) keys[px(i)] = i;
         }
         __syncthreads();
-        move_columns(c, cur, cl, r, li, cl.begin, n_c, keys, sh64, false);
+        // a7: permute G columns at a time through LDS (stage index g * n_c + rank),
+        // then write each column's cell range contiguously: [0, nl) to the left
+        // child, [nl, n_c) to the right child.
+        {
+            const bool lleaf = r.flags & RES_LEFT_LEAF, rleaf = r.flags & RES_RIGHT_LEAF;
+            const bool stats = MAXVAR && (r.flags & RES_SPLIT) && !(lleaf && rleaf);
+            const int shift = MAXVAR ? maxvar_shift(c.ts[cl.tree].maxabs) : 0;
+            const uint32_t d = T.d, n = T.n, nxt = cur ^ 1;
+            const uint32_t G = MAXVAR ? 1u : min(d + 1, max(1u, uint32_t(SMALL_MAX) / n_c));
+            const uint32_t dk = NT / n_c, de = NT % n_c;
+            for (uint32_t k0 = 0; k0 <= d; k0 += G) {
+                const uint32_t g_end = min(G, d + 1 - k0), items = g_end * n_c;
+                uint32_t g = threadIdx.x / n_c, e = threadIdx.x % n_c;
+#pragma unroll
+                for (int j = 0; j < PER_THREAD; j++) {
+                    const uint32_t it = j * NT + threadIdx.x;
+                    if (it < items) {
+                        const uint32_t k = k0 + g;
+                        const KD_GLOBAL uint32_t *src =
+                            gp(k == d ? T.perm[cur] : T.cols[cur] + uint64_t(k) * n);
+                        stage[g * n_c + keys[px(e)]] = src[cl.begin + e];
+                    }
+                    e += de;
+                    g += dk;
+                    if (e >= n_c) {
+                        e -= n_c;
+                        g++;
+                    }
+                }
+                __syncthreads();
+                unsigned long long acc[6] = {0, 0, 0, 0, 0, 0};
+                for (uint32_t gg = 0; gg < g_end; gg++) {
+                    const uint32_t k = k0 + gg;
+                    const uint32_t *sg = stage + gg * n_c;
+                    KD_GLOBAL uint32_t *next =
+                        gp(k == d ? T.perm[nxt] : T.cols[nxt] + uint64_t(k) * n) + cl.begin;
+                    KD_GLOBAL uint32_t *out =
+                        k == d ? gp(T.out_perm) + cl.begin
+                               : (T.pts_out ? gp(T.pts_out + uint64_t(k) * n) + cl.begin : nullptr);
+                    KD_GLOBAL uint32_t *ldst = lleaf ? out : next;
+                    KD_GLOBAL uint32_t *rdst = rleaf ? out : next;
+                    for (uint32_t i = threadIdx.x; i < r.nl; i += NT) {
+                        const uint32_t val = sg[i];
+                        if (ldst) ldst[i] = val;
+                        if (stats && k < d && !lleaf) add_stats(acc, val, shift, false);
+                    }
+                    for (uint32_t i = r.nl + threadIdx.x; i < n_c; i += NT) {
+                        const uint32_t val = sg[i];
+                        if (rdst) rdst[i] = val;
+                        if (stats && k < d && !rleaf) add_stats(acc, val, shift, true);
+                    }
+                }
+                if (stats && k0 < d) flush_stats(T, nxt, li, k0, acc, lleaf, rleaf, sh64, false);
+                __syncthreads();
+            }
+        }
         if (threadIdx.x == 0) c.res[ci] = r;
         __syncthreads();
+    }
+}
+
+// Small cells of at most WMAX points: one wave64 per cell, four cells per
+// workgroup, wave-level select, ranks and staged scatter (no workgroup
+// barriers).  Same results as k_small.
+constexpr int WMAX = int(WAVE_CELL_MAX);
+constexpr int WPAD = WMAX + WMAX / 32;
+constexpr int WPER = WMAX / WAVE;  // positions per lane
+
+template <int RULE, bool MAXVAR>
+__global__ __launch_bounds__(NT) void k_small_wave(Ctx c, uint32_t level, uint32_t ncells) {
+    __shared__ uint32_t keys_all[NW][WPAD];
+    __shared__ uint32_t stage_all[NW][WMAX];
+    __shared__ uint32_t h_all[NW][NBINS];
+    __shared__ long long mom_all[NW][RULE == KD_SPLIT_FOURIER ? 2 * FOURIER_JMAX : 1];
+    extern __shared__ uint32_t dyn[];  // SUBSET: per wave bounds[S + 1], medians[S]
+    const uint32_t cur = level & 1, nxt = cur ^ 1;
+    const int w = wave(), l = lane();
+    uint32_t *keys = keys_all[w], *stage = stage_all[w], *h = h_all[w];
+    const int J = int(c.J);
+    for (uint32_t cw = blockIdx.x * NW + w; cw < ncells; cw += gridDim.x * NW) {
+        const uint32_t ci = __builtin_amdgcn_readfirstlane(cw);
+        const Cell cl = c.cells[cur][ci];
+        const uint32_t n_c = cl.end - cl.begin;
+        if (cl.big != NONE || n_c > uint32_t(WMAX)) continue;
+        const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
+        const uint32_t li = ci - c.ts[cl.tree].first[cur];
+        CellRes r = c.res[ci];
+        {
+            const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n + cl.begin);
+            uint32_t u[WPER];
+#pragma unroll
+            for (int j = 0; j < WPER; j++) {
+                const uint32_t i = j * WAVE + l;
+                u[j] = i < n_c ? key_of_bits(col[i]) : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < WPER; j++) {
+                const uint32_t i = j * WAVE + l;
+                if (i < n_c) keys[px(i)] = u[j];
+            }
+        }
+        wave_sync();
+        uint32_t m;
+        if (RULE == KD_SPLIT_EXACT) {
+            m = wave_select(keys, 0, n_c, r.rank, h);
+        } else if (RULE == KD_SPLIT_FOURIER) {
+            uint32_t mn = NONE, mx = 0;
+            for (uint32_t i = l; i < n_c; i += WAVE) {
+                mn = min(mn, keys[px(i)]);
+                mx = max(mx, keys[px(i)]);
+            }
+            mn = wave_min(mn);
+            mx = wave_max(mx);
+            m = mn;
+            if (mn != mx) {
+                const int e = fourier_exponent(mn, mx);
+                const double xmin = value_of_key(mn), scale = fourier_scale(e);
+                long long *mom = mom_all[w];
+                for (int j0 = 0; j0 < J; j0 += FCHUNK) {
+                    long long acc[2 * FCHUNK];
+#pragma unroll
+                    for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
+                    for (uint32_t i = l; i < n_c; i += WAVE)
+                        fourier_terms(keys[px(i)], xmin, scale, J, j0, c.trig, acc);
+#pragma unroll
+                    for (int k = 0; k < 2 * FCHUNK; k++) {
+                        const long long sum = (long long)wave_sum64((unsigned long long)acc[k]);
+                        const int j = j0 + (k % FCHUNK);
+                        if (l == k && j < J) mom[(k < FCHUNK ? 0 : FOURIER_JMAX) + j] = sum;
+                    }
+                }
+                wave_sync();
+                m = fourier_solve_wave(mom, mom + FOURIER_JMAX, J, mn, mx, e, c.trig);
+            }
+        } else {
+            uint32_t *B = dyn + w * (2 * c.S + 1), *med = B + c.S + 1;
+            if (l == 0) subset_bounds(c, n_c, level, li, B);
+            wave_sync();
+            for (uint32_t sb = 0; sb < c.S; sb++) {
+                const uint32_t ns = B[sb + 1] - B[sb];
+                uint32_t v = NONE;
+                if (ns > 0) v = wave_select(keys, B[sb], ns, (ns - 1) / 2, h);
+                if (l == 0) med[sb] = v;
+            }
+            wave_sync();
+            uint32_t mm = 0;
+            if (l == 0) mm = subset_mean(B, med, c.S, n_c);
+            m = __shfl(mm, 0, WAVE);
+        }
+        uint32_t lt = 0, le = 0;
+        for (uint32_t i = l; i < n_c; i += WAVE) {
+            const uint32_t u = keys[px(i)];
+            lt += u < m;
+            le += u <= m;
+        }
+        lt = uint32_t(wave_sum64(lt));
+        le = uint32_t(wave_sum64(le));
+        finish_cell(c, level, n_c, r, m, lt, le);
+        // ranks: lane l owns E consecutive positions
+        const uint32_t E = (n_c + WAVE - 1) / WAVE;
+        const uint32_t i0 = min(uint32_t(l) * E, n_c), i1 = min(i0 + E, n_c);
+        if (r.flags & RES_SPLIT) {
+            uint32_t nleft = 0;
+            for (uint32_t i = i0; i < i1; i++) nleft += keys[px(i)] <= r.split;
+            const uint32_t lpre = wave_incl_scan(nleft) - nleft;
+            uint32_t lo = lpre, ro = r.nl + (i0 - lpre);
+            for (uint32_t i = i0; i < i1; i++) keys[px(i)] = keys[px(i)] <= r.split ? lo++ : ro++;
+        } else {
+            for (uint32_t i = i0; i < i1; i++) keys[px(i)] = i;
+        }
+        wave_sync();
+        // a7: G columns at a time through LDS, then contiguous child runs
+        const bool lleaf = r.flags & RES_LEFT_LEAF, rleaf = r.flags & RES_RIGHT_LEAF;
+        const bool stats = MAXVAR && (r.flags & RES_SPLIT) && !(lleaf && rleaf);
+        const int shift = MAXVAR ? maxvar_shift(c.ts[cl.tree].maxabs) : 0;
+        const uint32_t d = T.d, n = T.n;
+        const uint32_t G = MAXVAR ? 1u : min(d + 1, max(1u, uint32_t(WMAX) / n_c));
+        const uint32_t dk = WAVE / n_c, de = WAVE % n_c;
+        for (uint32_t k0 = 0; k0 <= d; k0 += G) {
+            const uint32_t g_end = min(G, d + 1 - k0), items = g_end * n_c;
+            uint32_t g = l / n_c, e = l % n_c;
+#pragma unroll
+            for (int j = 0; j < WPER; j++) {
+                const uint32_t it = j * WAVE + l;
+                if (it < items) {
+                    const uint32_t k = k0 + g;
+                    const KD_GLOBAL uint32_t *src =
+                        gp(k == d ? T.perm[cur] : T.cols[cur] + uint64_t(k) * n);
+                    stage[g * n_c + keys[px(e)]] = src[cl.begin + e];
+                }
+                e += de;
+                g += dk;
+                if (e >= n_c) {
+                    e -= n_c;
+                    g++;
+                }
+            }
+            wave_sync();
+            unsigned long long acc[6] = {0, 0, 0, 0, 0, 0};
+            for (uint32_t gg = 0; gg < g_end; gg++) {
+                const uint32_t k = k0 + gg;
+                const uint32_t *sg = stage + gg * n_c;
+                KD_GLOBAL uint32_t *next =
+                    gp(k == d ? T.perm[nxt] : T.cols[nxt] + uint64_t(k) * n) + cl.begin;
+                KD_GLOBAL uint32_t *out =
+                    k == d ? gp(T.out_perm) + cl.begin
+                           : (T.pts_out ? gp(T.pts_out + uint64_t(k) * n) + cl.begin : nullptr);
+                KD_GLOBAL uint32_t *ldst = lleaf ? out : next;
+                KD_GLOBAL uint32_t *rdst = rleaf ? out : next;
+                for (uint32_t i = l; i < r.nl; i += WAVE) {
+                    const uint32_t val = sg[i];
+                    if (ldst) ldst[i] = val;
+                    if (stats && k < d && !lleaf) add_stats(acc, val, shift, false);
+                }
+                for (uint32_t i = r.nl + l; i < n_c; i += WAVE) {
+                    const uint32_t val = sg[i];
+                    if (rdst) rdst[i] = val;
+                    if (stats && k < d && !rleaf) add_stats(acc, val, shift, true);
+                }
+            }
+            if (stats && k0 < d) {
+#pragma unroll
+                for (int q = 0; q < 6; q++) acc[q] = wave_sum64(acc[q]);
+                if (l < 6) {
+                    const int side = l / 3, j = l % 3;
+                    if (!(side ? rleaf : lleaf))
+                        T.stats[nxt][(uint64_t(2 * li + side) * d + k0) * 3 + j] = acc[l];
+                }
+            }
+            wave_sync();
+        }
+        if (l == 0) c.res[ci] = r;
     }
 }
 
@@ -856,6 +1210,8 @@ __device__ __forceinline__ void emit_counts(const Ctx &c, uint32_t level, uint32
             cnt[2] += (sz[s] + TILE - 1) / TILE;
             cnt[4] += sz[s];
             cnt[5]++;
+        } else if (sz[s] > WAVE_CELL_MAX) {
+            cnt[8]++;
         }
     }
 }
@@ -873,7 +1229,7 @@ __global__ __launch_bounds__(NT) void k_emit_sum(Ctx c, uint32_t level, uint32_t
 
 __global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t ncells, uint32_t nblocks) {
     __shared__ uint32_t sh[NW + 1];
-    uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t b0 = 0; b0 < nblocks; b0 += NT) {
         const uint32_t b = b0 + threadIdx.x;
         for (int k = 0; k < EMIT_COUNTERS; k++) {
@@ -893,6 +1249,7 @@ __global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t ncells, uint32
         in.points = base[3];
         in.big_points = base[4];
         in.num_big = base[5];
+        in.mid_cells = base[8];
         *c.info = in;
     }
 }
@@ -945,7 +1302,7 @@ __global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level, uint32
     const CellRes r = c.res[ci];
     if (!(r.flags & RES_SPLIT)) return;
     const Cell cl = c.cells[cur][ci];
-    const TreeDesc &T = c.trees[cl.tree];
+    const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
     const TreeState &S = c.ts[cl.tree];
     const uint32_t *pre = c.pre + uint64_t(ci) * EMIT_STRIDE;
     const uint32_t left = S.nodes_base + 2 * (pre[0] - S.split_base);
@@ -989,7 +1346,7 @@ __global__ void k_leaf_count(Ctx c, uint32_t depth) {
     const uint32_t t = blockIdx.y;
     const TreeState &S = c.ts[t];
     if (S.status != KD_OK || depth > S.depth) return;
-    const TreeDesc &T = c.trees[t];
+    const KD_CONST TreeDesc &T = cref(&c.trees[t]);
     const uint32_t a = S.depth_first[depth], b = S.depth_first[depth + 1];
     for (uint32_t k = a + blockIdx.x * NT + threadIdx.x; k < b; k += gridDim.x * NT) {
         const int32_t ch = T.node_child[k];
@@ -1001,7 +1358,7 @@ __global__ void k_leaf_first(Ctx c, uint32_t depth) {
     const uint32_t t = blockIdx.y;
     const TreeState &S = c.ts[t];
     if (S.status != KD_OK || depth > S.depth) return;
-    const TreeDesc &T = c.trees[t];
+    const KD_CONST TreeDesc &T = cref(&c.trees[t]);
     const uint32_t a = S.depth_first[depth], b = S.depth_first[depth + 1];
     for (uint32_t k = a + blockIdx.x * NT + threadIdx.x; k < b; k += gridDim.x * NT) {
         const int32_t ch = T.node_child[k];
@@ -1018,7 +1375,7 @@ __global__ __launch_bounds__(NT) void k_leaf_write(Ctx c) {
     const uint32_t t = blockIdx.y;
     const TreeState &S = c.ts[t];
     if (S.status != KD_OK) return;
-    const TreeDesc &T = c.trees[t];
+    const KD_CONST TreeDesc &T = cref(&c.trees[t]);
     unsigned long long over = 0;
     for (uint32_t k = blockIdx.x * NT + threadIdx.x; k < S.num_nodes; k += gridDim.x * NT) {
         if (T.node_child[k] < 0) {
@@ -1037,7 +1394,7 @@ __global__ void k_header(Ctx c) {
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < c.ntrees;
          t += gridDim.x * blockDim.x) {
         const TreeState &S = c.ts[t];
-        const TreeDesc &T = c.trees[t];
+        const KD_CONST TreeDesc &T = cref(&c.trees[t]);
         const uint32_t leaves = S.status == KD_OK ? T.leaf_cnt[0] : 0u;
         if (S.status == KD_OK) T.leaf_offsets[leaves] = T.n;
         kd_header h{};
@@ -1110,7 +1467,7 @@ struct TreeLayout {
 };
 
 struct Layout {
-    uint64_t trees, ts, cells[2], res, big_list, tile_lt, tile_le, tile_off, hist, mm, mom,
+    uint64_t trees, ts, cells[2], res, big_list, tile_lt, tile_le, tile_off, tile_cell, tiles, hist, mm, mom,
         bounds, med, pre, scan, info, total;
     uint64_t max_cells, max_tiles, max_big, scan_blocks;
     std::vector<TreeLayout> per_tree;
@@ -1134,7 +1491,9 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     L.tile_lt = B.take(L.max_tiles * 4);
     L.tile_le = B.take(L.max_tiles * 4);
     L.tile_off = B.take(L.max_tiles * 4);
-    L.hist = B.take(L.max_big * NBINS * 4);
+    L.tile_cell = B.take(L.max_tiles * 4);
+    L.tiles = B.take(L.max_tiles * sizeof(TileDesc));
+    L.hist = B.take(L.max_big * BIG_BINS * 4);
     const bool fourier = p->split_rule == KD_SPLIT_FOURIER;
     const bool subset = p->split_rule == KD_SPLIT_SUBSET;
     L.mm = B.take(fourier ? L.max_big * 8 : 0);
@@ -1311,6 +1670,8 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     c.tile_lt = reinterpret_cast<uint32_t *>(ws + L.tile_lt);
     c.tile_le = reinterpret_cast<uint32_t *>(ws + L.tile_le);
     c.tile_off = reinterpret_cast<uint32_t *>(ws + L.tile_off);
+    c.tile_cell = reinterpret_cast<uint32_t *>(ws + L.tile_cell);
+    c.tiles = reinterpret_cast<TileDesc *>(ws + L.tiles);
     c.hist = reinterpret_cast<uint32_t *>(ws + L.hist);
     c.mm = reinterpret_cast<uint32_t *>(ws + L.mm);
     c.mom = reinterpret_cast<long long *>(ws + L.mom);
@@ -1331,20 +1692,22 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     c.trig = make_trig();
 
     uint64_t maxcap = 0, maxn = 0;
+    uint32_t maxd = 0;
     for (uint32_t t = 0; t < ntrees; t++) {
         maxcap = cap[t] > maxcap ? cap[t] : maxcap;
         maxn = n[t] > maxn ? n[t] : maxn;
+        maxd = d[t] > maxd ? d[t] : maxd;
     }
     const dim3 per_tree_nodes(grid_for(maxcap / NT + 1, 1024), ntrees);
     const dim3 per_tree_points(grid_for(maxn / NT + 1, 1024), ntrees);
     P.run(KD_PROF_OTHER, 0, 0, [&] {
-        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.max_big, 4096)), dim3(NT), 0, st, c.hist,
-                           L.max_big * NBINS, 0u);
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.max_big * BIG_BINS / NT + 1, 4096)),
+                           dim3(NT), 0, st, c.hist, L.max_big * BIG_BINS, 0u);
         hipLaunchKernelGGL(k_init, per_tree_nodes, dim3(NT), 0, st, c);
     });
     P.run(KD_PROF_INGEST, total_points, 8 * sum_d + 4 * total_points, [&] {
-        hipLaunchKernelGGL(k_ingest, dim3(grid_for(maxn / (NT * 4) + 1, 1024), ntrees), dim3(NT),
-                           0, st, c);
+        hipLaunchKernelGGL(k_ingest, dim3(grid_for(maxn / (NT * 4) + 1, 1024), maxd, ntrees),
+                           dim3(NT), 0, st, c);
     });
     P.run(KD_PROF_OTHER, 0, 0, [&] {
         hipLaunchKernelGGL(k_roots, dim3(1), dim3(NT), 0, st, c);
@@ -1355,7 +1718,15 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     KD_LAUNCH_CHECK();
 
     const uint64_t scatter_avg_bpp = (8 * sum_d + 8 * total_points) / total_points;
+    const bool maxvar = p->key_rule == KD_KEY_MAXVAR;
+    const uint32_t hist_grid = 65535;  // workgroups of the histogram passes (tiles per group vary)
+    // dynamic LDS of the small-cell kernels (SUBSET: subset bounds and medians);
+    // the wave kernel keeps one table per wave, so it is used only while that
+    // fits next to its static LDS
     const size_t small_dyn = p->split_rule == KD_SPLIT_SUBSET ? (2 * size_t(c.S) + 1) * 4 : 0;
+    const bool wave_small = p->split_rule != KD_SPLIT_SUBSET || c.S <= 256;
+    static_assert(sizeof(uint32_t) * (2 * MAX_SUBSETS + 1) + 48 * 1024 <= 160 * 1024,
+                  "block small-cell kernel LDS");
     LevelInfo hi{};
     uint32_t levels_run = 0;
     for (uint32_t level = 0;; level++) {
@@ -1371,10 +1742,14 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                                c, level, nc);
         });
         if (ntl > 0) {
+            P.run(KD_PROF_OTHER, 0, 0, [&] {
+                hipLaunchKernelGGL(k_tile_map, dim3(grid_for(ntl / NT + 1, 4096)), dim3(NT), 0, st,
+                                   c, level, nc, ntl);
+            });
             if (p->split_rule == KD_SPLIT_EXACT) {
-                for (uint32_t pass = 0; pass < uint32_t(RPASSES); pass++) {
+                for (uint32_t pass = 0; pass < uint32_t(BIG_PASSES); pass++) {
                     P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
-                        hipLaunchKernelGGL(k_big_hist, dim3(grid_for(ntl, 65535)), dim3(NT), 0,
+                        hipLaunchKernelGGL(k_big_hist, dim3(grid_for(ntl, hist_grid)), dim3(NT), 0,
                                            st, c, level, pass, nc, ntl);
                     });
                     P.run(KD_PROF_PICK, 0, 0, [&] {
@@ -1413,14 +1788,35 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                                    level, nbig);
             });
             P.run(KD_PROF_BIG_SCATTER, bigp, scatter_avg_bpp * bigp, [&] {
-                hipLaunchKernelGGL(k_big_scatter, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
-                                   level, nc, ntl);
+                if (maxvar)
+                    hipLaunchKernelGGL(k_big_scatter<true>, dim3(grid_for(ntl, 65535)), dim3(NT), 0,
+                                       st, c, level, ntl);
+                else
+                    hipLaunchKernelGGL(k_big_scatter<false>, dim3(grid_for(ntl, 65535)), dim3(NT),
+                                       0, st, c, level, ntl);
             });
         }
         if (smallp > 0) {
             P.run(KD_PROF_SMALL, smallp, scatter_avg_bpp * smallp, [&] {
-                hipLaunchKernelGGL(k_small, dim3(grid_for(nc, 1u << 20)), dim3(NT), small_dyn, st,
-                                   c, level, nc);
+                const dim3 g(grid_for(nc, 1u << 20)), gw(grid_for(nc / NW + 1, 1u << 20));
+#define KD_SMALL(R, M)                                                                     \
+    do {                                                                                   \
+        if (!wave_small || hi.mid_cells > 0)                                               \
+            hipLaunchKernelGGL((k_small<R, M>), g, dim3(NT), small_dyn, st, c, level, nc,   \
+                               wave_small ? WAVE_CELL_MAX : 0u);                           \
+        if (wave_small)                                                                    \
+            hipLaunchKernelGGL((k_small_wave<R, M>), gw, dim3(NT), NW * small_dyn, st, c,   \
+                               level, nc);                                                 \
+    } while (0)
+                switch (p->split_rule * 2 + (maxvar ? 1 : 0)) {
+                    case 0: KD_SMALL(KD_SPLIT_EXACT, false); break;
+                    case 1: KD_SMALL(KD_SPLIT_EXACT, true); break;
+                    case 2: KD_SMALL(KD_SPLIT_FOURIER, false); break;
+                    case 3: KD_SMALL(KD_SPLIT_FOURIER, true); break;
+                    case 4: KD_SMALL(KD_SPLIT_SUBSET, false); break;
+                    default: KD_SMALL(KD_SPLIT_SUBSET, true); break;
+                }
+#undef KD_SMALL
             });
         }
         const uint32_t nb = (nc + NT - 1) / NT;
