@@ -58,6 +58,103 @@ def cpu_baseline(w, rule, sample_n):
                       f"{t['point_levels']} point-levels"}
 
 
+def gpu_uniform24(n, d, gen):
+    import torch
+    k = torch.randint(0, 1 << 24, (d, n), generator=gen, device="cuda", dtype=torch.int32)
+    return k.to(torch.float32) * (2.0 ** -24)
+
+
+def gpu_gmm(n, d, gen, components=10, box=5.0, sigma=0.5):
+    import torch
+    means = (torch.rand((components, d), generator=gen, device="cuda", dtype=torch.float64)
+             * 2 * box - box)
+    comp = torch.randint(0, components, (n,), generator=gen, device="cuda")
+    z = torch.randn((n, d), generator=gen, device="cuda", dtype=torch.float64)
+    return (means[comp] + sigma * z).to(torch.float32).t().contiguous()
+
+
+def bench_batched(trees=512, reps=3):
+    """512 independent trees: one kd_build_batched against 512 plain kd_build
+    calls on the same inputs; trees must be identical."""
+    import torch
+
+    from paper_2201_08288_amd import kdtree, synth
+    shapes = synth.batched_shapes(trees)
+    gen = torch.Generator(device="cuda").manual_seed(synth.BASE_SEED + 4)
+    pts = [gpu_uniform24(n, d, gen) for n, d in shapes]
+    kw = dict(leaf_size=32, num_subsets=32)
+    plain = [kdtree.build(x, **kw) for x in pts]  # also allocates outputs/workspaces
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for x, t in zip(pts, plain):
+            kdtree.build(x, workspace=t.workspace, tree=t, **kw)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    bt = kdtree.build_batched(pts, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bt = kdtree.build_batched(pts, **kw)
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / reps
+    same = True
+    for a, b in zip(plain, bt):
+        ha, hb = a.header(), b.header()
+        same &= ha == hb
+        if ha != hb:
+            continue
+        size = {"perm": a.n, "node_child": ha["num_nodes"], "node_split": ha["num_nodes"],
+                "node_dim": ha["num_nodes"], "leaf_offsets": ha["num_leaves"] + 1}
+        for f, m in size.items():
+            same &= bool(torch.equal(getattr(a, f)[:m], getattr(b, f)[:m]))
+    total = sum(n for n, _ in shapes)
+    pl = sum(t.header()["point_levels"] for t in bt)
+    return {"trees": trees, "points": total, "point_levels": pl,
+            "plain_trees_per_s": trees / t_plain, "batched_trees_per_s": trees / t_batched,
+            "speedup": t_plain / t_batched, "plain_ms": 1e3 * t_plain,
+            "batched_ms": 1e3 * t_batched, "identical": bool(same),
+            "workload": "512 trees, n log-uniform [2^10, 2^20], d in {2,3,8,32}, uniform24, "
+                        "S=32, leaf 32, EXACT, cyclic"}
+
+
+def bench_serving(rates=(50, 200, 1000, 2000), per_rate=150, warm=20, workers=3):
+    """Poisson build requests (n log-uniform [2^12, 2^22], d in {3,16},
+    Gaussian mixture, S=64, leaf 64) each followed by 1,024 lookups of its
+    own points; p50/p99 latency from arrival to lookups done."""
+    import numpy as np
+    import torch
+
+    from paper_2201_08288_amd import serve, synth
+    gen = torch.Generator(device="cuda").manual_seed(synth.BASE_SEED + 5)
+    params = dict(leaf_size=64, num_subsets=64)
+    eng = serve.ServeEngine(params, cap_bytes=64 << 30, workers=workers)
+    out = {}
+    try:
+        for rate in rates:
+            reqs = synth.poisson_requests(warm + per_rate, rate, stream=rate)
+            data = []
+            for k, (_, n, d) in enumerate(reqs):
+                x = gpu_gmm(n, d, gen)
+                idx = torch.randint(0, n, (1024,), generator=gen, device="cuda")
+                data.append((x, x[:, idx].contiguous()))
+            torch.cuda.synchronize()
+            done = serve.run_poisson(eng, data, rate, seed=rate)
+            ok = all(r.status == 0 for r in done)
+            st = serve.latency_stats(done[warm:])
+            st["all_ok"] = ok
+            st["mean_batch"] = float(np.mean(eng.batch_sizes)) if eng.batch_sizes else 0.0
+            eng.batch_sizes.clear()
+            out[str(rate)] = st
+            del data, done
+            torch.cuda.empty_cache()
+    finally:
+        eng.close()
+    return {"rates_per_s": out, "workers": workers,
+            "workload": "Poisson arrivals; n log-uniform [2^12, 2^22], d in {3,16}, Gaussian "
+                        "mixture, S=64, leaf 64, EXACT; 1,024 lookups per request; cap 64 GB"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +164,8 @@ def main():
     ap.add_argument("--rule", default="exact", choices=sorted(RULES))
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the build does not shard across GPUs); "
@@ -138,6 +237,14 @@ def main():
     b_alg = 8 * d + 12
     level_gbps = b_alg * pl / (ms * 1e-3) / 1e9
 
+    batched = serving = None
+    if not args.no_batched:
+        log("[bench] batched vs plain (512 trees)")
+        batched = bench_batched()
+    if not args.no_serving:
+        log("[bench] serving")
+        serving = bench_serving()
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline on {args.cpu_sample} points")
@@ -155,6 +262,7 @@ def main():
         "whole_build_alg_GBps": round(level_gbps, 1),
         "whole_build_alg_frac": round(level_gbps / HBM_PEAK_GBPS, 4),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
+        "batched": batched, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -587,3 +587,33 @@ uint32_t kdo_query_leaf(const int32_t *node_child, const uint32_t *node_dim,
     }
     return node_leaf[node];
 }
+
+/* ------------------------------------------------------------------ */
+/* Checks of a large tree built elsewhere, for sizes where rebuilding it */
+/* here is too slow.  Counts violations of the partition property:     */
+/* for every internal node, every point of the left child has key <=   */
+/* split and every point of the right child has key > split on the     */
+/* node's coordinate.  perm == NULL reads pts in position order (pts    */
+/* then holds the points already permuted, [d][ld]).                     */
+/* ------------------------------------------------------------------ */
+uint64_t kdo_check_partition(const float *pts, uint32_t d, uint64_t ld, const uint32_t *perm,
+                             uint64_t num_nodes, const uint32_t *node_begin,
+                             const uint32_t *node_end, const int32_t *node_child,
+                             const uint32_t *node_dim, const uint32_t *node_split)
+{
+    uint64_t bad = 0;
+    for (uint64_t k = 0; k < num_nodes; k++) {
+        if (node_child[k] < 0) continue;
+        uint32_t t = node_dim[k];
+        if (t >= d) { bad++; continue; }
+        uint32_t lc = (uint32_t)node_child[k];
+        uint32_t mid = node_end[lc];
+        for (uint64_t i = node_begin[k]; i < node_end[k]; i++) {
+            uint64_t j = perm ? perm[i] : i;
+            uint32_t u = kdo_key_of_bits(bits_of_float(pts[t * ld + j]));
+            int left = i < mid;
+            if (left != (u <= node_split[k])) bad++;
+        }
+    }
+    return bad;
+}

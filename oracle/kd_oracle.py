@@ -87,6 +87,8 @@ def lib():
                                      ctypes.POINTER(u32)]
         L.kdo_build.restype = ctypes.c_int
         L.kdo_build.argtypes = [vp, u64, u32, u64, ctypes.POINTER(Params)] + [vp] * 10
+        L.kdo_check_partition.restype = u64
+        L.kdo_check_partition.argtypes = [vp, u32, u64, vp, u64, vp, vp, vp, vp, vp]
         L.kdo_query_leaf.restype = u32
         L.kdo_query_leaf.argtypes = [vp, vp, vp, vp, vp, u64]
         _lib = L
@@ -275,3 +277,17 @@ def query_leaf(tree, queries):
         out[i] = L.kdo_query_leaf(_ptr(nc), _ptr(nd), _ptr(ns), _ptr(nl),
                                   ctypes.c_void_p(base + 4 * i), nq)
     return out
+
+
+def check_partition(points, tree, permuted=False):
+    """Number of points on the wrong side of their node's split (0 = valid).
+    permuted=True: points are already in the tree's position order."""
+    p = np.ascontiguousarray(points, dtype=np.float32)
+    d, n = p.shape
+    arr = {k: np.ascontiguousarray(tree[k], dtype=np.int32 if k == "node_child" else np.uint32)
+           for k in ("node_begin", "node_end", "node_child", "node_dim", "node_split")}
+    perm = None if permuted else np.ascontiguousarray(tree["perm"], dtype=np.uint32)
+    return lib().kdo_check_partition(_ptr(p), d, n, _ptr(perm), arr["node_begin"].size,
+                                     _ptr(arr["node_begin"]), _ptr(arr["node_end"]),
+                                     _ptr(arr["node_child"]), _ptr(arr["node_dim"]),
+                                     _ptr(arr["node_split"]))

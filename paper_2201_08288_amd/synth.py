@@ -29,24 +29,36 @@ def uniform24(n, d, seed=BASE_SEED, stream=0):
     return (k.astype(np.float32) * np.float32(2.0 ** -24)).astype(np.float32)
 
 
+def _columns(d, fn, workers=16):
+    """Run fn(c) for every column c in parallel threads (numpy's generators
+    release the GIL); each column has its own seeded stream."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(workers, d)) as ex:
+        list(ex.map(fn, range(d)))
+
+
 def gmm(n, d, seed=BASE_SEED, stream=0, components=10, box=5.0, sigma=0.5):
     rng = rng_for(seed, 2, stream)
     means = rng.uniform(-box, box, size=(components, d))
     comp = rng.integers(0, components, size=n)
     out = np.empty((d, n), dtype=np.float32)
-    for c in range(d):
-        z = rng.standard_normal(n, dtype=np.float32).astype(np.float64)
+
+    def col(c):
+        z = rng_for(seed, 2, stream, 1 + c).standard_normal(n, dtype=np.float32).astype(np.float64)
         out[c] = (means[comp, c] + sigma * z).astype(np.float32)
+
+    _columns(d, col)
     return out
 
 
 def student_t_grid(n, d, seed=BASE_SEED, stream=0, nu=3.0, grid_bits=10, clamp_log2=13):
-    rng = rng_for(seed, 3, stream)
     out = np.empty((d, n), dtype=np.float32)
     lim = np.float32(2.0 ** clamp_log2 - 2.0 ** -grid_bits)
     scale = np.float32(2.0 ** grid_bits)
     chunk = 1 << 22
-    for c in range(d):
+
+    def col(c):
+        rng = rng_for(seed, 3, stream, 1 + c)
         for s in range(0, n, chunk):
             m = min(chunk, n - s)
             z = rng.standard_normal(m, dtype=np.float32)
@@ -54,6 +66,8 @@ def student_t_grid(n, d, seed=BASE_SEED, stream=0, nu=3.0, grid_bits=10, clamp_l
             x = z / np.sqrt(np.maximum(g, np.float32(1e-30)))
             x = np.rint(x * scale) / scale
             out[c, s:s + m] = np.clip(x, -lim, lim)
+
+    _columns(d, col)
     return out
 
 

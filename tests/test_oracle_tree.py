@@ -186,3 +186,50 @@ def test_paper_accuracy_panel_fourier_J15():
     assert t["num_leaves"] == 2 ** g["depth"]
     rel = np.diff(t["leaf_offsets"].astype(np.int64)) / (n / 2 ** g["depth"])
     assert rel.min() >= lo_rel and rel.max() <= hi_rel, (rel.min(), rel.max())
+
+
+def test_partition_checker_detects_wrong_split():
+    from paper_2201_08288_amd import synth
+    x = synth.gmm(5000, 3, seed=11)
+    t = oracle.build_tree(x, leaf_size=8)
+    assert oracle.check_partition(x, t) == 0
+    assert oracle.check_partition(x[:, t["perm"]], t, permuted=True) == 0
+    internal = np.nonzero(t["node_child"] >= 0)[0]
+    bad = dict(t)
+    bad["node_split"] = t["node_split"].copy()
+    k = internal[0]
+    # move the root split below its left child's largest key
+    keys = oracle.keys_of_floats(x[t["node_dim"][k], t["perm"][t["node_begin"][k]:t["node_end"][t["node_child"][k]]]])
+    bad["node_split"][k] = np.uint32(int(keys.max()) - 1)
+    assert oracle.check_partition(x, bad) > 0
+    swapped = dict(t)
+    swapped["perm"] = t["perm"].copy()
+    mid = t["node_end"][t["node_child"][k]]
+    swapped["perm"][[0, mid]] = swapped["perm"][[mid, 0]]
+    assert oracle.check_partition(x, swapped) > 0
+
+
+@pytest.mark.parametrize("rule,key,pool", [(0, 0, False), (2, 1, True), (1, 1, False),
+                                           (2, 0, False)])
+def test_sampled_node_recompute_matches_whole_build(rule, key, pool):
+    """Recomputing each node's split from its own points (ascending original
+    index, depth, rank among its level's cells) reproduces the whole build;
+    this is the check used on trees too large to rebuild."""
+    from paper_2201_08288_amd import synth
+    from tests.gpu_common import check_sampled_nodes
+    x = synth.student_t_grid(6000, 4, seed=3 + rule)
+    S = 8
+    pl = synth.dirichlet_pool(32, S, seed=5) if pool else None
+    kw = dict(num_subsets=S, key_rule=key, split_rule=rule, pool=pl, seed=9)
+    t = oracle.build_tree(x, leaf_size=16, **kw)
+    shift = oracle.maxvar_shift(x) if key == 1 else 0
+    n = check_sampled_nodes(x, t, range(t["num_nodes"]), 16, shift=shift, **kw)
+    assert n > 100
+    # a wrong rank must be caught by the pool rule
+    if pool:
+        t2 = dict(t)
+        t2["node_split"] = t["node_split"].copy()
+        k = np.nonzero(t["node_child"] >= 0)[0][5]
+        t2["node_split"][k] ^= np.uint32(1 << 20)
+        with pytest.raises(AssertionError):
+            check_sampled_nodes(x, t2, [k], 16, shift=shift, **kw)
