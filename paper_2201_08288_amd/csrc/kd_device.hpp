@@ -36,7 +36,7 @@ struct Cell {
     uint32_t big;         // index among the level's large cells, NONE if small
     uint32_t slot;        // max-variance statistics slot (parent-local index * 2 + side)
     uint32_t tree;
-    uint32_t pad;
+    uint32_t voff;        // small cells: points of the level's earlier small cells
 };
 
 // Per-cell state and result of one level.
@@ -100,7 +100,7 @@ struct TreeState {
 // Totals of the level about to run (read back by the host).
 struct LevelInfo {
     uint32_t num_cells, num_tiles, points, big_points;
-    uint32_t num_big, mid_cells, pad[2];  // mid: small cells above the wave-kernel size
+    uint32_t num_big, pad[3];
 };
 
 // Pointers read from device-side descriptors are generic; accesses through

@@ -40,12 +40,11 @@ static_assert(2 * FCHUNK <= NT, "moment chunk fits one workgroup");
 
 namespace {
 
-constexpr int EMIT_COUNTERS = 9;
+constexpr int EMIT_COUNTERS = 8;
 constexpr int EMIT_STRIDE = 12;
 constexpr uint32_t WAVE_CELL_MAX = 1024;  // small cells up to this size: one wave per cell
 // emit counters: splits, active children, tiles, points, large-cell points,
-// large cells, points of split cells, unsplittable cells, small cells above
-// WAVE_CELL_MAX
+// large cells, points of split cells, unsplittable cells
 
 struct Ctx {
     TreeDesc *trees;
@@ -64,6 +63,7 @@ struct Ctx {
     uint32_t *med;
     uint32_t *pre;
     uint32_t *scan_tmp;
+    uint32_t *bucket_first;  // small cells: first cell of each bucket of TILE numbers
     LevelInfo *info;
     const uint32_t *pool;
     uint32_t pool_entries;
@@ -154,13 +154,22 @@ __global__ __launch_bounds__(NT) void k_ingest(Ctx c) {
     }
 }
 
+// Small cell `slot` holds the level's small-point numbers [voff, voff + n):
+// for every bucket boundary b * TILE in (voff, voff + n], the first cell that
+// starts at or after it is at slot + 1 or later.
+__device__ __forceinline__ void mark_buckets(const Ctx &c, uint32_t voff, uint32_t n,
+                                             uint32_t slot) {
+    for (uint32_t b = voff / TILE + 1; uint64_t(b) * TILE <= uint64_t(voff) + n; b++)
+        c.bucket_first[b] = slot + 1;
+}
+
 // Root cells of all trees whose root is split (one workgroup).
 __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
     __shared__ uint32_t sh[NW + 1];
-    uint32_t base[6] = {0, 0, 0, 0, 0, 0};  // cells, tiles, points, big points, big cells, mid
+    uint32_t base[5] = {0, 0, 0, 0, 0};  // cells, tiles, points, big points, big cells
     for (uint32_t t0 = 0; t0 < c.ntrees; t0 += NT) {
         const uint32_t t = t0 + threadIdx.x;
-        uint32_t v[6] = {0, 0, 0, 0, 0, 0};
+        uint32_t v[5] = {0, 0, 0, 0, 0};
         uint32_t n = 0;
         if (t < c.ntrees) {
             n = c.trees[t].n;
@@ -172,11 +181,10 @@ __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
                 v[2] = n;
                 v[3] = big ? n : 0u;
                 v[4] = big ? 1u : 0u;
-                v[5] = (!big && n > WAVE_CELL_MAX) ? 1u : 0u;
             }
         }
-        uint32_t pre[6];
-        for (int k = 0; k < 6; k++) {
+        uint32_t pre[5];
+        for (int k = 0; k < 5; k++) {
             uint32_t tot;
             pre[k] = base[k] + block_excl_scan(v[k], sh, &tot);
             base[k] += tot;
@@ -186,9 +194,11 @@ __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
             S.first[0] = pre[0];
             S.count[0] = v[0];
             if (v[0]) {
-                Cell cl{0u, n, 0u, pre[1], v[4] ? pre[4] : NONE, 0u, t, 0u};
+                const uint32_t voff = pre[2] - pre[3];
+                Cell cl{0u, n, 0u, pre[1], v[4] ? pre[4] : NONE, 0u, t, voff};
                 c.cells[0][pre[0]] = cl;
                 if (v[4]) c.big_list[pre[4]] = pre[0];
+                else mark_buckets(c, voff, n, pre[0]);
             }
         }
     }
@@ -199,8 +209,8 @@ __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
         in.points = base[2];
         in.big_points = base[3];
         in.num_big = base[4];
-        in.mid_cells = base[5];
         *c.info = in;
+        c.bucket_first[0] = 0;
     }
 }
 
@@ -849,340 +859,464 @@ __global__ __launch_bounds__(NT) void k_big_scatter(Ctx c, uint32_t level, uint3
     }
 }
 
-// Small cells: the whole level step of one cell in one workgroup.
+// ------------------------------------------------------------ small cells
+//
+// Cells of at most SMALL_MAX points.  Each small cell carries voff, the
+// number of points in the level's earlier small cells, so the level's small
+// points are numbered 0, 1, ... in cell order.  Those numbers are cut into
+// buckets of TILE; a workgroup takes the cells that start in its bucket and
+// works through them in chunks of whole cells of one tree (at most TILE points
+// and SCELLS cells), doing the whole level step of a chunk on chip: keys staged
+// in LDS, the split of every cell (one wave per cell up to WAVE_CELL_MAX
+// points, otherwise the workgroup), ranks from one chunk-wide scan, then every
+// column and the permutation permuted through LDS.  A chunk's cells hold the
+// same positions before and after the step, so each column is read and written
+// over the same position ranges, with coalesced accesses.
 
-template <int RULE, bool MAXVAR>
-__global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t ncells,
-                                              uint32_t skip_le) {
-    __shared__ uint32_t keys[SMALL_MAX + SMALL_MAX / 32];
-    __shared__ uint32_t stage[SMALL_MAX];
-    __shared__ uint32_t h[NW][NBINS];
-    __shared__ uint32_t sh[2 * NW + 1], s3[4];
-    __shared__ unsigned long long sh64[NW * 2 * FCHUNK];
-    __shared__ long long mom[2 * FOURIER_JMAX];
-    extern __shared__ uint32_t dyn[];  // SUBSET: bounds[S + 1], medians[S]
-    const uint32_t cur = level & 1;
-    const int J = int(c.J);
-    for (uint32_t ci = blockIdx.x; ci < ncells; ci += gridDim.x) {
-        const Cell cl = c.cells[cur][ci];
-        if (cl.big != NONE || cl.end - cl.begin <= skip_le) continue;
-        const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
-        const uint32_t n_c = cl.end - cl.begin;
-        const uint32_t li = ci - c.ts[cl.tree].first[cur];
-        CellRes r = c.res[ci];
-        const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n + cl.begin);
-        for (uint32_t i = threadIdx.x; i < n_c; i += NT) keys[px(i)] = key_of_bits(col[i]);
-        __syncthreads();
-        uint32_t m = 0, lt = 0, le = 0;
-        bool counted = false;
-        if (RULE == KD_SPLIT_EXACT) {
-            const SelectResult sel =
-                block_select([&](uint32_t i) { return keys[px(i)]; }, n_c, r.rank, h[0], sh, s3);
-            m = sel.key;
-            lt = sel.lt;
-            le = sel.le;
-            counted = true;
-        } else if (RULE == KD_SPLIT_FOURIER) {
-            uint32_t mn = NONE, mx = 0;
-            for (uint32_t i = threadIdx.x; i < n_c; i += NT) {
-                mn = min(mn, keys[px(i)]);
-                mx = max(mx, keys[px(i)]);
-            }
-            block_minmax(mn, mx, sh);
-            m = mn;
-            if (mn != mx) {
-                const int e = fourier_exponent(mn, mx);
-                const double xmin = value_of_key(mn), scale = fourier_scale(e);
-                for (int j0 = 0; j0 < J; j0 += FCHUNK) {
-                    long long acc[2 * FCHUNK];
+constexpr int SCELLS = 128;  // cells per chunk (chunk-local cell ids fit a byte)
+
+struct ChunkLds {
+    uint32_t ci[SCELLS];         // cell index in the level list
+    uint32_t start[SCELLS + 1];  // chunk-local number of the cell's first point
+    uint32_t off[SCELLS];        // position minus chunk-local number
+    uint32_t dim[SCELLS];
+    uint32_t li[SCELLS];         // index in the tree's level list
+    uint32_t split[SCELLS], nl[SCELLS], flags[SCELLS], base[SCELLS];
+    uint32_t wide[4];            // cells above WAVE_CELL_MAX points (at most 3)
+    uint32_t count, total, tree, next, nwide;
+};
+
+// Wave 0: collect the next chunk, starting at cell `pos`, from the cells that
+// start before number v1.  Big cells are skipped; a chunk stops at the first
+// cell of another tree, at SCELLS cells, and before a cell that runs past v1
+// (such a cell, the bucket's last, forms a chunk of its own).
+__device__ void form_chunk(const Ctx &c, uint32_t cur, uint32_t ncells, uint32_t pos,
+                           uint32_t v1, ChunkLds &C) {
+    const int l = lane();
+    uint32_t count = 0, total = 0, tree = NONE, first = 0, nwide = 0;
+    for (;;) {
+        const uint32_t ci = pos + l;
+        const bool valid = ci < ncells;
+        Cell cl{};
+        if (valid) cl = c.cells[cur][ci];
+        const bool small = valid && cl.big == NONE;
+        const uint32_t nk = cl.end - cl.begin;
+        const bool beyond = !valid || (small && cl.voff >= v1);
+        const unsigned long long bmask = __ballot(beyond);
+        const int fb = bmask ? __builtin_ctzll(bmask) : WAVE;
+        const unsigned long long below_fb = fb == WAVE ? ~0ull : ((1ull << fb) - 1);
+        const unsigned long long smask = __ballot(small) & below_fb;
+        if (tree == NONE && smask) {
+            tree = __shfl(cl.tree, __builtin_ctzll(smask), WAVE);
+            first = c.ts[tree].first[cur];
+        }
+        const uint32_t before =
+            count + uint32_t(__popcll(smask & ((1ull << l) - 1)));  // small cells before lane l
+        const bool cross = small && !beyond && uint64_t(cl.voff) + nk > v1;
+        const bool stop =
+            beyond || (small && (cl.tree != tree || before >= uint32_t(SCELLS) || (cross && before > 0)));
+        const unsigned long long stmask = __ballot(stop);
+        const int s = stmask ? __builtin_ctzll(stmask) : WAVE;
+        const bool take = small && l < s;
+        const uint32_t sz = take ? nk : 0u;
+        const uint32_t incl = wave_incl_scan(sz);
+        if (take) {
+            const uint32_t k = before, st = total + incl - sz;
+            C.ci[k] = ci;
+            C.start[k] = st;
+            C.off[k] = cl.begin - st;
+            C.dim[k] = c.res[ci].dim;
+            C.li[k] = ci - first;
+        }
+        const unsigned long long wmask = __ballot(take && nk > WAVE_CELL_MAX);
+        if (take && nk > WAVE_CELL_MAX) C.wide[nwide + __popcll(wmask & ((1ull << l) - 1))] = before;
+        nwide += uint32_t(__popcll(wmask));
+        count += uint32_t(__popcll(__ballot(take)));
+        total += __shfl(incl, WAVE - 1, WAVE);
+        pos += uint32_t(s);
+        if (s < WAVE) break;
+    }
+    if (l == 0) {
+        C.count = count;
+        C.total = total;
+        C.tree = tree;
+        C.next = pos;
+        C.nwide = nwide;
+        C.start[count] = total;
+    }
+}
+
+// Split of one chunk cell from its candidate and counts; the result goes to
+// the level's cell results and to the chunk table.
+__device__ __forceinline__ void store_cell(const Ctx &c, uint32_t level, ChunkLds &C, uint32_t k,
+                                           uint32_t m, uint32_t lt, uint32_t le) {
+    const uint32_t n_c = C.start[k + 1] - C.start[k];
+    CellRes r{};
+    r.dim = C.dim[k];
+    r.rank = (n_c - 1) / 2;
+    finish_cell(c, level, n_c, r, m, lt, le);
+    r.lt = lt;
+    r.le = le;
+    c.res[C.ci[k]] = r;
+    C.split[k] = r.split;
+    C.nl[k] = r.nl;
+    C.flags[k] = r.flags;
+}
+
+// Candidate of a cell of at most WAVE_CELL_MAX points by one wave (EXACT,
+// FOURIER); keys at keys[px(s0 + i)], i < nk.
+template <int RULE>
+__device__ void wave_candidate(const Ctx &c, const uint32_t *keys, uint32_t s0, uint32_t nk,
+                               uint32_t *h, long long *mom, uint32_t &m, uint32_t &lt,
+                               uint32_t &le) {
+    const int l = lane();
+    if (RULE == KD_SPLIT_EXACT) {
+        m = wave_select(keys, s0, nk, (nk - 1) / 2, h);
+    } else {
+        uint32_t mn = NONE, mx = 0;
+        for (uint32_t i = l; i < nk; i += WAVE) {
+            const uint32_t u = keys[px(s0 + i)];
+            mn = min(mn, u);
+            mx = max(mx, u);
+        }
+        mn = wave_min(mn);
+        mx = wave_max(mx);
+        m = mn;
+        if (mn != mx) {
+            const int J = int(c.J);
+            const int e = fourier_exponent(mn, mx);
+            const double xmin = value_of_key(mn), scale = fourier_scale(e);
+            for (int j0 = 0; j0 < J; j0 += FCHUNK) {
+                long long acc[2 * FCHUNK];
 #pragma unroll
-                    for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
-                    for (uint32_t i = threadIdx.x; i < n_c; i += NT)
-                        fourier_terms(keys[px(i)], xmin, scale, J, j0, c.trig, acc);
-                    reduce_moments(acc, sh64, j0, J, mom, false);
+                for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
+                for (uint32_t i = l; i < nk; i += WAVE)
+                    fourier_terms(keys[px(s0 + i)], xmin, scale, J, j0, c.trig, acc);
+#pragma unroll
+                for (int k = 0; k < 2 * FCHUNK; k++) {
+                    const long long sum = (long long)wave_sum64((unsigned long long)acc[k]);
+                    const int j = j0 + (k % FCHUNK);
+                    if (l == k && j < J) mom[(k < FCHUNK ? 0 : FOURIER_JMAX) + j] = sum;
                 }
-                if (wave() == 0) {
-                    const uint32_t mm = fourier_solve_wave(mom, mom + FOURIER_JMAX, J, mn, mx, e,
-                                                           c.trig);
-                    if (lane() == 0) s3[0] = mm;
-                }
-                __syncthreads();
-                m = s3[0];
-                __syncthreads();
             }
-        } else {
-            uint32_t *B = dyn, *med = dyn + c.S + 1;
-            if (threadIdx.x == 0) subset_bounds(c, n_c, level, li, B);
-            __syncthreads();
-            for (uint32_t s = wave(); s < c.S; s += NW) {
-                const uint32_t ns = B[s + 1] - B[s];
-                uint32_t v = NONE;
-                if (ns > 0) v = wave_select(keys, B[s], ns, (ns - 1) / 2, h[wave()]);
-                if (lane() == 0) med[s] = v;
+            wave_sync();
+            m = fourier_solve_wave(mom, mom + FOURIER_JMAX, J, mn, mx, e, c.trig);
+            wave_sync();
+        }
+    }
+    uint32_t a = 0, b = 0;
+    for (uint32_t i = l; i < nk; i += WAVE) {
+        const uint32_t u = keys[px(s0 + i)];
+        a += u < m;
+        b += u <= m;
+    }
+    lt = uint32_t(wave_sum64(a));
+    le = uint32_t(wave_sum64(b));
+}
+
+// Candidate of one cell by the whole workgroup (every rule).
+template <int RULE>
+__device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *keys, uint32_t s0,
+                                uint32_t nk, uint32_t li, uint32_t (*h)[NBINS], uint32_t *sh,
+                                uint32_t *s3, unsigned long long *sh64, long long *mom,
+                                uint32_t *dyn, uint32_t &m, uint32_t &lt, uint32_t &le) {
+    if (RULE == KD_SPLIT_EXACT) {
+        const SelectResult sel = block_select([&](uint32_t i) { return keys[px(s0 + i)]; }, nk,
+                                              (nk - 1) / 2, h[0], sh, s3);
+        m = sel.key;
+        lt = sel.lt;
+        le = sel.le;
+        return;
+    }
+    if (RULE == KD_SPLIT_FOURIER) {
+        uint32_t mn = NONE, mx = 0;
+        for (uint32_t i = threadIdx.x; i < nk; i += NT) {
+            const uint32_t u = keys[px(s0 + i)];
+            mn = min(mn, u);
+            mx = max(mx, u);
+        }
+        block_minmax(mn, mx, sh);
+        m = mn;
+        if (mn != mx) {
+            const int J = int(c.J);
+            const int e = fourier_exponent(mn, mx);
+            const double xmin = value_of_key(mn), scale = fourier_scale(e);
+            for (int j0 = 0; j0 < J; j0 += FCHUNK) {
+                long long acc[2 * FCHUNK];
+#pragma unroll
+                for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
+                for (uint32_t i = threadIdx.x; i < nk; i += NT)
+                    fourier_terms(keys[px(s0 + i)], xmin, scale, J, j0, c.trig, acc);
+                reduce_moments(acc, sh64, j0, J, mom, false);
             }
-            __syncthreads();
-            if (threadIdx.x == 0) s3[0] = subset_mean(B, med, c.S, n_c);
+            if (wave() == 0) {
+                const uint32_t mm = fourier_solve_wave(mom, mom + FOURIER_JMAX, J, mn, mx, e,
+                                                       c.trig);
+                if (lane() == 0) s3[0] = mm;
+            }
             __syncthreads();
             m = s3[0];
             __syncthreads();
         }
-        if (!counted) {
-            unsigned long long cnt2[2] = {0, 0};
-            for (uint32_t i = threadIdx.x; i < n_c; i += NT) {
-                cnt2[0] += keys[px(i)] < m;
-                cnt2[1] += keys[px(i)] <= m;
-            }
-            block_sum64n<2>(cnt2, sh64);
-            lt = uint32_t(cnt2[0]);
-            le = uint32_t(cnt2[1]);
-        }
-        finish_cell(c, level, n_c, r, m, lt, le);
-        // ranks: thread t owns E consecutive positions
-        const uint32_t E = (n_c + NT - 1) / NT;
-        const uint32_t i0 = min(threadIdx.x * E, n_c), i1 = min(i0 + E, n_c);
-        if (r.flags & RES_SPLIT) {
-            uint32_t nleft = 0;
-            for (uint32_t i = i0; i < i1; i++) nleft += keys[px(i)] <= r.split;
-            uint32_t tot;
-            const uint32_t lpre = block_excl_scan(nleft, sh, &tot);
-            uint32_t lo = lpre, ro = r.nl + (i0 - lpre);
-            for (uint32_t i = i0; i < i1; i++) keys[px(i)] = keys[px(i)] <= r.split ? lo++ : ro++;
-        } else {
-            for (uint32_t i = i0; i < i1; i++) keys[px(i)] = i;
+    } else {
+        uint32_t *B = dyn, *med = dyn + c.S + 1;
+        if (threadIdx.x == 0) subset_bounds(c, nk, level, li, B);
+        __syncthreads();
+        for (uint32_t s = wave(); s < c.S; s += NW) {
+            const uint32_t ns = B[s + 1] - B[s];
+            uint32_t v = NONE;
+            if (ns > 0) v = wave_select(keys, s0 + B[s], ns, (ns - 1) / 2, h[wave()]);
+            if (lane() == 0) med[s] = v;
         }
         __syncthreads();
-        // a7: permute G columns at a time through LDS (stage index g * n_c + rank),
-        // then write each column's cell range contiguously: [0, nl) to the left
-        // child, [nl, n_c) to the right child.
-        {
-            const bool lleaf = r.flags & RES_LEFT_LEAF, rleaf = r.flags & RES_RIGHT_LEAF;
-            const bool stats = MAXVAR && (r.flags & RES_SPLIT) && !(lleaf && rleaf);
-            const int shift = MAXVAR ? maxvar_shift(c.ts[cl.tree].maxabs) : 0;
-            const uint32_t d = T.d, n = T.n, nxt = cur ^ 1;
-            const uint32_t G = MAXVAR ? 1u : min(d + 1, max(1u, uint32_t(SMALL_MAX) / n_c));
-            const uint32_t dk = NT / n_c, de = NT % n_c;
-            for (uint32_t k0 = 0; k0 <= d; k0 += G) {
-                const uint32_t g_end = min(G, d + 1 - k0), items = g_end * n_c;
-                uint32_t g = threadIdx.x / n_c, e = threadIdx.x % n_c;
-#pragma unroll
-                for (int j = 0; j < PER_THREAD; j++) {
-                    const uint32_t it = j * NT + threadIdx.x;
-                    if (it < items) {
-                        const uint32_t k = k0 + g;
-                        const KD_GLOBAL uint32_t *src =
-                            gp(k == d ? T.perm[cur] : T.cols[cur] + uint64_t(k) * n);
-                        stage[g * n_c + keys[px(e)]] = src[cl.begin + e];
-                    }
-                    e += de;
-                    g += dk;
-                    if (e >= n_c) {
-                        e -= n_c;
-                        g++;
-                    }
-                }
-                __syncthreads();
-                unsigned long long acc[6] = {0, 0, 0, 0, 0, 0};
-                for (uint32_t gg = 0; gg < g_end; gg++) {
-                    const uint32_t k = k0 + gg;
-                    const uint32_t *sg = stage + gg * n_c;
-                    KD_GLOBAL uint32_t *next =
-                        gp(k == d ? T.perm[nxt] : T.cols[nxt] + uint64_t(k) * n) + cl.begin;
-                    KD_GLOBAL uint32_t *out =
-                        k == d ? gp(T.out_perm) + cl.begin
-                               : (T.pts_out ? gp(T.pts_out + uint64_t(k) * n) + cl.begin : nullptr);
-                    KD_GLOBAL uint32_t *ldst = lleaf ? out : next;
-                    KD_GLOBAL uint32_t *rdst = rleaf ? out : next;
-                    for (uint32_t i = threadIdx.x; i < r.nl; i += NT) {
-                        const uint32_t val = sg[i];
-                        if (ldst) ldst[i] = val;
-                        if (stats && k < d && !lleaf) add_stats(acc, val, shift, false);
-                    }
-                    for (uint32_t i = r.nl + threadIdx.x; i < n_c; i += NT) {
-                        const uint32_t val = sg[i];
-                        if (rdst) rdst[i] = val;
-                        if (stats && k < d && !rleaf) add_stats(acc, val, shift, true);
-                    }
-                }
-                if (stats && k0 < d) flush_stats(T, nxt, li, k0, acc, lleaf, rleaf, sh64, false);
-                __syncthreads();
-            }
-        }
-        if (threadIdx.x == 0) c.res[ci] = r;
+        if (threadIdx.x == 0) s3[0] = subset_mean(B, med, c.S, nk);
+        __syncthreads();
+        m = s3[0];
         __syncthreads();
     }
+    unsigned long long cnt2[2] = {0, 0};
+    for (uint32_t i = threadIdx.x; i < nk; i += NT) {
+        const uint32_t u = keys[px(s0 + i)];
+        cnt2[0] += u < m;
+        cnt2[1] += u <= m;
+    }
+    block_sum64n<2>(cnt2, sh64);
+    lt = uint32_t(cnt2[0]);
+    le = uint32_t(cnt2[1]);
 }
 
-// Small cells of at most WMAX points: one wave64 per cell, four cells per
-// workgroup, wave-level select, ranks and staged scatter (no workgroup
-// barriers).  Same results as k_small.
-constexpr int WMAX = int(WAVE_CELL_MAX);
-constexpr int WPAD = WMAX + WMAX / 32;
-constexpr int WPER = WMAX / WAVE;  // positions per lane
-
 template <int RULE, bool MAXVAR>
-__global__ __launch_bounds__(NT) void k_small_wave(Ctx c, uint32_t level, uint32_t ncells) {
-    __shared__ uint32_t keys_all[NW][WPAD];
-    __shared__ uint32_t stage_all[NW][WMAX];
-    __shared__ uint32_t h_all[NW][NBINS];
-    __shared__ long long mom_all[NW][RULE == KD_SPLIT_FOURIER ? 2 * FOURIER_JMAX : 1];
-    extern __shared__ uint32_t dyn[];  // SUBSET: per wave bounds[S + 1], medians[S]
+__global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t ncells,
+                                              uint32_t nbuckets) {
+    __shared__ uint32_t keys[PADDED];  // staged keys, then each number's destination
+    __shared__ __attribute__((aligned(16))) uint32_t stage[TILE];
+    __shared__ __attribute__((aligned(16))) uint8_t seg[TILE];  // chunk cell of each number
+    __shared__ ChunkLds C;
+    __shared__ uint32_t h[NW][NBINS];
+    __shared__ uint32_t sh[2 * NW + 1], s3[4];
+    __shared__ unsigned long long sh64[NW * 2 * FCHUNK];
+    __shared__ long long mom[NW][RULE == KD_SPLIT_FOURIER ? 2 * FOURIER_JMAX : 1];
+    __shared__ unsigned long long acc[MAXVAR ? 2 * SCELLS * 3 : 1];
+    extern __shared__ uint32_t dyn[];  // SUBSET: bounds[S + 1], medians[S]
     const uint32_t cur = level & 1, nxt = cur ^ 1;
     const int w = wave(), l = lane();
-    uint32_t *keys = keys_all[w], *stage = stage_all[w], *h = h_all[w];
-    const int J = int(c.J);
-    for (uint32_t cw = blockIdx.x * NW + w; cw < ncells; cw += gridDim.x * NW) {
-        const uint32_t ci = __builtin_amdgcn_readfirstlane(cw);
-        const Cell cl = c.cells[cur][ci];
-        const uint32_t n_c = cl.end - cl.begin;
-        if (cl.big != NONE || n_c > uint32_t(WMAX)) continue;
-        const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
-        const uint32_t li = ci - c.ts[cl.tree].first[cur];
-        CellRes r = c.res[ci];
-        {
-            const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n + cl.begin);
-            uint32_t u[WPER];
+    for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
+        uint32_t pos = c.bucket_first[b];
+        const uint32_t v1 = (b + 1) * uint32_t(TILE);
+        for (;;) {
+            if (w == 0) form_chunk(c, cur, ncells, pos, v1, C);
+            __syncthreads();
+            const uint32_t K = C.count, tot = C.total;
+            pos = C.next;
+            const uint32_t tr = __builtin_amdgcn_readfirstlane(C.tree);
+            __syncthreads();
+            if (K == 0) break;
+            const KD_CONST TreeDesc &T = cref(&c.trees[tr]);
+            const uint32_t d = T.d, n = T.n;
+            for (uint32_t k = w; k < K; k += NW)
+                for (uint32_t e = C.start[k] + l; e < C.start[k + 1]; e += WAVE) seg[e] = uint8_t(k);
+            if (MAXVAR)
+                for (uint32_t i = threadIdx.x; i < 6 * K; i += NT) acc[i] = 0;
+            __syncthreads();
+            // keys of the chunk (EXACT: the first column is requested at the same
+            // time and arrives while the cells are split)
+            uint32_t vn[PER_THREAD];
+            {
+                uint32_t u[PER_THREAD], p[PER_THREAD];
 #pragma unroll
-            for (int j = 0; j < WPER; j++) {
-                const uint32_t i = j * WAVE + l;
-                u[j] = i < n_c ? key_of_bits(col[i]) : 0u;
-            }
-#pragma unroll
-            for (int j = 0; j < WPER; j++) {
-                const uint32_t i = j * WAVE + l;
-                if (i < n_c) keys[px(i)] = u[j];
-            }
-        }
-        wave_sync();
-        uint32_t m;
-        if (RULE == KD_SPLIT_EXACT) {
-            m = wave_select(keys, 0, n_c, r.rank, h);
-        } else if (RULE == KD_SPLIT_FOURIER) {
-            uint32_t mn = NONE, mx = 0;
-            for (uint32_t i = l; i < n_c; i += WAVE) {
-                mn = min(mn, keys[px(i)]);
-                mx = max(mx, keys[px(i)]);
-            }
-            mn = wave_min(mn);
-            mx = wave_max(mx);
-            m = mn;
-            if (mn != mx) {
-                const int e = fourier_exponent(mn, mx);
-                const double xmin = value_of_key(mn), scale = fourier_scale(e);
-                long long *mom = mom_all[w];
-                for (int j0 = 0; j0 < J; j0 += FCHUNK) {
-                    long long acc[2 * FCHUNK];
-#pragma unroll
-                    for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
-                    for (uint32_t i = l; i < n_c; i += WAVE)
-                        fourier_terms(keys[px(i)], xmin, scale, J, j0, c.trig, acc);
-#pragma unroll
-                    for (int k = 0; k < 2 * FCHUNK; k++) {
-                        const long long sum = (long long)wave_sum64((unsigned long long)acc[k]);
-                        const int j = j0 + (k % FCHUNK);
-                        if (l == k && j < J) mom[(k < FCHUNK ? 0 : FOURIER_JMAX) + j] = sum;
+                for (int j = 0; j < PER_THREAD; j++) {
+                    const uint32_t e = j * NT + threadIdx.x;
+                    u[j] = 0;
+                    vn[j] = 0;
+                    if (e < tot) {
+                        const uint32_t k = seg[e];
+                        p[j] = C.off[k] + e;
+                        u[j] = gp(T.cols[cur] + uint64_t(C.dim[k]) * n)[p[j]];
+                        if (RULE == KD_SPLIT_EXACT) vn[j] = gp(T.cols[cur])[p[j]];
                     }
                 }
-                wave_sync();
-                m = fourier_solve_wave(mom, mom + FOURIER_JMAX, J, mn, mx, e, c.trig);
-            }
-        } else {
-            uint32_t *B = dyn + w * (2 * c.S + 1), *med = B + c.S + 1;
-            if (l == 0) subset_bounds(c, n_c, level, li, B);
-            wave_sync();
-            for (uint32_t sb = 0; sb < c.S; sb++) {
-                const uint32_t ns = B[sb + 1] - B[sb];
-                uint32_t v = NONE;
-                if (ns > 0) v = wave_select(keys, B[sb], ns, (ns - 1) / 2, h);
-                if (l == 0) med[sb] = v;
-            }
-            wave_sync();
-            uint32_t mm = 0;
-            if (l == 0) mm = subset_mean(B, med, c.S, n_c);
-            m = __shfl(mm, 0, WAVE);
-        }
-        uint32_t lt = 0, le = 0;
-        for (uint32_t i = l; i < n_c; i += WAVE) {
-            const uint32_t u = keys[px(i)];
-            lt += u < m;
-            le += u <= m;
-        }
-        lt = uint32_t(wave_sum64(lt));
-        le = uint32_t(wave_sum64(le));
-        finish_cell(c, level, n_c, r, m, lt, le);
-        // ranks: lane l owns E consecutive positions
-        const uint32_t E = (n_c + WAVE - 1) / WAVE;
-        const uint32_t i0 = min(uint32_t(l) * E, n_c), i1 = min(i0 + E, n_c);
-        if (r.flags & RES_SPLIT) {
-            uint32_t nleft = 0;
-            for (uint32_t i = i0; i < i1; i++) nleft += keys[px(i)] <= r.split;
-            const uint32_t lpre = wave_incl_scan(nleft) - nleft;
-            uint32_t lo = lpre, ro = r.nl + (i0 - lpre);
-            for (uint32_t i = i0; i < i1; i++) keys[px(i)] = keys[px(i)] <= r.split ? lo++ : ro++;
-        } else {
-            for (uint32_t i = i0; i < i1; i++) keys[px(i)] = i;
-        }
-        wave_sync();
-        // a7: G columns at a time through LDS, then contiguous child runs
-        const bool lleaf = r.flags & RES_LEFT_LEAF, rleaf = r.flags & RES_RIGHT_LEAF;
-        const bool stats = MAXVAR && (r.flags & RES_SPLIT) && !(lleaf && rleaf);
-        const int shift = MAXVAR ? maxvar_shift(c.ts[cl.tree].maxabs) : 0;
-        const uint32_t d = T.d, n = T.n;
-        const uint32_t G = MAXVAR ? 1u : min(d + 1, max(1u, uint32_t(WMAX) / n_c));
-        const uint32_t dk = WAVE / n_c, de = WAVE % n_c;
-        for (uint32_t k0 = 0; k0 <= d; k0 += G) {
-            const uint32_t g_end = min(G, d + 1 - k0), items = g_end * n_c;
-            uint32_t g = l / n_c, e = l % n_c;
 #pragma unroll
-            for (int j = 0; j < WPER; j++) {
-                const uint32_t it = j * WAVE + l;
-                if (it < items) {
-                    const uint32_t k = k0 + g;
+                for (int j = 0; j < PER_THREAD; j++) {
+                    const uint32_t e = j * NT + threadIdx.x;
+                    if (e < tot) keys[px(e)] = key_of_bits(u[j]);
+                }
+            }
+            __syncthreads();
+            // split of every cell: wide cells by the workgroup, the rest one per wave
+            if (RULE == KD_SPLIT_SUBSET) {
+                for (uint32_t k = 0; k < K; k++) {
+                    uint32_t m, lt, le;
+                    block_candidate<RULE>(c, level, keys, C.start[k], C.start[k + 1] - C.start[k],
+                                          C.li[k], h, sh, s3, sh64, mom[0], dyn, m, lt, le);
+                    if (threadIdx.x == 0) store_cell(c, level, C, k, m, lt, le);
+                }
+            } else {
+                for (uint32_t q = 0; q < C.nwide; q++) {
+                    const uint32_t k = C.wide[q];
+                    uint32_t m, lt, le;
+                    block_candidate<RULE>(c, level, keys, C.start[k], C.start[k + 1] - C.start[k],
+                                          C.li[k], h, sh, s3, sh64, mom[0], dyn, m, lt, le);
+                    if (threadIdx.x == 0) store_cell(c, level, C, k, m, lt, le);
+                }
+                for (uint32_t k = w; k < K; k += NW) {
+                    const uint32_t s0 = C.start[k], nk = C.start[k + 1] - s0;
+                    if (nk > WAVE_CELL_MAX) continue;
+                    uint32_t m, lt, le;
+                    wave_candidate<RULE>(c, keys, s0, nk, h[w], mom[w], m, lt, le);
+                    if (l == 0) store_cell(c, level, C, k, m, lt, le);
+                }
+            }
+            __syncthreads();
+            // ranks: thread t owns numbers 16t .. 16t+15; one chunk-wide scan of
+            // the left flags, less the scan value at each cell's first number
+            {
+                const uint32_t e0 = threadIdx.x * PER_THREAD;
+                const uint4 sq = *reinterpret_cast<const uint4 *>(seg + e0);
+                const uint32_t sw[4] = {sq.x, sq.y, sq.z, sq.w};
+                uint32_t sk[PER_THREAD];
+#pragma unroll
+                for (int j = 0; j < PER_THREAD; j++) sk[j] = (sw[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                uint32_t nleft = 0, fl = 0;
+#pragma unroll
+                for (int j = 0; j < PER_THREAD; j++) {
+                    const uint32_t e = e0 + j;
+                    if (e < tot && keys[px(e)] <= C.split[sk[j]]) {
+                        nleft++;
+                        fl |= 1u << j;
+                    }
+                }
+                uint32_t all;
+                const uint32_t lbase = block_excl_scan(nleft, sh, &all);
+                uint32_t run = lbase;
+#pragma unroll
+                for (int j = 0; j < PER_THREAD; j++) {
+                    const uint32_t e = e0 + j;
+                    if (e < tot && e == C.start[sk[j]]) C.base[sk[j]] = run;
+                    run += (fl >> j) & 1u;
+                }
+                __syncthreads();
+                run = lbase;
+#pragma unroll
+                for (int j = 0; j < PER_THREAD; j++) {
+                    const uint32_t e = e0 + j;
+                    if (e < tot) {
+                        const uint32_t k = sk[j], s = C.start[k], lr = run - C.base[k];
+                        const uint32_t dd = (fl >> j) & 1u ? s + lr : s + C.nl[k] + (e - s) - lr;
+                        keys[px(e)] = min(dd, uint32_t(TILE - 1));
+                    }
+                    run += (fl >> j) & 1u;
+                }
+            }
+            __syncthreads();
+            // every column and the permutation: stage at the destination, write
+            // in number order; numbers whose child stops go to the outputs
+            uint32_t ps[PER_THREAD], leafm = 0;
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) {
+                const uint32_t e = j * NT + threadIdx.x;
+                ps[j] = 0;
+                if (e < tot) {
+                    const uint32_t k = seg[e];
+                    ps[j] = C.off[k] + e;
+                    const bool right = e - C.start[k] >= C.nl[k];
+                    if (C.flags[k] & (right ? RES_RIGHT_LEAF : RES_LEFT_LEAF)) leafm |= 1u << j;
+                    if (RULE != KD_SPLIT_EXACT) vn[j] = gp(T.cols[cur])[ps[j]];
+                }
+            }
+            const int shift = MAXVAR ? maxvar_shift(c.ts[tr].maxabs) : 0;
+            for (uint32_t col = 0; col <= d; col++) {
+                uint32_t v[PER_THREAD];
+#pragma unroll
+                for (int j = 0; j < PER_THREAD; j++) v[j] = vn[j];
+                if (col < d) {
                     const KD_GLOBAL uint32_t *src =
-                        gp(k == d ? T.perm[cur] : T.cols[cur] + uint64_t(k) * n);
-                    stage[g * n_c + keys[px(e)]] = src[cl.begin + e];
-                }
-                e += de;
-                g += dk;
-                if (e >= n_c) {
-                    e -= n_c;
-                    g++;
-                }
-            }
-            wave_sync();
-            unsigned long long acc[6] = {0, 0, 0, 0, 0, 0};
-            for (uint32_t gg = 0; gg < g_end; gg++) {
-                const uint32_t k = k0 + gg;
-                const uint32_t *sg = stage + gg * n_c;
-                KD_GLOBAL uint32_t *next =
-                    gp(k == d ? T.perm[nxt] : T.cols[nxt] + uint64_t(k) * n) + cl.begin;
-                KD_GLOBAL uint32_t *out =
-                    k == d ? gp(T.out_perm) + cl.begin
-                           : (T.pts_out ? gp(T.pts_out + uint64_t(k) * n) + cl.begin : nullptr);
-                KD_GLOBAL uint32_t *ldst = lleaf ? out : next;
-                KD_GLOBAL uint32_t *rdst = rleaf ? out : next;
-                for (uint32_t i = l; i < r.nl; i += WAVE) {
-                    const uint32_t val = sg[i];
-                    if (ldst) ldst[i] = val;
-                    if (stats && k < d && !lleaf) add_stats(acc, val, shift, false);
-                }
-                for (uint32_t i = r.nl + l; i < n_c; i += WAVE) {
-                    const uint32_t val = sg[i];
-                    if (rdst) rdst[i] = val;
-                    if (stats && k < d && !rleaf) add_stats(acc, val, shift, true);
-                }
-            }
-            if (stats && k0 < d) {
+                        gp(col + 1 == d ? T.perm[cur] : T.cols[cur] + uint64_t(col + 1) * n);
 #pragma unroll
-                for (int q = 0; q < 6; q++) acc[q] = wave_sum64(acc[q]);
-                if (l < 6) {
-                    const int side = l / 3, j = l % 3;
-                    if (!(side ? rleaf : lleaf))
-                        T.stats[nxt][(uint64_t(2 * li + side) * d + k0) * 3 + j] = acc[l];
+                    for (int j = 0; j < PER_THREAD; j++)
+                        if (j * NT + threadIdx.x < tot) vn[j] = src[ps[j]];
+                }
+#pragma unroll
+                for (int j = 0; j < PER_THREAD; j++) {
+                    const uint32_t e = j * NT + threadIdx.x;
+                    if (e < tot) stage[keys[px(e)]] = v[j];
+                }
+                __syncthreads();
+                KD_GLOBAL uint32_t *nb =
+                    gp(col == d ? T.perm[nxt] : T.cols[nxt] + uint64_t(col) * n);
+                KD_GLOBAL uint32_t *ob =
+                    col == d ? gp(T.out_perm)
+                             : (T.pts_out ? gp(T.pts_out + uint64_t(col) * n) : nullptr);
+#pragma unroll
+                for (int j = 0; j < PER_THREAD; j++) {
+                    const uint32_t e = j * NT + threadIdx.x;
+                    if (e < tot) {
+                        KD_GLOBAL uint32_t *p = (leafm >> j) & 1u ? ob : nb;
+                        if (p) p[ps[j]] = stage[e];
+                    }
+                }
+                if (MAXVAR && col < d) {
+                    // sums of the children that go on, over runs of one child
+                    const uint32_t e0 = threadIdx.x * PER_THREAD;
+                    const uint4 sq = *reinterpret_cast<const uint4 *>(seg + e0);
+                    const uint32_t sw[4] = {sq.x, sq.y, sq.z, sq.w};
+                    uint32_t sv[PER_THREAD];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const uint4 x = *reinterpret_cast<const uint4 *>(stage + e0 + 4 * q);
+                        sv[4 * q] = x.x;
+                        sv[4 * q + 1] = x.y;
+                        sv[4 * q + 2] = x.z;
+                        sv[4 * q + 3] = x.w;
+                    }
+                    uint32_t run_seg = NONE;
+                    unsigned long long a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+                    for (int j = 0; j < PER_THREAD; j++) {
+                        const uint32_t e = e0 + j;
+                        if (e >= tot) break;
+                        const uint32_t k = (sw[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                        const bool right = e - C.start[k] >= C.nl[k];
+                        if (C.flags[k] & (right ? RES_RIGHT_LEAF : RES_LEFT_LEAF)) continue;
+                        const uint32_t s2 = 2 * k + (right ? 1u : 0u);
+                        if (s2 != run_seg) {
+                            if (run_seg != NONE) {
+                                atomicAdd(&acc[3 * run_seg], a0);
+                                atomicAdd(&acc[3 * run_seg + 1], a1);
+                                atomicAdd(&acc[3 * run_seg + 2], a2);
+                            }
+                            run_seg = s2;
+                            a0 = a1 = a2 = 0;
+                        }
+                        const long long qv = maxvar_q(sv[j], shift);
+                        const unsigned long long q2 = (unsigned long long)(qv * qv);
+                        a0 += (unsigned long long)qv;
+                        a1 += q2 >> 32;
+                        a2 += q2 & 0xffffffffull;
+                    }
+                    if (run_seg != NONE) {
+                        atomicAdd(&acc[3 * run_seg], a0);
+                        atomicAdd(&acc[3 * run_seg + 1], a1);
+                        atomicAdd(&acc[3 * run_seg + 2], a2);
+                    }
+                }
+                __syncthreads();
+                if (MAXVAR && col < d) {
+                    for (uint32_t s2 = threadIdx.x; s2 < 2 * K; s2 += NT) {
+                        const uint32_t k = s2 >> 1, side = s2 & 1u;
+                        if (!(C.flags[k] & (side ? RES_RIGHT_LEAF : RES_LEFT_LEAF)) &&
+                            (C.flags[k] & RES_SPLIT)) {
+                            unsigned long long *st =
+                                T.stats[nxt] + (uint64_t(2 * C.li[k] + side) * d + col) * 3;
+                            st[0] = acc[3 * s2];
+                            st[1] = acc[3 * s2 + 1];
+                            st[2] = acc[3 * s2 + 2];
+                        }
+                        acc[3 * s2] = acc[3 * s2 + 1] = acc[3 * s2 + 2] = 0;
+                    }
                 }
             }
-            wave_sync();
+            __syncthreads();
         }
-        if (l == 0) c.res[ci] = r;
     }
 }
 
@@ -1210,8 +1344,6 @@ __device__ __forceinline__ void emit_counts(const Ctx &c, uint32_t level, uint32
             cnt[2] += (sz[s] + TILE - 1) / TILE;
             cnt[4] += sz[s];
             cnt[5]++;
-        } else if (sz[s] > WAVE_CELL_MAX) {
-            cnt[8]++;
         }
     }
 }
@@ -1229,7 +1361,7 @@ __global__ __launch_bounds__(NT) void k_emit_sum(Ctx c, uint32_t level, uint32_t
 
 __global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t ncells, uint32_t nblocks) {
     __shared__ uint32_t sh[NW + 1];
-    uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t b0 = 0; b0 < nblocks; b0 += NT) {
         const uint32_t b = b0 + threadIdx.x;
         for (int k = 0; k < EMIT_COUNTERS; k++) {
@@ -1249,7 +1381,6 @@ __global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t ncells, uint32
         in.points = base[3];
         in.big_points = base[4];
         in.num_big = base[5];
-        in.mid_cells = base[8];
         *c.info = in;
     }
 }
@@ -1320,7 +1451,7 @@ __global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level, uint32
         T.node_begin[left + 1] = mid;
         T.node_end[left + 1] = cl.end;
     }
-    uint32_t slot = pre[1], tile = pre[2], big = pre[5];
+    uint32_t slot = pre[1], tile = pre[2], big = pre[5], voff = pre[3] - pre[4];
     const uint32_t b[2] = {cl.begin, mid}, e[2] = {mid, cl.end};
     const uint32_t leaf[2] = {r.flags & RES_LEFT_LEAF, r.flags & RES_RIGHT_LEAF};
     for (int s = 0; s < 2; s++) {
@@ -1328,11 +1459,14 @@ __global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level, uint32
         const uint32_t sz = e[s] - b[s];
         const bool isbig = sz > uint32_t(SMALL_MAX);
         c.cells[nxt][slot] = Cell{b[s], e[s], left + s, tile, isbig ? big : NONE, 2 * li + s,
-                                  cl.tree, 0u};
+                                  cl.tree, voff};
         if (isbig) {
             c.big_list[big] = slot;
             big++;
             tile += (sz + TILE - 1) / TILE;
+        } else {
+            mark_buckets(c, voff, sz, slot);
+            voff += sz;
         }
         slot++;
     }
@@ -1468,7 +1602,7 @@ struct TreeLayout {
 
 struct Layout {
     uint64_t trees, ts, cells[2], res, big_list, tile_lt, tile_le, tile_off, tile_cell, tiles, hist, mm, mom,
-        bounds, med, pre, scan, info, total;
+        bounds, med, pre, scan, buckets, info, total;
     uint64_t max_cells, max_tiles, max_big, scan_blocks;
     std::vector<TreeLayout> per_tree;
 };
@@ -1502,6 +1636,9 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     L.med = B.take(subset ? L.max_big * p->num_subsets * 4 : 0);
     L.pre = B.take((L.max_cells + 1) * EMIT_STRIDE * 4);
     L.scan = B.take((L.scan_blocks + 1) * EMIT_STRIDE * 4);
+    uint64_t all_points = 0;
+    for (uint32_t t = 0; t < T; t++) all_points += n[t];
+    L.buckets = B.take((all_points / TILE + 2) * 4);
     L.info = B.take(sizeof(LevelInfo));
     L.per_tree.resize(T);
     for (uint32_t t = 0; t < T; t++) {
@@ -1679,6 +1816,7 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     c.med = reinterpret_cast<uint32_t *>(ws + L.med);
     c.pre = reinterpret_cast<uint32_t *>(ws + L.pre);
     c.scan_tmp = reinterpret_cast<uint32_t *>(ws + L.scan);
+    c.bucket_first = reinterpret_cast<uint32_t *>(ws + L.buckets);
     c.info = reinterpret_cast<LevelInfo *>(ws + L.info);
     c.pool = p->subset_pool;
     c.pool_entries = p->pool_entries;
@@ -1720,13 +1858,10 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     const uint64_t scatter_avg_bpp = (8 * sum_d + 8 * total_points) / total_points;
     const bool maxvar = p->key_rule == KD_KEY_MAXVAR;
     const uint32_t hist_grid = 65535;  // workgroups of the histogram passes (tiles per group vary)
-    // dynamic LDS of the small-cell kernels (SUBSET: subset bounds and medians);
-    // the wave kernel keeps one table per wave, so it is used only while that
-    // fits next to its static LDS
+    // dynamic LDS of the small-cell kernel (SUBSET: subset bounds and medians)
     const size_t small_dyn = p->split_rule == KD_SPLIT_SUBSET ? (2 * size_t(c.S) + 1) * 4 : 0;
-    const bool wave_small = p->split_rule != KD_SPLIT_SUBSET || c.S <= 256;
-    static_assert(sizeof(uint32_t) * (2 * MAX_SUBSETS + 1) + 48 * 1024 <= 160 * 1024,
-                  "block small-cell kernel LDS");
+    static_assert(sizeof(uint32_t) * (2 * MAX_SUBSETS + 1) + 64 * 1024 <= 160 * 1024,
+                  "small-cell kernel LDS");
     LevelInfo hi{};
     uint32_t levels_run = 0;
     for (uint32_t level = 0;; level++) {
@@ -1798,16 +1933,10 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         }
         if (smallp > 0) {
             P.run(KD_PROF_SMALL, smallp, scatter_avg_bpp * smallp, [&] {
-                const dim3 g(grid_for(nc, 1u << 20)), gw(grid_for(nc / NW + 1, 1u << 20));
-#define KD_SMALL(R, M)                                                                     \
-    do {                                                                                   \
-        if (!wave_small || hi.mid_cells > 0)                                               \
-            hipLaunchKernelGGL((k_small<R, M>), g, dim3(NT), small_dyn, st, c, level, nc,   \
-                               wave_small ? WAVE_CELL_MAX : 0u);                           \
-        if (wave_small)                                                                    \
-            hipLaunchKernelGGL((k_small_wave<R, M>), gw, dim3(NT), NW * small_dyn, st, c,   \
-                               level, nc);                                                 \
-    } while (0)
+                const uint32_t nbk = uint32_t((smallp + TILE - 1) / TILE);
+                const dim3 g(grid_for(nbk, 1u << 20));
+#define KD_SMALL(R, M)                                                                    \
+    hipLaunchKernelGGL((k_small<R, M>), g, dim3(NT), small_dyn, st, c, level, nc, nbk)
                 switch (p->split_rule * 2 + (maxvar ? 1 : 0)) {
                     case 0: KD_SMALL(KD_SPLIT_EXACT, false); break;
                     case 1: KD_SMALL(KD_SPLIT_EXACT, true); break;
