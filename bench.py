@@ -166,6 +166,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (a kernel of known "
+                         "traffic for calibrating hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the build does not shard across GPUs); "
@@ -177,6 +180,15 @@ def main():
 
     from paper_2201_08288_amd import kdtree
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib:
+        m = args.copy_probe_mib << 20
+        a = torch.ones(m // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {m} bytes read, {m} bytes written")
+        del a, b
     log(f"[bench] generating workload {args.workload}")
     w, x, pool = workload_arrays(args.workload)
     d, n = x.shape

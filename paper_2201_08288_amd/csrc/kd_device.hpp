@@ -152,6 +152,44 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
     return x;
 }
 
+// Inclusive prefix sum over a wave64 with DPP moves (no LDS traffic): row
+// shifts scan each row of 16 lanes, then the row broadcasts carry the totals
+// of rows 0..2 into the rows after them.  Lane 63 holds the wave's total.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_add64(unsigned long long x) {
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, uint32_t(x), CTRL, ROWS, 0xf, true);
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, uint32_t(x >> 32), CTRL, ROWS, 0xf, true);
+    return x + ((unsigned long long)hi << 32 | lo);
+}
+__device__ __forceinline__ unsigned long long wave_scan64(unsigned long long x) {
+    x = dpp_add64<0x111, 0xf>(x);  // row_shr:1
+    x = dpp_add64<0x112, 0xf>(x);  // row_shr:2
+    x = dpp_add64<0x114, 0xf>(x);  // row_shr:4
+    x = dpp_add64<0x118, 0xf>(x);  // row_shr:8
+    x = dpp_add64<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x = dpp_add64<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+// Per-thread sums of the largest-variance grid values of one column:
+// s1 = sum q, and sum q^2 kept as hi * 2^32 + lo (any split of the exact sum
+// is allowed; only hi * 2^32 + lo is used).  Squares (each at most 2^60) are
+// added into sq, which the caller folds into hi and lo after at most 8 adds,
+// so nothing wraps.
+struct VarSums {
+    unsigned long long s1 = 0, hi = 0, lo = 0, sq = 0;
+    __device__ __forceinline__ void fold() {
+        hi += sq >> 32;
+        lo += sq & 0xffffffffull;
+        sq = 0;
+    }
+    __device__ __forceinline__ void add(int q) {
+        const uint32_t a = uint32_t(q < 0 ? -q : q);
+        s1 += (unsigned long long)(long long)q;
+        sq += (unsigned long long)a * a;
+    }
+};
+
 __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
 #pragma unroll
     for (int o = WAVE / 2; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, WAVE));
@@ -269,6 +307,9 @@ __device__ __forceinline__ int maxvar_shift(uint32_t maxabs_bits) {
 // q = rint(x * 2^shift) on that grid (|q| <= 2^30).
 __device__ __forceinline__ long long maxvar_q(uint32_t bits, int shift) {
     return (long long)(int)rintf(ldexpf(__uint_as_float(bits), shift));
+}
+__device__ __forceinline__ int maxvar_q32(uint32_t bits, int shift) {
+    return (int)rintf(ldexpf(__uint_as_float(bits), shift));
 }
 
 }  // namespace kd

@@ -728,41 +728,15 @@ __global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level, uint32
     }
 }
 
-// Largest-variance sums of one column's values for both children, added into
-// the children's statistics slots (atomically when several tiles share them).
-__device__ __forceinline__ void flush_stats(const KD_CONST TreeDesc &T, uint32_t nxt, uint32_t li,
-                                            uint32_t k, unsigned long long *acc, bool lleaf,
-                                            bool rleaf, unsigned long long *sh64, bool atomic) {
-    block_sum64n<6>(acc, sh64);
-    if (threadIdx.x < 6) {
-        const int side = threadIdx.x / 3, j = threadIdx.x % 3;
-        if (!(side ? rleaf : lleaf)) {
-            unsigned long long *st = T.stats[nxt] + (uint64_t(2 * li + side) * T.d + k) * 3 + j;
-            if (atomic) atomicAdd(st, acc[threadIdx.x]);
-            else *st = acc[threadIdx.x];
-        }
-    }
-}
-
-__device__ __forceinline__ void add_stats(unsigned long long *acc, uint32_t bits, int shift,
-                                          bool right) {
-    const long long q = maxvar_q(bits, shift);
-    const unsigned long long q2 = (unsigned long long)(q * q);
-    const int o = right ? 3 : 0;
-    acc[o] += (unsigned long long)q;
-    acc[o + 1] += q2 >> 32;
-    acc[o + 2] += q2 & 0xffffffffull;
-}
-
 // a7, large cells: stable partition-scatter of one tile.  Ranks come from the
 // staged key column; each column (and the permutation) is then permuted in
 // LDS and written as two contiguous runs, the left and right children's.
 template <bool MAXVAR>
-__global__ __launch_bounds__(NT) void k_big_scatter(Ctx c, uint32_t level, uint32_t ntiles) {
+__global__ __launch_bounds__(NT, MAXVAR ? 3 : 4) void k_big_scatter(Ctx c, uint32_t level, uint32_t ntiles) {
     __shared__ uint32_t stage0[PADDED];  // staged keys / ranks, then a column buffer
     __shared__ uint32_t stage1[TILE];
     __shared__ uint32_t sh[NW + 1];
-    __shared__ unsigned long long sh64[NW * 6];
+    __shared__ unsigned long long vacc[MAXVAR ? 16 : 1][6];  // a group of 16 columns
     const uint32_t cur = level & 1, nxt = cur ^ 1;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileDesc D = c.tiles[__builtin_amdgcn_readfirstlane(t)];
@@ -813,19 +787,35 @@ __global__ __launch_bounds__(NT) void k_big_scatter(Ctx c, uint32_t level, uint3
             for (int j = 0; j < PER_THREAD; j++) dr[j] = j * NT + threadIdx.x;
             nleft_tile = cnt;
         }
-        __syncthreads();
         const int shift = MAXVAR ? maxvar_shift(c.ts[D.tree].maxabs) : 0;
         const bool stats = MAXVAR && (D.flags & RES_SPLIT) && !(lleaf && rleaf);
-        for (uint32_t k = 0; k <= d; k++) {
-            const bool is_perm = k == d;
-            const KD_GLOBAL uint32_t *src =
-                gp(is_perm ? T.perm[cur] + D.tb : T.cols[cur] + uint64_t(k) * n + D.tb);
-            uint32_t *sg = (k & 1) ? stage1 : stage0;
-            uint32_t v[PER_THREAD];
+        if (stats)
+            for (uint32_t i = threadIdx.x; i < 16 * 6; i += NT) (&vacc[0][0])[i] = 0;
+        __syncthreads();
+        // column k is staged while column k + 1 is on its way
+        uint32_t vn[PER_THREAD];
+        {
+            const KD_GLOBAL uint32_t *src = gp(T.cols[cur] + D.tb);
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
                 const uint32_t i = j * NT + threadIdx.x;
-                if (i < cnt) v[j] = src[i];
+                vn[j] = i < cnt ? src[i] : 0u;
+            }
+        }
+        for (uint32_t k = 0; k <= d; k++) {
+            const bool is_perm = k == d;
+            uint32_t *sg = (k & 1) ? stage1 : stage0;
+            uint32_t v[PER_THREAD];
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) v[j] = vn[j];
+            if (k < d) {
+                const KD_GLOBAL uint32_t *src =
+                    gp(k + 1 == d ? T.perm[cur] + D.tb : T.cols[cur] + uint64_t(k + 1) * n + D.tb);
+#pragma unroll
+                for (int j = 0; j < PER_THREAD; j++) {
+                    const uint32_t i = j * NT + threadIdx.x;
+                    if (i < cnt) vn[j] = src[i];
+                }
             }
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
@@ -837,23 +827,57 @@ __global__ __launch_bounds__(NT) void k_big_scatter(Ctx c, uint32_t level, uint3
                 gp(is_perm ? T.perm[nxt] : T.cols[nxt] + uint64_t(k) * n);
             KD_GLOBAL uint32_t *lout =
                 gp(is_perm ? T.out_perm : (T.pts_out ? T.pts_out + uint64_t(k) * n : nullptr));
-            unsigned long long acc[6] = {0, 0, 0, 0, 0, 0};
+            const bool kstats = stats && !is_perm;
+            VarSums L, R;
             // left run: staged [0, nleft_tile) -> D.lpos; right run -> D.rpos
             KD_GLOBAL uint32_t *ldst = lleaf ? lout : lnext;
             if (ldst) ldst += D.lpos;
-            for (uint32_t i = threadIdx.x; i < nleft_tile; i += NT) {
-                const uint32_t val = sg[i];
-                if (ldst) ldst[i] = val;
-                if (stats && !is_perm && !lleaf) add_stats(acc, val, shift, false);
+            for (uint32_t i0 = 0; i0 < nleft_tile; i0 += 8 * NT) {
+#pragma unroll
+                for (int jj = 0; jj < 8; jj++) {
+                    const uint32_t i = i0 + jj * NT + threadIdx.x;
+                    if (i < nleft_tile) {
+                        const uint32_t val = sg[i];
+                        if (ldst) ldst[i] = val;
+                        if (kstats && !lleaf) L.add(maxvar_q32(val, shift));
+                    }
+                }
+                L.fold();
             }
             KD_GLOBAL uint32_t *rdst = rleaf ? lout : lnext;
             if (rdst) rdst += D.rpos;
-            for (uint32_t i = nleft_tile + threadIdx.x; i < cnt; i += NT) {
-                const uint32_t val = sg[i];
-                if (rdst) rdst[i - nleft_tile] = val;
-                if (stats && !is_perm && !rleaf) add_stats(acc, val, shift, true);
+            for (uint32_t i0 = nleft_tile; i0 < cnt; i0 += 8 * NT) {
+#pragma unroll
+                for (int jj = 0; jj < 8; jj++) {
+                    const uint32_t i = i0 + jj * NT + threadIdx.x;
+                    if (i < cnt) {
+                        const uint32_t val = sg[i];
+                        if (rdst) rdst[i - nleft_tile] = val;
+                        if (kstats && !rleaf) R.add(maxvar_q32(val, shift));
+                    }
+                }
+                R.fold();
             }
-            if (stats && !is_perm) flush_stats(T, nxt, D.li, k, acc, lleaf, rleaf, sh64, true);
+            if (kstats) {
+                // wave sums into the workgroup's accumulators of this column
+                unsigned long long x[6] = {L.s1, L.hi, L.lo, R.s1, R.hi, R.lo};
+#pragma unroll
+                for (int q = 0; q < 6; q++) x[q] = wave_scan64(x[q]);
+                if (lane() == WAVE - 1)
+#pragma unroll
+                    for (int q = 0; q < 6; q++) atomicAdd(&vacc[k & 15][q], x[q]);
+                if ((k & 15) == 15 || k + 1 == d) {
+                    __syncthreads();
+                    const uint32_t k0 = k & ~15u;
+                    for (uint32_t i = threadIdx.x; i < 16 * 6; i += NT) {
+                        const uint32_t kk = k0 + i / 6, q = i % 6, side = q / 3;
+                        if (kk < d && !(side ? rleaf : lleaf))
+                            atomicAdd(T.stats[nxt] + (uint64_t(2 * D.li + side) * d + kk) * 3 + q % 3,
+                                      (&vacc[0][0])[i]);
+                        (&vacc[0][0])[i] = 0;
+                    }
+                }
+            }
         }
         __syncthreads();
     }
@@ -1086,7 +1110,7 @@ __device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *ke
 }
 
 template <int RULE, bool MAXVAR>
-__global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t ncells,
+__global__ __launch_bounds__(NT, (MAXVAR && RULE != KD_SPLIT_FOURIER) ? 3 : 1) void k_small(Ctx c, uint32_t level, uint32_t ncells,
                                               uint32_t nbuckets) {
     __shared__ uint32_t keys[PADDED];  // staged keys, then each number's destination
     __shared__ __attribute__((aligned(16))) uint32_t stage[TILE];
@@ -1096,7 +1120,10 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
     __shared__ uint32_t sh[2 * NW + 1], s3[4];
     __shared__ unsigned long long sh64[NW * 2 * FCHUNK];
     __shared__ long long mom[NW][RULE == KD_SPLIT_FOURIER ? 2 * FOURIER_JMAX : 1];
-    __shared__ unsigned long long acc[MAXVAR ? 2 * SCELLS * 3 : 1];
+    // MAXVAR: chunk prefix sums (S1, hi, lo) at every cell start (2k) and split
+    // point (2k + 1), and the chunk total (2K); per-wave totals of the scan
+    __shared__ unsigned long long pat[MAXVAR ? 2 * SCELLS + 1 : 1][3];
+    __shared__ unsigned long long wtot[MAXVAR ? NW : 1][3];
     extern __shared__ uint32_t dyn[];  // SUBSET: bounds[S + 1], medians[S]
     const uint32_t cur = level & 1, nxt = cur ^ 1;
     const int w = wave(), l = lane();
@@ -1115,8 +1142,6 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
             const uint32_t d = T.d, n = T.n;
             for (uint32_t k = w; k < K; k += NW)
                 for (uint32_t e = C.start[k] + l; e < C.start[k + 1]; e += WAVE) seg[e] = uint8_t(k);
-            if (MAXVAR)
-                for (uint32_t i = threadIdx.x; i < 6 * K; i += NT) acc[i] = 0;
             __syncthreads();
             // keys of the chunk (EXACT: the first column is requested at the same
             // time and arrives while the cells are split)
@@ -1168,7 +1193,10 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
             }
             __syncthreads();
             // ranks: thread t owns numbers 16t .. 16t+15; one chunk-wide scan of
-            // the left flags, less the scan value at each cell's first number
+            // the left flags, less the scan value at each cell's first number.
+            // MAXVAR records: bit j of rmask marks number 16t + j as a cell
+            // start or a split point, byte j of rid its record index.
+            uint32_t rmask = 0, rid[4] = {0, 0, 0, 0};
             {
                 const uint32_t e0 = threadIdx.x * PER_THREAD;
                 const uint4 sq = *reinterpret_cast<const uint4 *>(seg + e0);
@@ -1203,6 +1231,13 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
                         const uint32_t k = sk[j], s = C.start[k], lr = run - C.base[k];
                         const uint32_t dd = (fl >> j) & 1u ? s + lr : s + C.nl[k] + (e - s) - lr;
                         keys[px(e)] = min(dd, uint32_t(TILE - 1));
+                        if (MAXVAR) {
+                            const bool at_split = (C.flags[k] & RES_SPLIT) && e == s + C.nl[k];
+                            if (e == s || at_split) {
+                                rmask |= 1u << j;
+                                rid[j >> 2] |= (2 * k + (at_split ? 1u : 0u)) << (8 * (j & 3));
+                            }
+                        }
                     }
                     run += (fl >> j) & 1u;
                 }
@@ -1255,63 +1290,73 @@ __global__ __launch_bounds__(NT) void k_small(Ctx c, uint32_t level, uint32_t nc
                     }
                 }
                 if (MAXVAR && col < d) {
-                    // sums of the children that go on, over runs of one child
+                    // segment sums of the children from chunk prefix sums: each
+                    // thread sums its 16 numbers, one workgroup scan gives every
+                    // thread its starting prefix, records are taken at cell
+                    // starts and split points, and a child's sums are the
+                    // difference of the records at its two ends
                     const uint32_t e0 = threadIdx.x * PER_THREAD;
-                    const uint4 sq = *reinterpret_cast<const uint4 *>(seg + e0);
-                    const uint32_t sw[4] = {sq.x, sq.y, sq.z, sq.w};
-                    uint32_t sv[PER_THREAD];
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const uint4 x = *reinterpret_cast<const uint4 *>(stage + e0 + 4 * q);
-                        sv[4 * q] = x.x;
-                        sv[4 * q + 1] = x.y;
-                        sv[4 * q + 2] = x.z;
-                        sv[4 * q + 3] = x.w;
-                    }
-                    uint32_t run_seg = NONE;
-                    unsigned long long a0 = 0, a1 = 0, a2 = 0;
+                    // q of number e0 + j (read again from LDS rather than kept)
+                    auto qv = [&](int j) {
+                        return maxvar_q32(stage[e0 + j], shift);
+                    };
+                    // the total folds at the same points as the walk below, so
+                    // the hi and lo parts of the prefixes never decrease
+                    VarSums a;
 #pragma unroll
                     for (int j = 0; j < PER_THREAD; j++) {
-                        const uint32_t e = e0 + j;
-                        if (e >= tot) break;
-                        const uint32_t k = (sw[j >> 2] >> (8 * (j & 3))) & 0xffu;
-                        const bool right = e - C.start[k] >= C.nl[k];
-                        if (C.flags[k] & (right ? RES_RIGHT_LEAF : RES_LEFT_LEAF)) continue;
-                        const uint32_t s2 = 2 * k + (right ? 1u : 0u);
-                        if (s2 != run_seg) {
-                            if (run_seg != NONE) {
-                                atomicAdd(&acc[3 * run_seg], a0);
-                                atomicAdd(&acc[3 * run_seg + 1], a1);
-                                atomicAdd(&acc[3 * run_seg + 2], a2);
-                            }
-                            run_seg = s2;
-                            a0 = a1 = a2 = 0;
+                        if ((rmask >> j) & 1u) a.fold();
+                        if (e0 + j < tot) a.add(qv(j));
+                        if (j == 7 || j == PER_THREAD - 1) a.fold();
+                    }
+                    unsigned long long x[3] = {a.s1, a.hi, a.lo};
+#pragma unroll
+                    for (int i = 0; i < 3; i++) x[i] = wave_scan64(x[i]);
+                    if (l == WAVE - 1)
+#pragma unroll
+                        for (int i = 0; i < 3; i++) wtot[w][i] = x[i];
+                    __syncthreads();
+                    VarSums p;
+                    p.s1 = x[0] - a.s1;
+                    p.hi = x[1] - a.hi;
+                    p.lo = x[2] - a.lo;
+                    for (int ww = 0; ww < w; ww++) {
+                        p.s1 += wtot[ww][0];
+                        p.hi += wtot[ww][1];
+                        p.lo += wtot[ww][2];
+                    }
+                    if (threadIdx.x == 0) {
+                        unsigned long long t3[3] = {0, 0, 0};
+                        for (int ww = 0; ww < NW; ww++)
+                            for (int i = 0; i < 3; i++) t3[i] += wtot[ww][i];
+                        for (int i = 0; i < 3; i++) pat[2 * K][i] = t3[i];
+                    }
+#pragma unroll
+                    for (int j = 0; j < PER_THREAD; j++) {
+                        if ((rmask >> j) & 1u) {
+                            p.fold();
+                            const uint32_t r = (rid[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                            pat[r][0] = p.s1;
+                            pat[r][1] = p.hi;
+                            pat[r][2] = p.lo;
                         }
-                        const long long qv = maxvar_q(sv[j], shift);
-                        const unsigned long long q2 = (unsigned long long)(qv * qv);
-                        a0 += (unsigned long long)qv;
-                        a1 += q2 >> 32;
-                        a2 += q2 & 0xffffffffull;
+                        if (e0 + j < tot) p.add(qv(j));
+                        if (j == 7) p.fold();
                     }
-                    if (run_seg != NONE) {
-                        atomicAdd(&acc[3 * run_seg], a0);
-                        atomicAdd(&acc[3 * run_seg + 1], a1);
-                        atomicAdd(&acc[3 * run_seg + 2], a2);
-                    }
+                    p.fold();
                 }
                 __syncthreads();
                 if (MAXVAR && col < d) {
                     for (uint32_t s2 = threadIdx.x; s2 < 2 * K; s2 += NT) {
                         const uint32_t k = s2 >> 1, side = s2 & 1u;
-                        if (!(C.flags[k] & (side ? RES_RIGHT_LEAF : RES_LEFT_LEAF)) &&
-                            (C.flags[k] & RES_SPLIT)) {
+                        if ((C.flags[k] & RES_SPLIT) &&
+                            !(C.flags[k] & (side ? RES_RIGHT_LEAF : RES_LEFT_LEAF))) {
                             unsigned long long *st =
                                 T.stats[nxt] + (uint64_t(2 * C.li[k] + side) * d + col) * 3;
-                            st[0] = acc[3 * s2];
-                            st[1] = acc[3 * s2 + 1];
-                            st[2] = acc[3 * s2 + 2];
+                            const uint32_t r0 = 2 * k + side, r1 = r0 + 1;
+#pragma unroll
+                            for (int i = 0; i < 3; i++) st[i] = pat[r1][i] - pat[r0][i];
                         }
-                        acc[3 * s2] = acc[3 * s2 + 1] = acc[3 * s2 + 2] = 0;
                     }
                 }
             }
