@@ -66,7 +66,7 @@ enum { KD_SPLIT_EXACT = 0, KD_SPLIT_FOURIER = 1, KD_SPLIT_SUBSET = 2 };
 typedef struct kd_params {
     uint32_t leaf_size;        /* cells with > leaf_size points are split (>= 1)   */
     uint32_t max_depth;        /* cells at this depth stay leaves (0 -> 64)         */
-    uint32_t num_subsets;      /* S: subsets per cell (1..65536)                    */
+    uint32_t num_subsets;      /* S: subsets per cell (1..4096)                     */
     uint32_t key_rule;         /* KD_KEY_*                                          */
     uint32_t split_rule;       /* KD_SPLIT_*                                        */
     uint32_t fourier_J;        /* harmonics for FOURIER (1..64)                     */

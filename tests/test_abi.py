@@ -1,0 +1,75 @@
+"""The C ABI without a GPU: libkdtree.so loads, exports every function that
+include/kdtree.h declares, and its host-only calls (sizes, parameter
+checks, status strings) behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kdtree.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(kd_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2201_08288_amd import _build
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    return ctypes.CDLL(_build.LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("kd_build", "kd_build_batched", "kd_query_leaf", "kd_tree_bounds",
+              "kd_batch_bounds", "kd_build_profiled", "kd_status_string", "kd_version"):
+        assert f in names, f
+
+
+def test_library_exports_every_declared_function(lib):
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_host_only_calls(lib):
+    from paper_2201_08288_amd import kdtree
+    lib.kd_version.restype = ctypes.c_int
+    assert lib.kd_version() >= 1
+    lib.kd_status_string.restype = ctypes.c_char_p
+    lib.kd_status_string.argtypes = [ctypes.c_int32]
+    strings = {lib.kd_status_string(s) for s in range(7)}
+    assert len(strings) == 7 and all(strings)
+    L = kdtree.lib()
+    cap, ws = ctypes.c_uint64(), ctypes.c_uint64()
+    p = kdtree.make_params(leaf_size=32, num_subsets=16)
+    assert L.kd_tree_bounds(65536, 3, ctypes.byref(p), ctypes.byref(cap), ctypes.byref(ws)) == 0
+    assert cap.value == 4 * (65536 // 32) + 64 and ws.value > 0
+    for bad in (dict(leaf_size=0), dict(num_subsets=0), dict(num_subsets=4097),
+                dict(split_rule=3), dict(key_rule=2), dict(split_rule=1, fourier_J=0),
+                dict(split_rule=1, fourier_J=65), dict(max_depth=129)):
+        kw = dict(leaf_size=32, num_subsets=16)
+        kw.update(bad)
+        q = kdtree.make_params(**kw)
+        assert L.kd_tree_bounds(1000, 3, ctypes.byref(q), ctypes.byref(cap),
+                                ctypes.byref(ws)) == kdtree.KD_EINVAL, bad
+    assert L.kd_tree_bounds(0, 3, ctypes.byref(p), ctypes.byref(cap), ctypes.byref(ws)) == \
+        kdtree.KD_EINVAL
+    assert L.kd_tree_bounds(10, 0, ctypes.byref(p), ctypes.byref(cap), ctypes.byref(ws)) == \
+        kdtree.KD_EINVAL
+
+
+def test_workspace_grows_with_size(lib):
+    from paper_2201_08288_amd import kdtree
+    p = kdtree.make_params(leaf_size=64, num_subsets=256)
+    small = kdtree.tree_bounds(1 << 16, 8, p)[1]
+    large = kdtree.tree_bounds(1 << 24, 8, p)[1]
+    assert large > 100 * small
+    # two working copies of the columns and permutation at least
+    assert large >= 2 * (8 + 1) * 4 * (1 << 24)
