@@ -908,6 +908,7 @@ struct ChunkLds {
     uint32_t split[SCELLS], nl[SCELLS], flags[SCELLS], base[SCELLS];
     uint32_t wide[4];            // cells above WAVE_CELL_MAX points (at most 3)
     uint32_t count, total, tree, next, nwide;
+    uint32_t goes_on;            // some child of the chunk is split again
 };
 
 // Wave 0: collect the next chunk, starting at cell `pos`, from the cells that
@@ -967,6 +968,7 @@ __device__ void form_chunk(const Ctx &c, uint32_t cur, uint32_t ncells, uint32_t
         C.next = pos;
         C.nwide = nwide;
         C.start[count] = total;
+        C.goes_on = 0;
     }
 }
 
@@ -982,6 +984,7 @@ __device__ __forceinline__ void store_cell(const Ctx &c, uint32_t level, ChunkLd
     r.lt = lt;
     r.le = le;
     c.res[C.ci[k]] = r;
+    if ((r.flags & RES_SPLIT) && (~r.flags & (RES_LEFT_LEAF | RES_RIGHT_LEAF))) C.goes_on = 1;
     C.split[k] = r.split;
     C.nl[k] = r.nl;
     C.flags[k] = r.flags;
@@ -1259,6 +1262,7 @@ __global__ __launch_bounds__(NT, (MAXVAR && RULE != KD_SPLIT_FOURIER) ? 3 : 1) v
                 }
             }
             const int shift = MAXVAR ? maxvar_shift(c.ts[tr].maxabs) : 0;
+            const bool chunk_stats = MAXVAR && C.goes_on;
             for (uint32_t col = 0; col <= d; col++) {
                 uint32_t v[PER_THREAD];
 #pragma unroll
@@ -1289,73 +1293,82 @@ __global__ __launch_bounds__(NT, (MAXVAR && RULE != KD_SPLIT_FOURIER) ? 3 : 1) v
                         if (p) p[ps[j]] = stage[e];
                     }
                 }
-                if (MAXVAR && col < d) {
-                    // segment sums of the children from chunk prefix sums: each
-                    // thread sums its 16 numbers, one workgroup scan gives every
-                    // thread its starting prefix, records are taken at cell
-                    // starts and split points, and a child's sums are the
-                    // difference of the records at its two ends
+                if (chunk_stats && col < d) {
+                    // child sums as differences of chunk prefix sums.  Wave w
+                    // holds numbers [1024w, 1024w + 1024), thread t numbers
+                    // 16t .. 16t+15.  Each thread sums its numbers, taking a
+                    // record of its running sum at every cell start and split
+                    // point; a DPP scan adds the sums of the wave's earlier
+                    // threads to the records; after the barrier below, a record
+                    // plus the totals of the earlier waves is the chunk prefix
+                    // there.  Every record is an exact prefix (hi * 2^32 + lo),
+                    // so differences of records are exact.
                     const uint32_t e0 = threadIdx.x * PER_THREAD;
-                    // q of number e0 + j (read again from LDS rather than kept)
-                    auto qv = [&](int j) {
-                        return maxvar_q32(stage[e0 + j], shift);
-                    };
-                    // the total folds at the same points as the walk below, so
-                    // the hi and lo parts of the prefixes never decrease
                     VarSums a;
 #pragma unroll
-                    for (int j = 0; j < PER_THREAD; j++) {
-                        if ((rmask >> j) & 1u) a.fold();
-                        if (e0 + j < tot) a.add(qv(j));
-                        if (j == 7 || j == PER_THREAD - 1) a.fold();
+                    for (int qq = 0; qq < 4; qq++) {
+                        const uint4 x4 = *reinterpret_cast<const uint4 *>(stage + e0 + 4 * qq);
+                        const uint32_t xv[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+                        for (int jj = 0; jj < 4; jj++) {
+                            const int j = 4 * qq + jj;
+                            if ((rmask >> j) & 1u) {
+                                a.fold();
+                                const uint32_t r = (rid[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                                pat[r][0] = a.s1;
+                                pat[r][1] = a.hi;
+                                pat[r][2] = a.lo;
+                            }
+                            a.add(e0 + j < tot ? maxvar_q32(xv[jj], shift) : 0);
+                            if (j == 7) a.fold();
+                        }
                     }
+                    a.fold();
                     unsigned long long x[3] = {a.s1, a.hi, a.lo};
 #pragma unroll
                     for (int i = 0; i < 3; i++) x[i] = wave_scan64(x[i]);
+                    if (rmask) {
+                        const unsigned long long ex[3] = {x[0] - a.s1, x[1] - a.hi, x[2] - a.lo};
+                        for (uint32_t m = rmask; m; m &= m - 1) {
+                            const int j = __builtin_ctz(m);
+                            const uint32_t r = (rid[j >> 2] >> (8 * (j & 3))) & 0xffu;
+#pragma unroll
+                            for (int i = 0; i < 3; i++) pat[r][i] += ex[i];
+                        }
+                    }
                     if (l == WAVE - 1)
 #pragma unroll
                         for (int i = 0; i < 3; i++) wtot[w][i] = x[i];
-                    __syncthreads();
-                    VarSums p;
-                    p.s1 = x[0] - a.s1;
-                    p.hi = x[1] - a.hi;
-                    p.lo = x[2] - a.lo;
-                    for (int ww = 0; ww < w; ww++) {
-                        p.s1 += wtot[ww][0];
-                        p.hi += wtot[ww][1];
-                        p.lo += wtot[ww][2];
-                    }
-                    if (threadIdx.x == 0) {
-                        unsigned long long t3[3] = {0, 0, 0};
-                        for (int ww = 0; ww < NW; ww++)
-                            for (int i = 0; i < 3; i++) t3[i] += wtot[ww][i];
-                        for (int i = 0; i < 3; i++) pat[2 * K][i] = t3[i];
-                    }
-#pragma unroll
-                    for (int j = 0; j < PER_THREAD; j++) {
-                        if ((rmask >> j) & 1u) {
-                            p.fold();
-                            const uint32_t r = (rid[j >> 2] >> (8 * (j & 3))) & 0xffu;
-                            pat[r][0] = p.s1;
-                            pat[r][1] = p.hi;
-                            pat[r][2] = p.lo;
-                        }
-                        if (e0 + j < tot) p.add(qv(j));
-                        if (j == 7) p.fold();
-                    }
-                    p.fold();
                 }
                 __syncthreads();
-                if (MAXVAR && col < d) {
+                if (chunk_stats && col < d) {
+                    // chunk prefix at record r (position pos): the record plus
+                    // the totals of the waves before pos's wave; the chunk end
+                    // (r = 2K) is the sum of all wave totals
+                    auto prefix = [&](uint32_t r, uint32_t pos, int i) {
+                        unsigned long long v = r < 2 * K ? pat[r][i] : 0ull;
+                        const uint32_t wr = r < 2 * K ? pos / (WAVE * PER_THREAD) : uint32_t(NW);
+                        for (uint32_t ww = 0; ww < wr; ww++) v += wtot[ww][i];
+                        return v;
+                    };
                     for (uint32_t s2 = threadIdx.x; s2 < 2 * K; s2 += NT) {
                         const uint32_t k = s2 >> 1, side = s2 & 1u;
                         if ((C.flags[k] & RES_SPLIT) &&
                             !(C.flags[k] & (side ? RES_RIGHT_LEAF : RES_LEFT_LEAF))) {
                             unsigned long long *st =
                                 T.stats[nxt] + (uint64_t(2 * C.li[k] + side) * d + col) * 3;
-                            const uint32_t r0 = 2 * k + side, r1 = r0 + 1;
-#pragma unroll
-                            for (int i = 0; i < 3; i++) st[i] = pat[r1][i] - pat[r0][i];
+                            const uint32_t mid = C.start[k] + C.nl[k];
+                            const uint32_t r0 = 2 * k + side, p0 = side ? mid : C.start[k];
+                            const uint32_t r1 = r0 + 1, p1 = side ? C.start[k + 1] : mid;
+                            // sum q^2 = (hi1 - hi0) * 2^32 + (lo1 - lo0); the
+                            // parts may differ in sign, the value is exact
+                            const __int128 q2 =
+                                (__int128)(long long)(prefix(r1, p1, 1) - prefix(r0, p0, 1)) *
+                                    ((__int128)1 << 32) +
+                                (__int128)(long long)(prefix(r1, p1, 2) - prefix(r0, p0, 2));
+                            st[0] = prefix(r1, p1, 0) - prefix(r0, p0, 0);
+                            st[1] = (unsigned long long)(q2 >> 32);
+                            st[2] = (unsigned long long)(q2 & 0xffffffff);
                         }
                     }
                 }
