@@ -214,26 +214,39 @@ __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
     }
 }
 
-// Largest-variance sums of the root cells (slot 0 of parity 0).
+// Largest-variance sums of the root cells (slot 0 of parity 0).  Grid:
+// (blocks over points, column, tree); eight values per thread per step.
 __global__ __launch_bounds__(NT) void k_root_stats(Ctx c) {
-    __shared__ unsigned long long sh64[NW * 3];
-    const uint32_t t = blockIdx.y;
+    __shared__ unsigned long long sh[NW][3];
+    const uint32_t t = blockIdx.z, col = blockIdx.y;
     const TreeState &S = c.ts[t];
-    if (S.count[0] == 0) return;
     const KD_CONST TreeDesc &T = cref(&c.trees[t]);
+    if (S.count[0] == 0 || col >= T.d) return;
     const int shift = maxvar_shift(S.maxabs);
-    for (uint32_t col = 0; col < T.d; col++) {
-        const uint32_t *src = T.cols[0] + uint64_t(col) * T.n;
-        unsigned long long v[3] = {0, 0, 0};
-        for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < T.n; i += gridDim.x * NT) {
-            const long long q = maxvar_q(src[i], shift);
-            const unsigned long long q2 = (unsigned long long)(q * q);
-            v[0] += (unsigned long long)q;
-            v[1] += q2 >> 32;
-            v[2] += q2 & 0xffffffffull;
+    const KD_GLOBAL uint32_t *src = gp(T.cols[0] + uint64_t(col) * T.n);
+    const uint32_t n = T.n;
+    VarSums a;
+    for (uint32_t i0 = blockIdx.x * NT * 8 + threadIdx.x; i0 < n; i0 += gridDim.x * NT * 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const uint32_t i = i0 + j * NT;
+            v[j] = i < n ? src[i] : 0u;
         }
-        block_sum64n<3>(v, sh64);
-        if (threadIdx.x < 3) atomicAdd(&T.stats[0][col * 3 + threadIdx.x], v[threadIdx.x]);
+#pragma unroll
+        for (int j = 0; j < 8; j++) a.add(i0 + j * NT < n ? maxvar_q32(v[j], shift) : 0);
+        a.fold();
+    }
+    unsigned long long x[3] = {a.s1, a.hi, a.lo};
+#pragma unroll
+    for (int i = 0; i < 3; i++) x[i] = wave_scan64(x[i]);
+    if (lane() == WAVE - 1)
+        for (int i = 0; i < 3; i++) sh[wave()][i] = x[i];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long v = 0;
+        for (int w = 0; w < NW; w++) v += sh[w][threadIdx.x];
+        atomicAdd(&T.stats[0][col * 3 + threadIdx.x], v);
     }
 }
 
@@ -890,22 +903,27 @@ __global__ __launch_bounds__(NT, MAXVAR ? 3 : 4) void k_big_scatter(Ctx c, uint3
 // points are numbered 0, 1, ... in cell order.  Those numbers are cut into
 // buckets of TILE; a workgroup takes the cells that start in its bucket and
 // works through them in chunks of whole cells of one tree (at most TILE points
-// and SCELLS cells), doing the whole level step of a chunk on chip: keys staged
+// and SC cells), doing the whole level step of a chunk on chip: keys staged
 // in LDS, the split of every cell (one wave per cell up to WAVE_CELL_MAX
 // points, otherwise the workgroup), ranks from one chunk-wide scan, then every
 // column and the permutation permuted through LDS.  A chunk's cells hold the
 // same positions before and after the step, so each column is read and written
 // over the same position ranges, with coalesced accesses.
 
-constexpr int SCELLS = 128;  // cells per chunk (chunk-local cell ids fit a byte)
+// Cells per chunk: 64 keeps the plain kernel's LDS within four workgroups per
+// CU; the largest-variance kernel (three per CU by registers) takes 128.
+// Chunk-local cell ids fit a byte either way.
+template <bool MAXVAR>
+constexpr int chunk_cells() { return MAXVAR ? 128 : 64; }
 
+template <int SC>
 struct ChunkLds {
-    uint32_t ci[SCELLS];         // cell index in the level list
-    uint32_t start[SCELLS + 1];  // chunk-local number of the cell's first point
-    uint32_t off[SCELLS];        // position minus chunk-local number
-    uint32_t dim[SCELLS];
-    uint32_t li[SCELLS];         // index in the tree's level list
-    uint32_t split[SCELLS], nl[SCELLS], flags[SCELLS], base[SCELLS];
+    uint32_t ci[SC];         // cell index in the level list
+    uint32_t start[SC + 1];  // chunk-local number of the cell's first point
+    uint32_t off[SC];        // position minus chunk-local number
+    uint32_t dim[SC];
+    uint32_t li[SC];         // index in the tree's level list
+    uint32_t split[SC], nl[SC], flags[SC], base[SC];
     uint32_t wide[4];            // cells above WAVE_CELL_MAX points (at most 3)
     uint32_t count, total, tree, next, nwide;
     uint32_t goes_on;            // some child of the chunk is split again
@@ -913,10 +931,11 @@ struct ChunkLds {
 
 // Wave 0: collect the next chunk, starting at cell `pos`, from the cells that
 // start before number v1.  Big cells are skipped; a chunk stops at the first
-// cell of another tree, at SCELLS cells, and before a cell that runs past v1
+// cell of another tree, at SC cells, and before a cell that runs past v1
 // (such a cell, the bucket's last, forms a chunk of its own).
+template <int SC>
 __device__ void form_chunk(const Ctx &c, uint32_t cur, uint32_t ncells, uint32_t pos,
-                           uint32_t v1, ChunkLds &C) {
+                           uint32_t v1, ChunkLds<SC> &C) {
     const int l = lane();
     uint32_t count = 0, total = 0, tree = NONE, first = 0, nwide = 0;
     for (;;) {
@@ -939,7 +958,7 @@ __device__ void form_chunk(const Ctx &c, uint32_t cur, uint32_t ncells, uint32_t
             count + uint32_t(__popcll(smask & ((1ull << l) - 1)));  // small cells before lane l
         const bool cross = small && !beyond && uint64_t(cl.voff) + nk > v1;
         const bool stop =
-            beyond || (small && (cl.tree != tree || before >= uint32_t(SCELLS) || (cross && before > 0)));
+            beyond || (small && (cl.tree != tree || before >= uint32_t(SC) || (cross && before > 0)));
         const unsigned long long stmask = __ballot(stop);
         const int s = stmask ? __builtin_ctzll(stmask) : WAVE;
         const bool take = small && l < s;
@@ -974,7 +993,8 @@ __device__ void form_chunk(const Ctx &c, uint32_t cur, uint32_t ncells, uint32_t
 
 // Split of one chunk cell from its candidate and counts; the result goes to
 // the level's cell results and to the chunk table.
-__device__ __forceinline__ void store_cell(const Ctx &c, uint32_t level, ChunkLds &C, uint32_t k,
+template <int SC>
+__device__ __forceinline__ void store_cell(const Ctx &c, uint32_t level, ChunkLds<SC> &C, uint32_t k,
                                            uint32_t m, uint32_t lt, uint32_t le) {
     const uint32_t n_c = C.start[k + 1] - C.start[k];
     CellRes r{};
@@ -1113,19 +1133,33 @@ __device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *ke
 }
 
 template <int RULE, bool MAXVAR>
-__global__ __launch_bounds__(NT, (MAXVAR && RULE != KD_SPLIT_FOURIER) ? 3 : 1) void k_small(Ctx c, uint32_t level, uint32_t ncells,
+__global__ __launch_bounds__(NT, MAXVAR ? (RULE != KD_SPLIT_FOURIER ? 3 : 1) : (RULE == KD_SPLIT_EXACT ? 4 : 1)) void k_small(Ctx c, uint32_t level, uint32_t ncells,
                                               uint32_t nbuckets) {
+    constexpr int SC = chunk_cells<MAXVAR>();
+    // the column buffer is idle while cells are split: the select scratch
+    // (digit histograms, FOURIER moments, reductions) shares its space
+    struct SelectScratch {
+        uint32_t h[NW][NBINS];
+        unsigned long long sh64[NW * 2 * FCHUNK];
+        long long mom[NW][RULE == KD_SPLIT_FOURIER ? 2 * FOURIER_JMAX : 1];
+    };
+    union StageOrSelect {
+        uint32_t stage[TILE];
+        SelectScratch sel;
+    };
+    static_assert(sizeof(SelectScratch) <= sizeof(uint32_t) * TILE, "select scratch fits");
     __shared__ uint32_t keys[PADDED];  // staged keys, then each number's destination
-    __shared__ __attribute__((aligned(16))) uint32_t stage[TILE];
+    __shared__ __attribute__((aligned(16))) StageOrSelect lds;
     __shared__ __attribute__((aligned(16))) uint8_t seg[TILE];  // chunk cell of each number
-    __shared__ ChunkLds C;
-    __shared__ uint32_t h[NW][NBINS];
+    __shared__ ChunkLds<SC> C;
     __shared__ uint32_t sh[2 * NW + 1], s3[4];
-    __shared__ unsigned long long sh64[NW * 2 * FCHUNK];
-    __shared__ long long mom[NW][RULE == KD_SPLIT_FOURIER ? 2 * FOURIER_JMAX : 1];
+    uint32_t *const stage = lds.stage;
+    uint32_t(*const h)[NBINS] = lds.sel.h;
+    unsigned long long *const sh64 = lds.sel.sh64;
+    auto &mom = lds.sel.mom;
     // MAXVAR: chunk prefix sums (S1, hi, lo) at every cell start (2k) and split
     // point (2k + 1), and the chunk total (2K); per-wave totals of the scan
-    __shared__ unsigned long long pat[MAXVAR ? 2 * SCELLS + 1 : 1][3];
+    __shared__ unsigned long long pat[MAXVAR ? 2 * SC + 1 : 1][3];
     __shared__ unsigned long long wtot[MAXVAR ? NW : 1][3];
     extern __shared__ uint32_t dyn[];  // SUBSET: bounds[S + 1], medians[S]
     const uint32_t cur = level & 1, nxt = cur ^ 1;
@@ -1908,7 +1942,8 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     P.run(KD_PROF_OTHER, 0, 0, [&] {
         hipLaunchKernelGGL(k_roots, dim3(1), dim3(NT), 0, st, c);
         if (p->key_rule == KD_KEY_MAXVAR)
-            hipLaunchKernelGGL(k_root_stats, per_tree_points, dim3(NT), 0, st, c);
+            hipLaunchKernelGGL(k_root_stats, dim3(grid_for(maxn / (NT * 8) + 1, 512), maxd, ntrees),
+                               dim3(NT), 0, st, c);
         hipLaunchKernelGGL(k_copy_leafroots, per_tree_points, dim3(NT), 0, st, c);
     });
     KD_LAUNCH_CHECK();
