@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default launch shapes instead of kd_autotune's choice")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (a kernel of known "
                          "traffic for calibrating hardware byte counters)")
@@ -221,6 +223,10 @@ def main():
     xt = torch.from_numpy(x).to(dev)
     pool_t = None if pool is None else torch.from_numpy(pool.view(np.int32)).to(dev)
     kw = tree_kwargs(w, args.rule)
+    tuning = kdtree.get_tuning()
+    if not args.no_autotune:
+        log("[bench] autotune")
+        tuning = kdtree.autotune(xt, subset_pool=pool_t, **kw)
     tree = kdtree.build(xt, subset_pool=pool_t, **kw)
     torch.cuda.synchronize()
     hdr = tree.header()
@@ -280,6 +286,7 @@ def main():
     level_gbps = b_alg * pl / (ms * 1e-3) / 1e9
 
     batched = serving = None
+    kdtree.set_tuning()  # batched and serving run the default launch shapes
     if not args.no_batched:
         log("[bench] batched vs plain (512 trees)")
         batched = bench_batched()
@@ -299,7 +306,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "gen": w["gen"],
                    "split_rule": args.rule, "key": w["key"], "leaf_size": w["leaf_size"],
-                   "num_subsets": w["num_subsets"], "parallelism": "single-gpu"},
+                   "num_subsets": w["num_subsets"], "parallelism": "single-gpu",
+                   "launch_shapes": tuning},
         "point_levels_per_step": pl, "levels": agg.get("levels"),
         "ms_per_step_event_pass": round(ms_events, 4),
         "whole_build_alg_GBps": round(level_gbps, 1),

@@ -182,6 +182,34 @@ kd_status kd_build_batched(uint32_t count, const kd_batch_item *items, const kd_
 kd_status kd_query_leaf(const kd_tree *tree, const float *q, uint64_t nq, uint32_t d,
                         uint64_t ldq, uint32_t *leaf_out, void *stream);
 
+/* Launch shapes of the level kernels.  They change only how work is spread
+ * over workgroups, never the result: every setting builds the same tree bit
+ * for bit.  0 in a field means the default (2048 workgroups per digit pass,
+ * one workgroup per tile of 4096 points for count and scatter, one per
+ * bucket of small cells).                                                  */
+typedef struct kd_tuning {
+    uint32_t hist_blocks;      /* workgroups of a large-cell digit pass            */
+    uint32_t scatter_blocks;   /* workgroups of the large-cell count and scatter   */
+    uint32_t small_blocks;     /* workgroups of the small-cell kernel              */
+    uint32_t reserved;
+} kd_tuning;
+
+/* Process-wide launch shapes used by kd_build and kd_build_batched (host
+ * only; the library's only global state).  Set them between builds, not
+ * while builds run on other threads.                                        */
+kd_status kd_set_tuning(const kd_tuning *t);
+kd_status kd_get_tuning(kd_tuning *t);
+
+/* Time the build of the given input under a small set of launch shapes
+ * (one field at a time, 3 timed builds each, on `stream`), check that every
+ * shape yields the same tree as the current one, keep the fastest with
+ * kd_set_tuning and return it in *best.  Arguments as for kd_build; `out`
+ * and `workspace` are overwritten.  Returns KD_EDEVICE if a shape gave a
+ * different tree (which would be a library bug).                            */
+kd_status kd_autotune(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
+                      const kd_params *params, kd_tree *out, void *workspace,
+                      uint64_t ws_bytes, void *stream, kd_tuning *best);
+
 const char *kd_status_string(kd_status s);
 int kd_version(void);
 

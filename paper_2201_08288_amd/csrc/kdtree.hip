@@ -25,6 +25,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "kdtree.h"
@@ -1837,8 +1838,17 @@ struct HostTree {
 };
 
 // The level loop over every tree of the build.
+// Process-wide launch shapes (set by kd_set_tuning / kd_autotune).
+std::mutex g_tuning_mu;
+kd_tuning g_tuning{};
+
+kd_tuning current_tuning() {
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    return g_tuning;
+}
+
 kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, void *workspace,
-                    uint64_t ws_bytes, hipStream_t st, kd_profile *prof) {
+                    uint64_t ws_bytes, hipStream_t st, kd_profile *prof, const kd_tuning &tune) {
     std::vector<uint64_t> n(ntrees), cap(ntrees);
     std::vector<uint32_t> d(ntrees);
     uint64_t total_points = 0, sum_d = 0;
@@ -1950,7 +1960,11 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
 
     const uint64_t scatter_avg_bpp = (8 * sum_d + 8 * total_points) / total_points;
     const bool maxvar = p->key_rule == KD_KEY_MAXVAR;
-    const uint32_t hist_grid = 65535;  // workgroups of the histogram passes (tiles per group vary)
+    // launch shapes: workgroups of the digit passes, of the count and scatter
+    // (grid-stride over tiles) and of the small-cell kernel (over buckets)
+    const uint32_t hist_grid = tune.hist_blocks ? tune.hist_blocks : 2048u;
+    const uint32_t tile_grid = tune.scatter_blocks ? tune.scatter_blocks : 65535u;
+    const uint32_t small_grid = tune.small_blocks ? tune.small_blocks : (1u << 20);
     // dynamic LDS of the small-cell kernel (SUBSET: subset bounds and medians)
     const size_t small_dyn = p->split_rule == KD_SPLIT_SUBSET ? (2 * size_t(c.S) + 1) * 4 : 0;
     static_assert(sizeof(uint32_t) * (2 * MAX_SUBSETS + 1) + 64 * 1024 <= 160 * 1024,
@@ -2010,24 +2024,24 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                 });
             }
             P.run(KD_PROF_COUNT, bigp, 4 * bigp, [&] {
-                hipLaunchKernelGGL(k_big_count, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st, c,
+                hipLaunchKernelGGL(k_big_count, dim3(grid_for(ntl, tile_grid)), dim3(NT), 0, st, c,
                                    level, nc, ntl);
                 hipLaunchKernelGGL(k_big_decide, dim3(grid_for(nbig, 65535)), dim3(NT), 0, st, c,
                                    level, nbig);
             });
             P.run(KD_PROF_BIG_SCATTER, bigp, scatter_avg_bpp * bigp, [&] {
                 if (maxvar)
-                    hipLaunchKernelGGL(k_big_scatter<true>, dim3(grid_for(ntl, 65535)), dim3(NT), 0,
+                    hipLaunchKernelGGL(k_big_scatter<true>, dim3(grid_for(ntl, tile_grid)), dim3(NT), 0,
                                        st, c, level, ntl);
                 else
-                    hipLaunchKernelGGL(k_big_scatter<false>, dim3(grid_for(ntl, 65535)), dim3(NT),
+                    hipLaunchKernelGGL(k_big_scatter<false>, dim3(grid_for(ntl, tile_grid)), dim3(NT),
                                        0, st, c, level, ntl);
             });
         }
         if (smallp > 0) {
             P.run(KD_PROF_SMALL, smallp, scatter_avg_bpp * smallp, [&] {
                 const uint32_t nbk = uint32_t((smallp + TILE - 1) / TILE);
-                const dim3 g(grid_for(nbk, 1u << 20));
+                const dim3 g(grid_for(nbk, small_grid));
 #define KD_SMALL(R, M)                                                                    \
     hipLaunchKernelGGL((k_small<R, M>), g, dim3(NT), small_dyn, st, c, level, nc, nbk)
                 switch (p->split_rule * 2 + (maxvar ? 1 : 0)) {
@@ -2112,7 +2126,8 @@ kd_status kd_build_profiled(const float *pts, uint64_t n, uint32_t d, uint64_t l
     if (!params_ok(p) || !shape_ok(n, d) || !pts || ld < n || !workspace || !tree_ok(out))
         return KD_EINVAL;
     const HostTree ht{pts, n, ld, d, out};
-    return run_build(1, &ht, p, workspace, ws_bytes, reinterpret_cast<hipStream_t>(stream), prof);
+    return run_build(1, &ht, p, workspace, ws_bytes, reinterpret_cast<hipStream_t>(stream), prof,
+                     current_tuning());
 }
 
 kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const kd_params *p,
@@ -2162,7 +2177,121 @@ kd_status kd_build_batched(uint32_t count, const kd_batch_item *items, const kd_
         ht[t] = HostTree{it.pts, it.n, it.ld, it.d, &it.out};
     }
     return run_build(count, ht.data(), params, workspace, ws_bytes,
-                     reinterpret_cast<hipStream_t>(stream), nullptr);
+                     reinterpret_cast<hipStream_t>(stream), nullptr, current_tuning());
+}
+
+kd_status kd_set_tuning(const kd_tuning *t) {
+    if (!t) return KD_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    g_tuning = *t;
+    g_tuning.reserved = 0;
+    return KD_OK;
+}
+
+kd_status kd_get_tuning(kd_tuning *t) {
+    if (!t) return KD_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    *t = g_tuning;
+    return KD_OK;
+}
+
+namespace {
+
+// Host copy of the parts of a built tree that identify it.
+struct TreeSnapshot {
+    kd_header hdr{};
+    std::vector<uint32_t> perm, child, split;
+    bool operator==(const TreeSnapshot &o) const {
+        return memcmp(&hdr, &o.hdr, sizeof(hdr)) == 0 && perm == o.perm && child == o.child &&
+               split == o.split;
+    }
+};
+
+kd_status snapshot(const kd_tree *out, uint64_t n, hipStream_t st, TreeSnapshot &s) {
+    if (hipMemcpyAsync(&s.hdr, out->hdr, sizeof(kd_header), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return KD_EDEVICE;
+    const uint64_t nn = s.hdr.num_nodes;
+    s.perm.resize(n);
+    s.child.resize(nn);
+    s.split.resize(nn);
+    if (hipMemcpyAsync(s.perm.data(), out->perm, n * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(s.child.data(), out->node_child, nn * 4, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(s.split.data(), out->node_split, nn * 4, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return KD_EDEVICE;
+    return KD_OK;
+}
+
+}  // namespace
+
+kd_status kd_autotune(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
+                      const kd_params *p, kd_tree *out, void *workspace, uint64_t ws_bytes,
+                      void *stream, kd_tuning *best) {
+    if (!params_ok(p) || !shape_ok(n, d) || !pts || ld < n || !workspace || !tree_ok(out) || !best)
+        return KD_EINVAL;
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const HostTree ht{pts, n, ld, d, out};
+    kd_tuning cur = current_tuning();
+    kd_status s = run_build(1, &ht, p, workspace, ws_bytes, st, nullptr, cur);
+    if (s != KD_OK) return s;
+    TreeSnapshot ref;
+    if ((s = snapshot(out, n, st, ref)) != KD_OK) return s;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return KD_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return KD_EDEVICE;
+    }
+    auto timed = [&](const kd_tuning &t, float &ms, bool &same) -> kd_status {
+        kd_status r = run_build(1, &ht, p, workspace, ws_bytes, st, nullptr, t);  // warm
+        if (r != KD_OK) return r;
+        TreeSnapshot got;
+        if ((r = snapshot(out, n, st, got)) != KD_OK) return r;
+        same = got == ref;
+        if (hipEventRecord(e0, st) != hipSuccess) return KD_EDEVICE;
+        for (int i = 0; i < 3; i++)
+            if ((r = run_build(1, &ht, p, workspace, ws_bytes, st, nullptr, t)) != KD_OK) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return KD_EDEVICE;
+        return KD_OK;
+    };
+    float best_ms = 0.0f;
+    bool same = true;
+    s = timed(cur, best_ms, same);
+    // one field at a time: each candidate replaces that field of the best so far
+    static const uint32_t kHist[] = {0, 65535, 4096, 1024, 512};
+    static const uint32_t kTile[] = {0, 4096, 2048, 1024};
+    static const uint32_t kSmall[] = {0, 8192, 4096, 2048};
+    for (int field = 0; field < 3 && s == KD_OK; field++) {
+        const uint32_t *vals = field == 0 ? kHist : field == 1 ? kTile : kSmall;
+        const int nv = field == 0 ? 5 : 4;
+        for (int i = 0; i < nv && s == KD_OK; i++) {
+            kd_tuning t = cur;
+            uint32_t &f = field == 0 ? t.hist_blocks : field == 1 ? t.scatter_blocks : t.small_blocks;
+            if (f == vals[i]) continue;
+            f = vals[i];
+            float ms = 0.0f;
+            bool ok = true;
+            s = timed(t, ms, ok);
+            if (s == KD_OK && !ok) s = KD_EDEVICE;
+            if (s == KD_OK && ms < best_ms) {
+                best_ms = ms;
+                cur = t;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s == KD_OK && !same) s = KD_EDEVICE;
+    if (s != KD_OK) return s;
+    kd_set_tuning(&cur);
+    *best = cur;
+    return KD_OK;
 }
 
 }  // extern "C"

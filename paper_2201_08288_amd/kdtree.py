@@ -52,6 +52,15 @@ class Profile(ctypes.Structure):
         return out
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("hist_blocks", _u32), ("scatter_blocks", _u32), ("small_blocks", _u32),
+                ("reserved", _u32)]
+
+    def to_dict(self):
+        return {"hist_blocks": self.hist_blocks, "scatter_blocks": self.scatter_blocks,
+                "small_blocks": self.small_blocks}
+
+
 class BatchItem(ctypes.Structure):
     _fields_ = [("pts", _vp), ("n", _u64), ("d", _u32), ("reserved", _u32), ("ld", _u64),
                 ("out", TreeStruct)]
@@ -86,6 +95,14 @@ def lib():
                                        _vp, _u64, _vp]
         L.kd_query_leaf.restype = st
         L.kd_query_leaf.argtypes = [ctypes.POINTER(TreeStruct), _vp, _u64, _u32, _u64, _vp, _vp]
+        L.kd_set_tuning.restype = st
+        L.kd_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.kd_get_tuning.restype = st
+        L.kd_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.kd_autotune.restype = st
+        L.kd_autotune.argtypes = [_vp, _u64, _u32, _u64, ctypes.POINTER(Params),
+                                  ctypes.POINTER(TreeStruct), _vp, _u64, _vp,
+                                  ctypes.POINTER(Tuning)]
         L.kd_status_string.restype = ctypes.c_char_p
         L.kd_status_string.argtypes = [st]
         L.kd_version.restype = ctypes.c_int
@@ -261,6 +278,37 @@ def query_leaf(tree, queries, stream=None):
     _check(lib().kd_query_leaf(ctypes.byref(tree.struct), queries.data_ptr(), nq, d, ldq,
                                out.data_ptr(), _stream_ptr(stream)), "kd_query_leaf")
     return out
+
+
+def set_tuning(hist_blocks=0, scatter_blocks=0, small_blocks=0):
+    """kd_set_tuning: process-wide launch shapes (0 = default)."""
+    t = Tuning(hist_blocks, scatter_blocks, small_blocks, 0)
+    _check(lib().kd_set_tuning(ctypes.byref(t)), "kd_set_tuning")
+
+
+def get_tuning():
+    t = Tuning()
+    _check(lib().kd_get_tuning(ctypes.byref(t)), "kd_get_tuning")
+    return t.to_dict()
+
+
+def autotune(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
+             split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0, stream=None):
+    """kd_autotune on this input; returns the chosen launch shapes (now in use)."""
+    assert points.is_cuda and points.dtype == torch.float32 and points.stride(1) == 1
+    d, n = points.shape
+    ld = points.stride(0) if d > 1 else n
+    prm = make_params(leaf_size, max_depth, num_subsets, key_rule, split_rule, fourier_J,
+                      subset_pool, seed, 0)
+    cap, ws = tree_bounds(n, d, prm)
+    prm.node_capacity = cap
+    workspace = torch.empty(ws, dtype=torch.uint8, device=points.device)
+    tree = KDTree(n, d, cap, points.device, False)
+    best = Tuning()
+    _check(lib().kd_autotune(points.data_ptr(), n, d, ld, ctypes.byref(prm),
+                             ctypes.byref(tree.struct), workspace.data_ptr(), workspace.numel(),
+                             _stream_ptr(stream), ctypes.byref(best)), "kd_autotune")
+    return best.to_dict()
 
 
 def version():

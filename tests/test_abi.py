@@ -73,3 +73,17 @@ def test_workspace_grows_with_size(lib):
     assert large > 100 * small
     # two working copies of the columns and permutation at least
     assert large >= 2 * (8 + 1) * 4 * (1 << 24)
+
+
+def test_tuning_round_trip(lib):
+    from paper_2201_08288_amd import kdtree
+    before = kdtree.get_tuning()
+    try:
+        kdtree.set_tuning(hist_blocks=1024, scatter_blocks=2048, small_blocks=4096)
+        assert kdtree.get_tuning() == {"hist_blocks": 1024, "scatter_blocks": 2048,
+                                       "small_blocks": 4096}
+    finally:
+        kdtree.set_tuning(**before)
+    assert kdtree.get_tuning() == before
+    L = kdtree.lib()
+    assert L.kd_set_tuning(None) == kdtree.KD_EINVAL and L.kd_get_tuning(None) == kdtree.KD_EINVAL
