@@ -1493,10 +1493,9 @@ __global__ __launch_bounds__(NT) void k_emit_prefix(Ctx c, uint32_t level, uint3
 
 // Per tree: node-id base of the new children, next level's cell range and
 // the tree's counters.
-__global__ void k_emit_trees(Ctx c, uint32_t level) {
+__device__ __forceinline__ void emit_tree(const Ctx &c, uint32_t level, uint32_t t) {
     const uint32_t cur = level & 1, nxt = cur ^ 1;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < c.ntrees;
-         t += gridDim.x * blockDim.x) {
+    {
         TreeState &S = c.ts[t];
         const uint32_t f = S.first[cur], n = S.count[cur];
         S.nodes_base = S.num_nodes;
@@ -1518,11 +1517,14 @@ __global__ void k_emit_trees(Ctx c, uint32_t level) {
         S.depth_first[level + 2] = S.num_nodes;
     }
 }
+__global__ void k_emit_trees(Ctx c, uint32_t level) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < c.ntrees;
+         t += gridDim.x * blockDim.x)
+        emit_tree(c, level, t);
+}
 
-__global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level, uint32_t ncells) {
+__device__ __forceinline__ void emit_cell(const Ctx &c, uint32_t level, uint32_t ci) {
     const uint32_t cur = level & 1, nxt = cur ^ 1;
-    const uint32_t ci = blockIdx.x * NT + threadIdx.x;
-    if (ci >= ncells) return;
     const CellRes r = c.res[ci];
     if (!(r.flags & RES_SPLIT)) return;
     const Cell cl = c.cells[cur][ci];
@@ -1563,6 +1565,54 @@ __global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level, uint32
         }
         slot++;
     }
+}
+__global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level, uint32_t ncells) {
+    const uint32_t ci = blockIdx.x * NT + threadIdx.x;
+    if (ci < ncells) emit_cell(c, level, ci);
+}
+
+// The whole emit step in one workgroup, for levels of at most EMIT_ONE_MAX
+// cells: counts and their prefix (each thread takes consecutive cells), the
+// totals, the per-tree update, then the node records and next cells.
+constexpr uint32_t EMIT_ONE_MAX = 2048;
+__global__ __launch_bounds__(NT) void k_emit_one(Ctx c, uint32_t level, uint32_t ncells) {
+    __shared__ uint32_t sh[NW + 1];
+    constexpr uint32_t PER = EMIT_ONE_MAX / NT;
+    const uint32_t c0 = threadIdx.x * PER;
+    uint32_t cnt[PER][EMIT_COUNTERS];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; j++) emit_counts(c, level, c0 + j, ncells, cnt[j]);
+    uint32_t tot[EMIT_COUNTERS];
+    for (int k = 0; k < EMIT_COUNTERS; k++) {
+        uint32_t local = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < PER; j++) local += cnt[j][k];
+        uint32_t run = block_excl_scan(local, sh, &tot[k]);
+#pragma unroll
+        for (uint32_t j = 0; j < PER; j++) {
+            if (c0 + j < ncells) c.pre[uint64_t(c0 + j) * EMIT_STRIDE + k] = run;
+            run += cnt[j][k];
+        }
+    }
+    if (threadIdx.x < EMIT_COUNTERS)
+        c.pre[uint64_t(ncells) * EMIT_STRIDE + threadIdx.x] = tot[threadIdx.x];
+    if (threadIdx.x == 0) {
+        LevelInfo in{};
+        in.num_cells = tot[1];
+        in.num_tiles = tot[2];
+        in.points = tot[3];
+        in.big_points = tot[4];
+        in.num_big = tot[5];
+        *c.info = in;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < c.ntrees; t += NT) emit_tree(c, level, t);
+    __threadfence_block();
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < PER; j++)
+        if (c0 + j < ncells) emit_cell(c, level, c0 + j);
 }
 
 // ------------------------------------------------------------ kernels: leaves
@@ -2057,6 +2107,10 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         }
         const uint32_t nb = (nc + NT - 1) / NT;
         P.run(KD_PROF_EMIT, 0, 0, [&] {
+            if (nc <= EMIT_ONE_MAX) {
+                hipLaunchKernelGGL(k_emit_one, dim3(1), dim3(NT), 0, st, c, level, nc);
+                return;
+            }
             hipLaunchKernelGGL(k_emit_sum, dim3(nb), dim3(NT), 0, st, c, level, nc);
             hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(NT), 0, st, c, nc, nb);
             hipLaunchKernelGGL(k_emit_prefix, dim3(nb), dim3(NT), 0, st, c, level, nc);
