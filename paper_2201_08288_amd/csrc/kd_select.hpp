@@ -52,6 +52,47 @@ __device__ SelectResult block_select(KEYS keys, uint32_t n, uint32_t k, uint32_t
     return SelectResult{prefix, lt, lt + cnt};
 }
 
+// Workgroup radix select of the k-th smallest key of a column in global
+// memory, col[0 .. n) holding fp32 bits: sixteen loads per thread in flight per
+// step.  h: NBINS words of LDS; sh: NW+1 words; s3: 3 words.
+__device__ uint32_t block_select_global(const uint32_t *col, uint32_t n, uint32_t k, uint32_t *h,
+                                        uint32_t *sh, uint32_t *s3) {
+    constexpr int U = 16;
+    const KD_GLOBAL uint32_t *g = gp(col);
+    uint32_t prefix = 0;
+    for (int pass = 0; pass < RPASSES; pass++) {
+        const int shift = 32 - RBITS * (pass + 1);
+        const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
+        for (int b = threadIdx.x; b < NBINS; b += NT) h[b] = 0;
+        __syncthreads();
+        for (uint32_t i0 = 0; i0 < n; i0 += U * NT) {
+            uint32_t u[U];
+#pragma unroll
+            for (int j = 0; j < U; j++) {
+                const uint32_t i = i0 + j * NT + threadIdx.x;
+                u[j] = i < n ? key_of_bits(g[i]) : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < U; j++) {
+                const uint32_t i = i0 + j * NT + threadIdx.x;
+                if (i < n && (u[j] & mask) == prefix) atomicAdd(&h[(u[j] >> shift) & (NBINS - 1)], 1u);
+            }
+        }
+        __syncthreads();
+        uint32_t hv = h[threadIdx.x], tot;
+        uint32_t ex = block_excl_scan(hv, sh, &tot);
+        if (ex <= k && k < ex + hv) {
+            s3[0] = threadIdx.x;
+            s3[1] = ex;
+        }
+        __syncthreads();
+        prefix |= s3[0] << shift;
+        k -= s3[1];
+        __syncthreads();
+    }
+    return prefix;
+}
+
 // Wave radix select over keys[off .. off+n) of an LDS array stored with one
 // pad word per 32 (element i at i + i / 32); h: this wave's NBINS words.
 __device__ uint32_t wave_select(const uint32_t *keys, uint32_t off, uint32_t n, uint32_t k,

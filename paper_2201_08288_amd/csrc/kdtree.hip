@@ -25,6 +25,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -630,8 +631,7 @@ __global__ __launch_bounds__(NT) void k_subset_select(Ctx c, uint32_t level, uin
             __syncthreads();
             m = block_select([&](uint32_t i) { return keys[i]; }, ns, (ns - 1) / 2, h, sh, s3).key;
         } else if (ns > 0) {
-            m = block_select([&](uint32_t i) { return key_of_bits(col[i]); }, ns, (ns - 1) / 2, h,
-                             sh, s3).key;
+            m = block_select_global(col, ns, (ns - 1) / 2, h, sh, s3);
         }
         if (threadIdx.x == 0) c.med[uint64_t(b) * c.S + s] = m;
         __syncthreads();
@@ -1062,7 +1062,7 @@ __device__ void wave_candidate(const Ctx &c, const uint32_t *keys, uint32_t s0, 
     le = uint32_t(wave_sum64(b));
 }
 
-// Candidate of one cell by the whole workgroup (every rule).
+// Candidate of one cell by the whole workgroup (EXACT, FOURIER).
 template <int RULE>
 __device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *keys, uint32_t s0,
                                 uint32_t nk, uint32_t li, uint32_t (*h)[NBINS], uint32_t *sh,
@@ -1076,7 +1076,7 @@ __device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *ke
         le = sel.le;
         return;
     }
-    if (RULE == KD_SPLIT_FOURIER) {
+    {  // FOURIER
         uint32_t mn = NONE, mx = 0;
         for (uint32_t i = threadIdx.x; i < nk; i += NT) {
             const uint32_t u = keys[px(s0 + i)];
@@ -1106,21 +1106,6 @@ __device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *ke
             m = s3[0];
             __syncthreads();
         }
-    } else {
-        uint32_t *B = dyn, *med = dyn + c.S + 1;
-        if (threadIdx.x == 0) subset_bounds(c, nk, level, li, B);
-        __syncthreads();
-        for (uint32_t s = wave(); s < c.S; s += NW) {
-            const uint32_t ns = B[s + 1] - B[s];
-            uint32_t v = NONE;
-            if (ns > 0) v = wave_select(keys, s0 + B[s], ns, (ns - 1) / 2, h[wave()]);
-            if (lane() == 0) med[s] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) s3[0] = subset_mean(B, med, c.S, nk);
-        __syncthreads();
-        m = s3[0];
-        __syncthreads();
     }
     unsigned long long cnt2[2] = {0, 0};
     for (uint32_t i = threadIdx.x; i < nk; i += NT) {
@@ -1131,6 +1116,124 @@ __device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *ke
     block_sum64n<2>(cnt2, sh64);
     lt = uint32_t(cnt2[0]);
     le = uint32_t(cnt2[1]);
+}
+
+// SUBSET, small cells: the split candidates of chunk cells [k0, k0 + G) at
+// once.  dyn holds, per cell, its subset bounds B[0..S] and medians med[0..S).
+// Subsets of at most RANK_MAX points find their lower median by counting
+// ranks (each point counts the smaller points of its subset, ties broken by
+// position); larger subsets use a wave radix select.  The weighted mean runs
+// one thread per cell, in subset order.
+constexpr uint32_t RANK_MAX = 64;
+constexpr uint32_t SUBSET_DYN_WORDS = 4096;  // dynamic LDS of the SUBSET small-cell kernel
+template <int SC>
+__device__ void subset_cells(const Ctx &c, uint32_t level, const uint32_t *keys,
+                             const uint8_t *seg, ChunkLds<SC> &C, uint32_t k0, uint32_t G,
+                             uint32_t *dyn, uint32_t (*h)[NBINS]) {
+    const uint32_t S = c.S, stride = 2 * S + 1;
+    const int w = wave(), l = lane();
+    // subset bounds, one wave per cell
+    for (uint32_t g = w; g < G; g += NW) {
+        const uint32_t k = k0 + g, n = C.start[k + 1] - C.start[k];
+        uint32_t *B = dyn + g * stride;
+        if (!c.pool) {
+            for (uint32_t r = l; r <= S; r += WAVE) B[r] = uint32_t((uint64_t(r) * n) / S);
+        } else {
+            const unsigned long long row =
+                splitmix64(c.seed ^ ((unsigned long long)level << 32) ^
+                           (unsigned long long)C.li[k]) % c.pool_entries;
+            const uint32_t *W = c.pool + row * S;
+            // B[r] = max over 1 <= j <= r of (n * W[j]) >> 32: a running maximum,
+            // lanes taking consecutive runs of r
+            const uint32_t per = (S + WAVE - 1) / WAVE, r0 = 1 + l * per;
+            uint32_t run = 0;
+            for (uint32_t r = r0; r < min(r0 + per, S); r++)
+                run = max(run, uint32_t((uint64_t(n) * W[r]) >> 32));
+            // exclusive running maximum of the lanes before this one
+            uint32_t x = run;
+#pragma unroll
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, WAVE);
+                if (l >= o) x = max(x, y);
+            }
+            uint32_t before = __shfl_up(x, 1, WAVE);
+            if (l == 0) before = 0;
+            for (uint32_t r = r0; r < min(r0 + per, S); r++) {
+                before = max(before, uint32_t((uint64_t(n) * W[r]) >> 32));
+                B[r] = before;
+            }
+            if (l == 0) {
+                B[0] = 0;
+                B[S] = n;
+            }
+        }
+    }
+    __syncthreads();
+    // lower medians of small subsets by counting ranks
+    const uint32_t e0 = C.start[k0], e1 = C.start[k0 + G];
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += NT) {
+        const uint32_t g = seg[e] - k0, i = e - C.start[k0 + g];
+        const uint32_t *B = dyn + g * stride;
+        // subset of position i: the last r with B[r] <= i
+        uint32_t lo = 0, hi = S;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (B[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t b = B[lo], m = B[lo + 1] - b;
+        if (m > RANK_MAX) continue;
+        const uint32_t s0 = C.start[k0 + g] + b, u = keys[px(e)];
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < m; j++) {
+            const uint32_t v = keys[px(s0 + j)];
+            rank += (v < u) || (v == u && s0 + j < e);
+        }
+        if (rank == (m - 1) / 2) dyn[g * stride + S + 1 + lo] = u;
+    }
+    // empty subsets, and lower medians of the large ones (a wave select
+    // each): a wave takes a cell and checks 64 subsets at a time
+    for (uint32_t g = w; g < G; g += NW) {
+        const uint32_t *B = dyn + g * stride;
+        uint32_t *med = dyn + g * stride + S + 1;
+        for (uint32_t r0 = 0; r0 < S; r0 += WAVE) {
+            const uint32_t r = r0 + l;
+            bool large = false;
+            if (r < S) {
+                const uint32_t m = B[r + 1] - B[r];
+                if (m == 0) med[r] = NONE;
+                large = m > RANK_MAX;
+            }
+            for (unsigned long long mask = __ballot(large); mask; mask &= mask - 1) {
+                const uint32_t rr = r0 + uint32_t(__builtin_ctzll(mask));
+                const uint32_t b = B[rr], m = B[rr + 1] - b;
+                const uint32_t v = wave_select(keys, C.start[k0 + g] + b, m, (m - 1) / 2, h[w]);
+                if (l == 0) med[rr] = v;
+            }
+        }
+    }
+    __syncthreads();
+    // weighted mean of the medians, in subset order (one thread per cell)
+    for (uint32_t g = threadIdx.x; g < G; g += NT) {
+        const uint32_t k = k0 + g;
+        C.split[k] = subset_mean(dyn + g * stride, dyn + g * stride + S + 1, S,
+                                 C.start[k + 1] - C.start[k]);
+    }
+    __syncthreads();
+    // counts around the candidate and the tie rule, one wave per cell
+    for (uint32_t g = w; g < G; g += NW) {
+        const uint32_t k = k0 + g, s0 = C.start[k], nk = C.start[k + 1] - s0, m = C.split[k];
+        uint32_t a = 0, b = 0;
+        for (uint32_t i = l; i < nk; i += WAVE) {
+            const uint32_t u = keys[px(s0 + i)];
+            a += u < m;
+            b += u <= m;
+        }
+        a = uint32_t(wave_sum64(a));
+        b = uint32_t(wave_sum64(b));
+        if (l == 0) store_cell(c, level, C, k, m, a, b);
+    }
+    __syncthreads();
 }
 
 template <int RULE, bool MAXVAR>
@@ -1207,12 +1310,9 @@ __global__ __launch_bounds__(NT, MAXVAR ? (RULE != KD_SPLIT_FOURIER ? 3 : 1) : (
             __syncthreads();
             // split of every cell: wide cells by the workgroup, the rest one per wave
             if (RULE == KD_SPLIT_SUBSET) {
-                for (uint32_t k = 0; k < K; k++) {
-                    uint32_t m, lt, le;
-                    block_candidate<RULE>(c, level, keys, C.start[k], C.start[k + 1] - C.start[k],
-                                          C.li[k], h, sh, s3, sh64, mom[0], dyn, m, lt, le);
-                    if (threadIdx.x == 0) store_cell(c, level, C, k, m, lt, le);
-                }
+                const uint32_t G = max(1u, SUBSET_DYN_WORDS / (2 * c.S + 1));
+                for (uint32_t k0 = 0; k0 < K; k0 += G)
+                    subset_cells(c, level, keys, seg, C, k0, min(G, K - k0), dyn, h);
             } else {
                 for (uint32_t q = 0; q < C.nwide; q++) {
                     const uint32_t k = C.wide[q];
@@ -2016,7 +2116,10 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     const uint32_t tile_grid = tune.scatter_blocks ? tune.scatter_blocks : 65535u;
     const uint32_t small_grid = tune.small_blocks ? tune.small_blocks : (1u << 20);
     // dynamic LDS of the small-cell kernel (SUBSET: subset bounds and medians)
-    const size_t small_dyn = p->split_rule == KD_SPLIT_SUBSET ? (2 * size_t(c.S) + 1) * 4 : 0;
+    const size_t small_dyn =
+        p->split_rule == KD_SPLIT_SUBSET
+            ? std::max<size_t>(SUBSET_DYN_WORDS, 2 * size_t(c.S) + 1) * 4
+            : 0;
     static_assert(sizeof(uint32_t) * (2 * MAX_SUBSETS + 1) + 64 * 1024 <= 160 * 1024,
                   "small-cell kernel LDS");
     LevelInfo hi{};
