@@ -146,11 +146,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
-__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, WAVE);
-    return x;
-}
 
 // Inclusive prefix sum over a wave64 with DPP moves (no LDS traffic): row
 // shifts scan each row of 16 lanes, then the row broadcasts carry the totals
@@ -169,6 +164,14 @@ __device__ __forceinline__ unsigned long long wave_scan64(unsigned long long x) 
     x = dpp_add64<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
     x = dpp_add64<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
     return x;
+}
+
+// Sum over a wave64, valid in every lane (DPP scan, then lane 63's total).
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
+    x = wave_scan64(x);
+    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(x), WAVE - 1);
+    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(x >> 32), WAVE - 1);
+    return (unsigned long long)hi << 32 | lo;
 }
 
 // Per-thread sums of the largest-variance grid values of one column:
