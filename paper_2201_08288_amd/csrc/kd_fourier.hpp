@@ -118,9 +118,20 @@ __device__ __forceinline__ void fourier_terms(uint32_t key, double xmin, double 
     }
 }
 
-// F(v) from the summed statistics Cc[j], Cs[j], j = 0..J-1 (harmonic 2j+1).
-__device__ __forceinline__ double fourier_F(const long long *Cc, const long long *Cs, int J,
-                                            double v, const TrigTables &T) {
+// F(v) from the summed statistics, held one harmonic per lane: lane j has
+// a_j = Cc[j] * 2^-24 and b_j = Cs[j] * 2^-24 (harmonic 2j+1, j < J); every
+// lane evaluates F at its own v, reading the coefficients from their lanes.
+// Call with all lanes of the wave active: an inactive lane's register may
+// hold another value.
+__device__ __forceinline__ double lane_value(double x, int j) {
+    const unsigned long long b = __double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(b), j);
+    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(b >> 32), j);
+    return __longlong_as_double((long long)((unsigned long long)hi << 32 | lo));
+}
+
+__device__ __forceinline__ double fourier_F(double a_lane, double b_lane, int J, double v,
+                                            const TrigTables &T) {
     double s1, c1;
     sincos64(v, T, s1, c1);
     const double ss = s1 * s1;
@@ -128,10 +139,9 @@ __device__ __forceinline__ double fourier_F(const long long *Cc, const long long
     const double sc = s1 * c1;
     const double S2 = 2.0 * sc;
     double cj = c1, sj = s1, F = 0.0;
-    const double q = 1.0 / 16777216.0;
     for (int j = 0; j < J; j++) {
-        const double a = double(Cc[j]) * q;
-        const double b = double(Cs[j]) * q;
+        const double a = lane_value(a_lane, j);
+        const double b = lane_value(b_lane, j);
         const double t1 = a * sj, t2 = b * cj;
         const double t = t1 - t2;
         const double wt = T.w[j] * t;
@@ -154,10 +164,15 @@ __device__ uint32_t fourier_solve_wave(const long long *Cc, const long long *Cs,
     const double xmin = value_of_key(lo);
     const double scale = fourier_scale(e);
     const int l = lane();
+    // the statistics as doubles, harmonic j in lane j
+    const double q = 1.0 / 16777216.0;
+    double a_lane = 0.0, b_lane = 0.0;
+    if (l < J) {
+        a_lane = double(Cc[l]) * q;
+        b_lane = double(Cs[l]) * q;
+    }
     // F at v = 0 (the smallest key)
-    double f0 = 0.0;
-    if (l == 0) f0 = fourier_F(Cc, Cs, J, 0.0, T);
-    f0 = __shfl(f0, 0, WAVE);
+    const double f0 = fourier_F(a_lane, b_lane, J, 0.0, T);
     if (f0 >= 0.0) return lo;
     while (hi - lo > 1u) {
         // heap node of this lane and its interval
@@ -176,8 +191,10 @@ __device__ uint32_t fourier_solve_wave(const long long *Cc, const long long *Cs,
         }
         live = live && (b - a > 1u);
         const uint32_t mid = a + (b - a) / 2u;
-        double f = 0.0;
-        if (live) f = fourier_F(Cc, Cs, J, (value_of_key(mid) - xmin) * scale, T);
+        // evaluated by every lane (the coefficients are read from their lanes,
+        // which must all be active); lanes without a live node use v = 0
+        const double v = live ? (value_of_key(mid) - xmin) * scale : 0.0;
+        const double f = fourier_F(a_lane, b_lane, J, v, T);
         const unsigned long long neg = __ballot(live && f < 0.0);
         // follow the sequential path for up to six steps
         uint32_t nd = 1;
