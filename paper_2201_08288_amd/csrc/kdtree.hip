@@ -66,6 +66,8 @@ struct Ctx {
     uint32_t *pre;
     uint32_t *scan_tmp;
     uint32_t *bucket_first;  // small cells: first cell of each bucket of TILE numbers
+    // SUBSET: subsets of more than SMALL_MAX points of the level's large cells
+    uint32_t *seg_count, *seg_job, *seg_prefix, *seg_rank, *seg_hist;
     LevelInfo *info;
     const uint32_t *pool;
     uint32_t pool_entries;
@@ -631,9 +633,108 @@ __global__ __launch_bounds__(NT) void k_subset_select(Ctx c, uint32_t level, uin
             __syncthreads();
             m = block_select([&](uint32_t i) { return keys[i]; }, ns, (ns - 1) / 2, h, sh, s3).key;
         } else if (ns > 0) {
-            m = block_select_global(col, ns, (ns - 1) / 2, h, sh, s3);
+            continue;  // a large subset: selected by the segmented passes
         }
         if (threadIdx.x == 0) c.med[uint64_t(b) * c.S + s] = m;
+        __syncthreads();
+    }
+}
+
+// SUBSET, large cells: subsets of more than SMALL_MAX points are selected by
+// several workgroups each.  A list of them is made first; then per 8-bit
+// digit, SEG_FAN workgroups per subset add the digit histogram of their part
+// into the subset's histogram, and one workgroup per subset picks the digit.
+constexpr uint32_t SEG_FAN = 64;
+
+__global__ __launch_bounds__(NT) void k_seg_list(Ctx c, uint32_t nbig) {
+    const uint64_t jobs = uint64_t(nbig) * c.S;
+    for (uint64_t job = blockIdx.x * uint64_t(NT) + threadIdx.x; job < jobs;
+         job += uint64_t(gridDim.x) * NT) {
+        const uint32_t b = uint32_t(job / c.S), s = uint32_t(job % c.S);
+        const uint32_t *B = c.bounds + uint64_t(b) * (c.S + 1);
+        const uint32_t ns = B[s + 1] - B[s];
+        if (ns > uint32_t(SMALL_MAX)) {
+            const uint32_t i = atomicAdd(c.seg_count, 1u);
+            c.seg_job[i] = uint32_t(job);
+            c.seg_prefix[i] = 0;
+            c.seg_rank[i] = (ns - 1) / 2;
+        }
+    }
+}
+
+// Column, first position and size of large subset i.
+struct SegView {
+    const uint32_t *col;
+    uint32_t b, s, ns;
+};
+__device__ __forceinline__ SegView seg_view(const Ctx &c, uint32_t cur, uint32_t i) {
+    SegView v;
+    const uint32_t job = c.seg_job[i];
+    v.b = job / c.S;
+    v.s = job % c.S;
+    const uint32_t ci = c.big_list[v.b];
+    const Cell cl = c.cells[cur][ci];
+    const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
+    const uint32_t *B = c.bounds + uint64_t(v.b) * (c.S + 1);
+    v.ns = B[v.s + 1] - B[v.s];
+    v.col = T.cols[cur] + uint64_t(c.res[ci].dim) * T.n + cl.begin + B[v.s];
+    return v;
+}
+
+__global__ __launch_bounds__(NT) void k_seg_hist(Ctx c, uint32_t level, uint32_t pass) {
+    __shared__ uint32_t h[NBINS];
+    const uint32_t cur = level & 1, nseg = *c.seg_count;
+    const int shift = 32 - RBITS * (pass + 1);
+    const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
+    for (uint32_t blk = blockIdx.x; blk < nseg * SEG_FAN; blk += gridDim.x) {
+        const uint32_t i = blk / SEG_FAN, f = blk % SEG_FAN;
+        const SegView v = seg_view(c, cur, i);
+        const uint32_t prefix = c.seg_prefix[i];
+        const uint32_t per = (v.ns + SEG_FAN - 1) / SEG_FAN;
+        const uint32_t a = min(f * per, v.ns), e = min(a + per, v.ns);
+        h[threadIdx.x] = 0;
+        __syncthreads();
+        const KD_GLOBAL uint32_t *g = gp(v.col);
+        for (uint32_t i0 = a; i0 < e; i0 += PER_THREAD * NT) {
+            uint32_t u[PER_THREAD];
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) {
+                const uint32_t x = i0 + j * NT + threadIdx.x;
+                u[j] = x < e ? key_of_bits(g[x]) : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) {
+                const uint32_t x = i0 + j * NT + threadIdx.x;
+                if (x < e && (u[j] & mask) == prefix) atomicAdd(&h[(u[j] >> shift) & (NBINS - 1)], 1u);
+            }
+        }
+        __syncthreads();
+        if (h[threadIdx.x]) atomicAdd(&c.seg_hist[uint64_t(i) * NBINS + threadIdx.x], h[threadIdx.x]);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_seg_pick(Ctx c, uint32_t pass) {
+    __shared__ uint32_t sh[NW + 1], s3[2];
+    const uint32_t nseg = *c.seg_count;
+    const int shift = 32 - RBITS * (pass + 1);
+    for (uint32_t i = blockIdx.x; i < nseg; i += gridDim.x) {
+        uint32_t *gh = c.seg_hist + uint64_t(i) * NBINS;
+        const uint32_t hv = gh[threadIdx.x], rank = c.seg_rank[i];
+        gh[threadIdx.x] = 0;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(hv, sh, &tot);
+        if (ex <= rank && rank < ex + hv) {
+            s3[0] = threadIdx.x;
+            s3[1] = ex;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t prefix = c.seg_prefix[i] | (s3[0] << shift);
+            c.seg_prefix[i] = prefix;
+            c.seg_rank[i] = rank - s3[1];
+            if (pass == RPASSES - 1) c.med[c.seg_job[i]] = prefix;
+        }
         __syncthreads();
     }
 }
@@ -1845,8 +1946,8 @@ struct TreeLayout {
 
 struct Layout {
     uint64_t trees, ts, cells[2], res, big_list, tile_lt, tile_le, tile_off, tile_cell, tiles, hist, mm, mom,
-        bounds, med, pre, scan, buckets, info, total;
-    uint64_t max_cells, max_tiles, max_big, scan_blocks;
+        bounds, med, pre, scan, buckets, segs, info, total;
+    uint64_t max_cells, max_tiles, max_big, scan_blocks, all_points;
     std::vector<TreeLayout> per_tree;
 };
 
@@ -1881,7 +1982,10 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     L.scan = B.take((L.scan_blocks + 1) * EMIT_STRIDE * 4);
     uint64_t all_points = 0;
     for (uint32_t t = 0; t < T; t++) all_points += n[t];
+    L.all_points = all_points;
     L.buckets = B.take((all_points / TILE + 2) * 4);
+    // at most one large subset per SMALL_MAX + 1 points
+    L.segs = B.take(subset ? (all_points / (SMALL_MAX + 1) + 2) * 4 * (3 + NBINS) + 256 : 0);
     L.info = B.take(sizeof(LevelInfo));
     L.per_tree.resize(T);
     for (uint32_t t = 0; t < T; t++) {
@@ -2069,6 +2173,15 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     c.pre = reinterpret_cast<uint32_t *>(ws + L.pre);
     c.scan_tmp = reinterpret_cast<uint32_t *>(ws + L.scan);
     c.bucket_first = reinterpret_cast<uint32_t *>(ws + L.buckets);
+    {
+        const uint64_t max_seg = L.all_points / (SMALL_MAX + 1) + 2;
+        uint32_t *sg = reinterpret_cast<uint32_t *>(ws + L.segs);
+        c.seg_count = sg;
+        c.seg_job = sg + 64;
+        c.seg_prefix = c.seg_job + max_seg;
+        c.seg_rank = c.seg_prefix + max_seg;
+        c.seg_hist = c.seg_rank + max_seg;
+    }
     c.info = reinterpret_cast<LevelInfo *>(ws + L.info);
     c.pool = p->subset_pool;
     c.pool_entries = p->pool_entries;
@@ -2094,6 +2207,11 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.max_big * BIG_BINS / NT + 1, 4096)),
                            dim3(NT), 0, st, c.hist, L.max_big * BIG_BINS, 0u);
         hipLaunchKernelGGL(k_init, per_tree_nodes, dim3(NT), 0, st, c);
+        if (p->split_rule == KD_SPLIT_SUBSET) {
+            const uint64_t words = (L.all_points / (SMALL_MAX + 1) + 2) * (3 + NBINS) + 64;
+            hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words / NT + 1, 4096)), dim3(NT), 0, st,
+                               c.seg_count, words, 0u);
+        }
     });
     P.run(KD_PROF_INGEST, total_points, 8 * sum_d + 4 * total_points, [&] {
         hipLaunchKernelGGL(k_ingest, dim3(grid_for(maxn / (NT * 4) + 1, 1024), maxd, ntrees),
@@ -2167,6 +2285,21 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                 P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
                     hipLaunchKernelGGL(k_big_bounds, dim3(grid_for(nbig / NT + 1, 4096)), dim3(NT),
                                        0, st, c, level, nbig);
+                    // subsets above SMALL_MAX points: segmented passes over many
+                    // workgroups; the rest: one workgroup each, in LDS
+                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(NT), 0, st, c.seg_count, 1ull, 0u);
+                    hipLaunchKernelGGL(k_seg_list, dim3(grid_for(uint64_t(nbig) * c.S / NT + 1, 4096)),
+                                       dim3(NT), 0, st, c, nbig);
+                    uint32_t nseg = 0;
+                    if (hipMemcpyAsync(&nseg, c.seg_count, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                        hipStreamSynchronize(st) != hipSuccess)
+                        nseg = uint32_t(bigp / (SMALL_MAX + 1) + 1);  // bound; kernels read the count
+                    for (uint32_t pass = 0; nseg > 0 && pass < uint32_t(RPASSES); pass++) {
+                        hipLaunchKernelGGL(k_seg_hist, dim3(grid_for(uint64_t(nseg) * SEG_FAN, 65535)),
+                                           dim3(NT), 0, st, c, level, pass);
+                        hipLaunchKernelGGL(k_seg_pick, dim3(grid_for(nseg, 65535)), dim3(NT), 0, st, c,
+                                           pass);
+                    }
                     hipLaunchKernelGGL(k_subset_select,
                                        dim3(grid_for(uint64_t(nbig) * c.S, 65535)), dim3(NT), 0,
                                        st, c, level, nbig);
