@@ -611,32 +611,67 @@ __global__ __launch_bounds__(NT) void k_big_bounds(Ctx c, uint32_t level, uint32
     }
 }
 
-// SUBSET, large cells: lower median of one subset per workgroup.
+// SUBSET, large cells: lower medians of the subsets of at most SMALL_MAX
+// points.  A workgroup takes four subsets: those of at most WAVE_SUB points go
+// to one wave each (keys staged in the wave's part of LDS), larger ones to the
+// whole workgroup afterwards.
+constexpr uint32_t WAVE_SUB = 1024;
 __global__ __launch_bounds__(NT) void k_subset_select(Ctx c, uint32_t level, uint32_t nbig) {
-    __shared__ uint32_t keys[SMALL_MAX];
-    __shared__ uint32_t h[NBINS];
+    __shared__ uint32_t keys[SMALL_MAX + SMALL_MAX / 32];
+    __shared__ uint32_t h[NW][NBINS];
     __shared__ uint32_t sh[NW + 1], s3[3];
     const uint32_t cur = level & 1;
+    const int w = wave(), l = lane();
     const uint64_t jobs = uint64_t(nbig) * c.S;
-    for (uint64_t job = blockIdx.x; job < jobs; job += gridDim.x) {
+    auto subset = [&](uint64_t job, const uint32_t *&col, uint32_t &ns) {
         const uint32_t b = uint32_t(job / c.S), s = uint32_t(job % c.S);
         const uint32_t ci = c.big_list[b];
         const Cell cl = c.cells[cur][ci];
-        const CellRes r = c.res[ci];
         const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
         const uint32_t *B = c.bounds + uint64_t(b) * (c.S + 1);
-        const uint32_t sb = cl.begin + B[s], ns = B[s + 1] - B[s];
-        const uint32_t *col = T.cols[cur] + uint64_t(r.dim) * T.n + sb;
-        uint32_t m = NONE;
-        if (ns > 0 && ns <= uint32_t(SMALL_MAX)) {
-            for (uint32_t i = threadIdx.x; i < ns; i += NT) keys[i] = key_of_bits(col[i]);
-            __syncthreads();
-            m = block_select([&](uint32_t i) { return keys[i]; }, ns, (ns - 1) / 2, h, sh, s3).key;
-        } else if (ns > 0) {
-            continue;  // a large subset: selected by the segmented passes
+        ns = B[s + 1] - B[s];
+        col = T.cols[cur] + uint64_t(c.res[ci].dim) * T.n + cl.begin + B[s];
+    };
+    for (uint64_t j0 = uint64_t(blockIdx.x) * NW; j0 < jobs; j0 += uint64_t(gridDim.x) * NW) {
+        // one wave per small subset
+        {
+            const uint64_t job = j0 + w;
+            if (job < jobs) {
+                const uint32_t *col;
+                uint32_t ns;
+                subset(job, col, ns);
+                if (ns <= WAVE_SUB) {
+                    uint32_t m = NONE;
+                    if (ns > 0) {
+                        const uint32_t off = uint32_t(w) * WAVE_SUB;
+                        for (uint32_t i = l; i < ns; i += WAVE) {
+                            const uint32_t g = off + i;
+                            keys[g + (g >> 5)] = key_of_bits(col[i]);
+                        }
+                        wave_sync();
+                        m = wave_select(keys, off, ns, (ns - 1) / 2, h[w]);
+                    }
+                    if (l == 0) c.med[job] = m;
+                }
+            }
         }
-        if (threadIdx.x == 0) c.med[uint64_t(b) * c.S + s] = m;
         __syncthreads();
+        // the workgroup for the others up to SMALL_MAX points
+        for (int q = 0; q < NW; q++) {
+            const uint64_t job = j0 + q;
+            if (job >= jobs) break;
+            const uint32_t *col;
+            uint32_t ns;
+            subset(job, col, ns);
+            if (ns <= WAVE_SUB || ns > uint32_t(SMALL_MAX)) continue;
+            for (uint32_t i = threadIdx.x; i < ns; i += NT) keys[px(i)] = key_of_bits(col[i]);
+            __syncthreads();
+            const uint32_t m =
+                block_select([&](uint32_t i) { return keys[px(i)]; }, ns, (ns - 1) / 2, h[0], sh, s3)
+                    .key;
+            if (threadIdx.x == 0) c.med[job] = m;
+            __syncthreads();
+        }
     }
 }
 
@@ -2301,8 +2336,8 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                                            pass);
                     }
                     hipLaunchKernelGGL(k_subset_select,
-                                       dim3(grid_for(uint64_t(nbig) * c.S, 65535)), dim3(NT), 0,
-                                       st, c, level, nbig);
+                                       dim3(grid_for(uint64_t(nbig) * c.S / NW + 1, 65535)),
+                                       dim3(NT), 0, st, c, level, nbig);
                 });
                 P.run(KD_PROF_PICK, 0, 0, [&] {
                     hipLaunchKernelGGL(k_subset_mean, dim3(grid_for(nbig / NT + 1, 4096)),
