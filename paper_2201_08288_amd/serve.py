@@ -33,7 +33,7 @@ def footprint_bytes(n, d, leaf_size, num_queries=0):
 
 class Request:
     __slots__ = ("rid", "points", "queries", "t_arrive", "t_admit", "t_done", "tree", "leaves",
-                 "status", "bytes", "event")
+                 "status", "bytes", "event", "ready")
 
     def __init__(self, rid, points, queries, t_arrive):
         self.rid, self.points, self.queries, self.t_arrive = rid, points, queries, t_arrive
@@ -42,6 +42,7 @@ class Request:
         self.status = None
         self.bytes = 0
         self.event = threading.Event()
+        self.ready = None  # device event: the inputs are complete on the submitting stream
 
 
 class ServeEngine:
@@ -65,6 +66,11 @@ class ServeEngine:
 
     # -------------------------------------------------------------- admission
     def submit(self, req):
+        if getattr(req.points, "is_cuda", False):
+            # the build runs on a worker stream: it waits for the work that
+            # produced the inputs on the caller's current stream
+            req.ready = torch.cuda.Event()
+            req.ready.record(torch.cuda.current_stream(req.points.device))
         d, n = req.points.shape
         nq = 0 if req.queries is None else req.queries.shape[1]
         req.bytes = footprint_bytes(n, d, self.params.get("leaf_size", 32), nq)
@@ -103,6 +109,9 @@ class ServeEngine:
         """One batched build of every request of the batch, then each
         request's lookups, all on this worker's stream."""
         with torch.cuda.stream(stream):
+            for r in batch:
+                if r.ready is not None:
+                    stream.wait_event(r.ready)
             trees = kdtree.build_batched([r.points for r in batch], stream=stream, **self.params)
             for r, t in zip(batch, trees):
                 r.tree = t

@@ -95,3 +95,36 @@ def test_oversize_request_rejected_others_complete():
         assert eng.used == 0
     finally:
         eng.close()
+
+
+def test_inputs_still_being_written_when_submitted():
+    """Points produced on the caller's stream right before submit (no host
+    sync): the worker stream waits for them, so results equal the alone
+    builds."""
+    import torch
+
+    from paper_2201_08288_amd import kdtree, serve
+    print("case serving stream handoff", flush=True)
+    params = dict(leaf_size=32, num_subsets=16)
+    eng = serve.ServeEngine(params, cap_bytes=8 << 30, workers=2)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    reqs, data = [], []
+    try:
+        for k in range(12):
+            x = torch.randn((3, 50000 + 1000 * k), generator=gen, device="cuda")
+            x = x * 3.0 + 1.0  # more work queued on the caller's stream
+            data.append(x)
+            r = serve.Request(k, x, None, time.perf_counter())
+            eng.submit(r)
+            reqs.append(r)
+        for r in reqs:
+            assert r.event.wait(60)
+    finally:
+        eng.close()
+    for r, x in zip(reqs, data):
+        assert r.status == kdtree.KD_OK
+        alone = kdtree.build(x, **params)
+        torch.cuda.synchronize()
+        a, b = alone.to_numpy(), r.tree.to_numpy()
+        for f in FIELDS:
+            assert np.array_equal(a[f], b[f]), (r.rid, f)
