@@ -117,3 +117,27 @@ def test_strided_input_and_no_points_out():
     t = kdtree.build(big.cuda()[:, :10000], leaf_size=8, points_out=False)
     g = t.to_numpy()
     assert_same_tree(g, oracle_tree(x, leaf_size=8))
+
+
+def test_workspace_too_small_rejected_before_any_work():
+    import ctypes
+
+    import torch
+
+    from paper_2201_08288_amd import kdtree
+    print("case small workspace", flush=True)
+    x = torch.from_numpy(synth.uniform24(10000, 3, seed=2)).cuda()
+    prm = kdtree.make_params(leaf_size=16)
+    cap, ws = kdtree.tree_bounds(10000, 3, prm)
+    prm.node_capacity = cap
+    tree = kdtree.KDTree(10000, 3, cap, x.device)
+    tree.hdr.fill_(7)
+    small = torch.empty(ws - 1, dtype=torch.uint8, device="cuda")
+    st = kdtree.lib().kd_build(x.data_ptr(), 10000, 3, 10000, ctypes.byref(prm),
+                               ctypes.byref(tree.struct), small.data_ptr(), small.numel(), None)
+    assert st == kdtree.KD_ENOMEM
+    torch.cuda.synchronize()
+    assert (tree.hdr.cpu() == 7).all()  # nothing was enqueued
+    # a null argument is rejected the same way
+    assert kdtree.lib().kd_build(None, 10000, 3, 10000, ctypes.byref(prm), ctypes.byref(tree.struct),
+                                 small.data_ptr(), small.numel(), None) == kdtree.KD_EINVAL
