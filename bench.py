@@ -42,6 +42,8 @@ def stored_traffic(workload, rule, kernel):
         return None
     e = t.get("entries", {}).get(f"{workload}/{rule}/{kernel}")
     return None if e is None else e["bytes_per_launch"]
+
+
 RULES = {"exact": 0, "fourier": 1, "subset": 2}
 KEYS = {"cyclic": 0, "maxvar": 1}
 
@@ -194,6 +196,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch shapes instead of kd_autotune's choice")
+    ap.add_argument("--tuning", default=None, metavar="HIST,SCATTER,SMALL",
+                    help="use these launch shapes (workgroup counts, 0 = default) instead of "
+                         "kd_autotune's choice")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (a kernel of known "
                          "traffic for calibrating hardware byte counters)")
@@ -224,7 +229,11 @@ def main():
     pool_t = None if pool is None else torch.from_numpy(pool.view(np.int32)).to(dev)
     kw = tree_kwargs(w, args.rule)
     tuning = kdtree.get_tuning()
-    if not args.no_autotune:
+    if args.tuning is not None:
+        h, sc, sm = (int(v) for v in args.tuning.split(","))
+        kdtree.set_tuning(h, sc, sm)
+        tuning = kdtree.get_tuning()
+    elif not args.no_autotune:
         log("[bench] autotune")
         tuning = kdtree.autotune(xt, subset_pool=pool_t, **kw)
     tree = kdtree.build(xt, subset_pool=pool_t, **kw)
