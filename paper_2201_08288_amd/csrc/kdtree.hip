@@ -213,7 +213,7 @@ __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
         in.points = base[2];
         in.big_points = base[3];
         in.num_big = base[4];
-        *c.info = in;
+        c.info[0] = in;
         c.bucket_first[0] = 0;
     }
 }
@@ -271,8 +271,9 @@ __global__ __launch_bounds__(NT) void k_copy_leafroots(Ctx c) {
 // ------------------------------------------------------------ kernels: per level
 
 // a2 and per-level state: key coordinate, select start, zeroed accumulators.
-__global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level, uint32_t ncells) {
+__global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level) {
     const uint32_t cur = level & 1, nxt = cur ^ 1;
+    const uint32_t ncells = c.info[level].num_cells;
     for (uint32_t ci = blockIdx.x * NT + threadIdx.x; ci < ncells; ci += gridDim.x * NT) {
         const Cell cl = c.cells[cur][ci];
         const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
@@ -364,20 +365,20 @@ __device__ __forceinline__ TileView tile_view(const Ctx &c, uint32_t cur, uint32
 }
 
 // Cell of every tile of the level's large cells.
-__global__ __launch_bounds__(NT) void k_tile_map(Ctx c, uint32_t level, uint32_t ncells,
-                                                 uint32_t ntiles) {
+__global__ __launch_bounds__(NT) void k_tile_map(Ctx c, uint32_t level) {
     const uint32_t cur = level & 1;
+    const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
     for (uint32_t t = blockIdx.x * NT + threadIdx.x; t < ntiles; t += gridDim.x * NT)
         c.tile_cell[t] = find_tile_cell(c.cells[cur], ncells, t);
 }
 
 // EXACT, large cells: digit histograms of a run of consecutive tiles in LDS,
 // added into the cell's histogram whenever the run moves to another cell.
-__global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t pass,
-                                                 uint32_t ncells, uint32_t ntiles) {
+__global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t pass) {
     __shared__ uint32_t h[BIG_BINS];
     __shared__ uint32_t s_cell;
     const uint32_t cur = level & 1;
+    const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
     const int shift = big_shift(pass);
     const uint32_t dmask = (1u << big_bits(pass)) - 1u;
     const uint32_t pmask = pass == 0 ? 0u : (~0u << (shift + big_bits(pass)));
@@ -423,9 +424,9 @@ __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t
 
 // EXACT, large cells: pick the digit that holds the target rank.  After the
 // last pass the candidate is the lower median and lt / le are exact.
-__global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t pass,
-                                                 uint32_t nbig) {
+__global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t pass) {
     constexpr int PER = BIG_BINS / NT;
+    const uint32_t nbig = c.info[level].num_big;
     __shared__ uint32_t sh[NW + 1];
     __shared__ uint32_t s_bin, s_below, s_cnt;
     const int shift = big_shift(pass);
@@ -469,11 +470,11 @@ __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t
 }
 
 // FOURIER, large cells: smallest and largest key of every cell.
-__global__ __launch_bounds__(NT) void k_big_minmax(Ctx c, uint32_t level, uint32_t ncells,
-                                                   uint32_t ntiles) {
+__global__ __launch_bounds__(NT) void k_big_minmax(Ctx c, uint32_t level) {
     __shared__ uint32_t s_cell;
     __shared__ uint32_t sh[2 * NW];
     const uint32_t cur = level & 1;
+    const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileView v = tile_view(c, cur, ncells, t, &s_cell);
         const CellRes r = c.res[v.ci];
@@ -518,11 +519,11 @@ __device__ __forceinline__ void reduce_moments(long long *acc, unsigned long lon
 }
 
 // FOURIER, large cells: the map step (quantized harmonics summed per cell).
-__global__ __launch_bounds__(NT) void k_big_moments(Ctx c, uint32_t level, uint32_t ncells,
-                                                    uint32_t ntiles) {
+__global__ __launch_bounds__(NT) void k_big_moments(Ctx c, uint32_t level) {
     __shared__ uint32_t s_cell;
     __shared__ unsigned long long sh64[NW * 2 * FCHUNK];
     const uint32_t cur = level & 1;
+    const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
     const int J = int(c.J);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileView v = tile_view(c, cur, ncells, t, &s_cell);
@@ -549,18 +550,19 @@ __global__ __launch_bounds__(NT) void k_big_moments(Ctx c, uint32_t level, uint3
 }
 
 // FOURIER, large cells: solve Eq. (2) for the candidate (one wave per cell).
-__global__ __launch_bounds__(NT) void k_big_fsolve(Ctx c, uint32_t level, uint32_t nbig) {
-    const uint32_t b = blockIdx.x * NW + wave();
-    if (b >= nbig) return;
-    const uint32_t ci = c.big_list[b];
-    const uint32_t lo = c.mm[2 * b], hi = c.mm[2 * b + 1];
-    uint32_t m = lo;
-    if (lo != hi) {
-        const long long *mom = c.mom + uint64_t(b) * 2 * FOURIER_JMAX;
-        m = fourier_solve_wave(mom, mom + FOURIER_JMAX, int(c.J), lo, hi,
-                               fourier_exponent(lo, hi), c.trig);
+__global__ __launch_bounds__(NT) void k_big_fsolve(Ctx c, uint32_t level) {
+    const uint32_t nbig = c.info[level].num_big;
+    for (uint32_t b = blockIdx.x * NW + wave(); b < nbig; b += gridDim.x * NW) {
+        const uint32_t ci = c.big_list[b];
+        const uint32_t lo = c.mm[2 * b], hi = c.mm[2 * b + 1];
+        uint32_t m = lo;
+        if (lo != hi) {
+            const long long *mom = c.mom + uint64_t(b) * 2 * FOURIER_JMAX;
+            m = fourier_solve_wave(mom, mom + FOURIER_JMAX, int(c.J), lo, hi,
+                                   fourier_exponent(lo, hi), c.trig);
+        }
+        if (lane() == 0) c.res[ci].cand = m;
     }
-    if (lane() == 0) c.res[ci].cand = m;
 }
 
 // Subset boundaries of a cell (§3.2: any partition; App. C.2: {r, X_r}).
@@ -601,8 +603,9 @@ __device__ __forceinline__ uint32_t subset_mean(const uint32_t *B, const uint32_
 }
 
 // SUBSET, large cells: subset bounds of every cell.
-__global__ __launch_bounds__(NT) void k_big_bounds(Ctx c, uint32_t level, uint32_t nbig) {
+__global__ __launch_bounds__(NT) void k_big_bounds(Ctx c, uint32_t level) {
     const uint32_t cur = level & 1;
+    const uint32_t nbig = c.info[level].num_big;
     for (uint32_t b = blockIdx.x * NT + threadIdx.x; b < nbig; b += gridDim.x * NT) {
         const uint32_t ci = c.big_list[b];
         const Cell cl = c.cells[cur][ci];
@@ -616,11 +619,12 @@ __global__ __launch_bounds__(NT) void k_big_bounds(Ctx c, uint32_t level, uint32
 // to one wave each (keys staged in the wave's part of LDS), larger ones to the
 // whole workgroup afterwards.
 constexpr uint32_t WAVE_SUB = 1024;
-__global__ __launch_bounds__(NT) void k_subset_select(Ctx c, uint32_t level, uint32_t nbig) {
+__global__ __launch_bounds__(NT) void k_subset_select(Ctx c, uint32_t level) {
     __shared__ uint32_t keys[SMALL_MAX + SMALL_MAX / 32];
     __shared__ uint32_t h[NW][NBINS];
     __shared__ uint32_t sh[NW + 1], s3[3];
     const uint32_t cur = level & 1;
+    const uint32_t nbig = c.info[level].num_big;
     const int w = wave(), l = lane();
     const uint64_t jobs = uint64_t(nbig) * c.S;
     auto subset = [&](uint64_t job, const uint32_t *&col, uint32_t &ns) {
@@ -681,7 +685,8 @@ __global__ __launch_bounds__(NT) void k_subset_select(Ctx c, uint32_t level, uin
 // into the subset's histogram, and one workgroup per subset picks the digit.
 constexpr uint32_t SEG_FAN = 64;
 
-__global__ __launch_bounds__(NT) void k_seg_list(Ctx c, uint32_t nbig) {
+__global__ __launch_bounds__(NT) void k_seg_list(Ctx c, uint32_t level) {
+    const uint32_t nbig = c.info[level].num_big;
     const uint64_t jobs = uint64_t(nbig) * c.S;
     for (uint64_t job = blockIdx.x * uint64_t(NT) + threadIdx.x; job < jobs;
          job += uint64_t(gridDim.x) * NT) {
@@ -775,8 +780,9 @@ __global__ __launch_bounds__(NT) void k_seg_pick(Ctx c, uint32_t pass) {
 }
 
 // SUBSET, large cells: the weighted mean (one thread per cell).
-__global__ __launch_bounds__(NT) void k_subset_mean(Ctx c, uint32_t level, uint32_t nbig) {
+__global__ __launch_bounds__(NT) void k_subset_mean(Ctx c, uint32_t level) {
     const uint32_t cur = level & 1;
+    const uint32_t nbig = c.info[level].num_big;
     for (uint32_t b = blockIdx.x * NT + threadIdx.x; b < nbig; b += gridDim.x * NT) {
         const uint32_t ci = c.big_list[b];
         const Cell cl = c.cells[cur][ci];
@@ -786,11 +792,11 @@ __global__ __launch_bounds__(NT) void k_subset_mean(Ctx c, uint32_t level, uint3
 }
 
 // a6, large cells: per tile, keys below and at the candidate.
-__global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level, uint32_t ncells,
-                                                  uint32_t ntiles) {
+__global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level) {
     __shared__ uint32_t s_cell;
     __shared__ uint32_t sh[NW + 1];
     const uint32_t cur = level & 1;
+    const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileView v = tile_view(c, cur, ncells, t, &s_cell);
         const CellRes r = c.res[v.ci];
@@ -821,9 +827,10 @@ __global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level, uint32_
 }
 
 // a6, large cells: tie rule, then the exclusive scan of the chosen tile counts.
-__global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level, uint32_t nbig) {
+__global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level) {
     __shared__ uint32_t sh[NW + 1];
     const uint32_t cur = level & 1;
+    const uint32_t nbig = c.info[level].num_big;
     for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
         const uint32_t ci = c.big_list[b];
         const Cell cl = c.cells[cur][ci];
@@ -882,12 +889,13 @@ __global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level, uint32
 // staged key column; each column (and the permutation) is then permuted in
 // LDS and written as two contiguous runs, the left and right children's.
 template <bool MAXVAR>
-__global__ __launch_bounds__(NT, MAXVAR ? 3 : 4) void k_big_scatter(Ctx c, uint32_t level, uint32_t ntiles) {
+__global__ __launch_bounds__(NT, MAXVAR ? 3 : 4) void k_big_scatter(Ctx c, uint32_t level) {
     __shared__ uint32_t stage0[PADDED];  // staged keys / ranks, then a column buffer
     __shared__ uint32_t stage1[TILE];
     __shared__ uint32_t sh[NW + 1];
     __shared__ unsigned long long vacc[MAXVAR ? 16 : 1][6];  // a group of 16 columns
     const uint32_t cur = level & 1, nxt = cur ^ 1;
+    const uint32_t ntiles = c.info[level].num_tiles;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileDesc D = c.tiles[__builtin_amdgcn_readfirstlane(t)];
         const KD_CONST TreeDesc &T = cref(&c.trees[D.tree]);
@@ -1373,8 +1381,7 @@ __device__ void subset_cells(const Ctx &c, uint32_t level, const uint32_t *keys,
 }
 
 template <int RULE, bool MAXVAR>
-__global__ __launch_bounds__(NT, MAXVAR ? (RULE != KD_SPLIT_FOURIER ? 3 : 1) : (RULE == KD_SPLIT_EXACT ? 4 : 1)) void k_small(Ctx c, uint32_t level, uint32_t ncells,
-                                              uint32_t nbuckets) {
+__global__ __launch_bounds__(NT, MAXVAR ? (RULE != KD_SPLIT_FOURIER ? 3 : 1) : (RULE == KD_SPLIT_EXACT ? 4 : 1)) void k_small(Ctx c, uint32_t level) {
     constexpr int SC = chunk_cells<MAXVAR>();
     // the column buffer is idle while cells are split: the select scratch
     // (digit histograms, FOURIER moments, reductions) shares its space
@@ -1404,6 +1411,9 @@ __global__ __launch_bounds__(NT, MAXVAR ? (RULE != KD_SPLIT_FOURIER ? 3 : 1) : (
     extern __shared__ uint32_t dyn[];  // SUBSET: bounds[S + 1], medians[S]
     const uint32_t cur = level & 1, nxt = cur ^ 1;
     const int w = wave(), l = lane();
+    const LevelInfo I = c.info[level];
+    const uint32_t ncells = I.num_cells;
+    const uint32_t nbuckets = (I.points - I.big_points + TILE - 1) / TILE;  // small-point buckets
     for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
         uint32_t pos = c.bucket_first[b];
         const uint32_t v1 = (b + 1) * uint32_t(TILE);
@@ -1677,8 +1687,9 @@ __device__ __forceinline__ void emit_counts(const Ctx &c, uint32_t level, uint32
     }
 }
 
-__global__ __launch_bounds__(NT) void k_emit_sum(Ctx c, uint32_t level, uint32_t ncells) {
+__global__ __launch_bounds__(NT) void k_emit_sum(Ctx c, uint32_t level) {
     __shared__ uint32_t sh[NW + 1];
+    const uint32_t ncells = c.info[level].num_cells;
     uint32_t cnt[EMIT_COUNTERS];
     emit_counts(c, level, blockIdx.x * NT + threadIdx.x, ncells, cnt);
     for (int k = 0; k < EMIT_COUNTERS; k++) {
@@ -1688,8 +1699,9 @@ __global__ __launch_bounds__(NT) void k_emit_sum(Ctx c, uint32_t level, uint32_t
     }
 }
 
-__global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t ncells, uint32_t nblocks) {
+__global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t level, uint32_t nblocks) {
     __shared__ uint32_t sh[NW + 1];
+    const uint32_t ncells = c.info[level].num_cells;
     uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t b0 = 0; b0 < nblocks; b0 += NT) {
         const uint32_t b = b0 + threadIdx.x;
@@ -1710,12 +1722,13 @@ __global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t ncells, uint32
         in.points = base[3];
         in.big_points = base[4];
         in.num_big = base[5];
-        *c.info = in;
+        c.info[level + 1] = in;
     }
 }
 
-__global__ __launch_bounds__(NT) void k_emit_prefix(Ctx c, uint32_t level, uint32_t ncells) {
+__global__ __launch_bounds__(NT) void k_emit_prefix(Ctx c, uint32_t level) {
     __shared__ uint32_t sh[NW + 1];
+    const uint32_t ncells = c.info[level].num_cells;
     const uint32_t ci = blockIdx.x * NT + threadIdx.x;
     uint32_t cnt[EMIT_COUNTERS];
     emit_counts(c, level, ci, ncells, cnt);
@@ -1802,7 +1815,8 @@ __device__ __forceinline__ void emit_cell(const Ctx &c, uint32_t level, uint32_t
         slot++;
     }
 }
-__global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level, uint32_t ncells) {
+__global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level) {
+    const uint32_t ncells = c.info[level].num_cells;
     const uint32_t ci = blockIdx.x * NT + threadIdx.x;
     if (ci < ncells) emit_cell(c, level, ci);
 }
@@ -1811,8 +1825,9 @@ __global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level, uint32
 // cells: counts and their prefix (each thread takes consecutive cells), the
 // totals, the per-tree update, then the node records and next cells.
 constexpr uint32_t EMIT_ONE_MAX = 2048;
-__global__ __launch_bounds__(NT) void k_emit_one(Ctx c, uint32_t level, uint32_t ncells) {
+__global__ __launch_bounds__(NT) void k_emit_one(Ctx c, uint32_t level) {
     __shared__ uint32_t sh[NW + 1];
+    const uint32_t ncells = c.info[level].num_cells;
     constexpr uint32_t PER = EMIT_ONE_MAX / NT;
     const uint32_t c0 = threadIdx.x * PER;
     uint32_t cnt[PER][EMIT_COUNTERS];
@@ -1839,7 +1854,7 @@ __global__ __launch_bounds__(NT) void k_emit_one(Ctx c, uint32_t level, uint32_t
         in.points = tot[3];
         in.big_points = tot[4];
         in.num_big = tot[5];
-        *c.info = in;
+        c.info[level + 1] = in;
     }
     __threadfence_block();
     __syncthreads();
@@ -2021,7 +2036,7 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     L.buckets = B.take((all_points / TILE + 2) * 4);
     // at most one large subset per SMALL_MAX + 1 points
     L.segs = B.take(subset ? (all_points / (SMALL_MAX + 1) + 2) * 4 * (3 + NBINS) + 256 : 0);
-    L.info = B.take(sizeof(LevelInfo));
+    L.info = B.take(sizeof(LevelInfo) * (MAX_LEVELS + 1));
     L.per_tree.resize(T);
     for (uint32_t t = 0; t < T; t++) {
         TreeLayout &tl = L.per_tree[t];
@@ -2125,6 +2140,68 @@ struct HostTree {
     uint32_t d;
     const kd_tree *out;
 };
+
+// Level totals read back by the host: a pinned slot per level and a ring of
+// events, made once per thread and device and kept until the process ends.
+// The level loop waits for the totals of the level LEVEL_LAG before the one
+// it is about to enqueue, so the device always has that many levels queued;
+// launch shapes come from bounds derived from the last totals read.
+constexpr uint32_t LEVEL_LAG = 2;
+constexpr uint32_t READBACK_RING = 4;
+static_assert(LEVEL_LAG < READBACK_RING, "an event is waited on before it is recorded again");
+constexpr int READBACK_DEVICES = 64;
+
+struct LevelReadback {
+    LevelInfo *host = nullptr;  // MAX_LEVELS + 1 pinned slots
+    hipEvent_t ev[READBACK_RING] = {};
+};
+
+LevelReadback *level_readback() {
+    thread_local LevelReadback per_device[READBACK_DEVICES];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= READBACK_DEVICES) return nullptr;
+    LevelReadback &r = per_device[dev];
+    if (!r.host) {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, sizeof(LevelInfo) * (MAX_LEVELS + 1), hipHostMallocDefault) !=
+            hipSuccess)
+            return nullptr;
+        for (uint32_t k = 0; k < READBACK_RING; k++)
+            if (hipEventCreateWithFlags(&r.ev[k], hipEventDisableTiming) != hipSuccess) {
+                for (uint32_t j = 0; j < k; j++) (void)hipEventDestroy(r.ev[j]);
+                (void)hipHostFree(h);
+                return nullptr;
+            }
+        r.host = static_cast<LevelInfo *>(h);
+    }
+    return &r;
+}
+
+// Upper bounds of a level's totals from the totals `K` of a level `gap`
+// levels earlier (gap 0: K itself).  Cells hold more than leaf_size points
+// and at most double per level; large cells hold more than SMALL_MAX points;
+// a cell of s points spans at most s / TILE + 1 tiles.
+struct LevelBound {
+    uint64_t cells, tiles, big, big_points, small_points;
+};
+
+LevelBound level_bound(const LevelInfo &K, uint32_t gap, uint32_t leaf_size, const Layout &L) {
+    LevelBound b;
+    if (gap == 0) {
+        b = LevelBound{K.num_cells, K.num_tiles, K.num_big, K.big_points,
+                       uint64_t(K.points) - K.big_points};
+    } else {
+        b.cells = std::min<uint64_t>(uint64_t(K.num_cells) << gap, K.points / (uint64_t(leaf_size) + 1));
+        b.big = std::min<uint64_t>(uint64_t(K.num_big) << gap, K.big_points / (SMALL_MAX + 1));
+        b.big_points = b.big ? K.big_points : 0;
+        b.tiles = b.big ? b.big_points / TILE + b.big : 0;
+        b.small_points = K.points;
+    }
+    b.cells = std::min(b.cells, L.max_cells);
+    b.big = std::min(b.big, L.max_big);
+    b.tiles = std::min(b.tiles, L.max_tiles);
+    return b;
+}
 
 // The level loop over every tree of the build.
 // Process-wide launch shapes (set by kd_set_tuning / kd_autotune).
@@ -2275,96 +2352,122 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
             : 0;
     static_assert(sizeof(uint32_t) * (2 * MAX_SUBSETS + 1) + 64 * 1024 <= 160 * 1024,
                   "small-cell kernel LDS");
-    LevelInfo hi{};
+    LevelReadback *rb = level_readback();
+    if (!rb) return KD_EDEVICE;
+    auto read_back = [&](uint32_t k) {  // enqueue the copy of level k's totals
+        return hipMemcpyAsync(&rb->host[k], c.info + k, sizeof(LevelInfo), hipMemcpyDeviceToHost,
+                              st) == hipSuccess &&
+               hipEventRecord(rb->ev[k % READBACK_RING], st) == hipSuccess;
+    };
+    auto fail = [&]() {
+        (void)hipStreamSynchronize(st);
+        return KD_EDEVICE;
+    };
+    if (!read_back(0)) return fail();
+    // level 0 on the host: one root cell per tree with more than leaf_size points
+    LevelInfo K{};
+    for (uint32_t t = 0; t < ntrees; t++) {
+        if (n[t] <= p->leaf_size || c.max_depth == 0) continue;
+        K.num_cells++;
+        K.points += uint32_t(n[t]);
+        if (n[t] > uint64_t(SMALL_MAX)) {
+            K.num_tiles += uint32_t((n[t] + TILE - 1) / TILE);
+            K.big_points += uint32_t(n[t]);
+            K.num_big++;
+        }
+    }
+    uint32_t known = 0, next_read = 0;
+    // profiled builds wait for every level's totals: exact shapes and byte counts
+    const uint32_t lag = prof ? 0u : LEVEL_LAG;
+    const uint32_t level_cap = std::min<uint32_t>(MAX_LEVELS, c.max_depth);
     uint32_t levels_run = 0;
-    for (uint32_t level = 0;; level++) {
-        if (hipMemcpyAsync(&hi, c.info, sizeof(hi), hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return KD_EDEVICE;
-        if (hi.num_cells == 0 || level >= MAX_LEVELS) break;
+    for (uint32_t level = 0; level < level_cap; level++) {
+        while (next_read + lag <= level) {
+            if (hipEventSynchronize(rb->ev[next_read % READBACK_RING]) != hipSuccess) return fail();
+            K = rb->host[next_read];
+            known = next_read++;
+        }
+        if (K.num_cells == 0) break;  // no cells at `known`, none after it
         levels_run++;
-        const uint32_t nc = hi.num_cells, ntl = hi.num_tiles, nbig = hi.num_big;
-        const uint64_t bigp = hi.big_points, smallp = hi.points - hi.big_points;
+        const LevelBound B = level_bound(K, level - known, p->leaf_size, L);
+        const uint64_t nc = B.cells, ntl = B.tiles, nbig = B.big;
+        const uint64_t bigp = B.big_points, smallp = B.small_points;
         P.run(KD_PROF_OTHER, 0, 0, [&] {
             hipLaunchKernelGGL(k_level_init, dim3(grid_for(nc / NT + 1, 4096)), dim3(NT), 0, st,
-                               c, level, nc);
+                               c, level);
         });
-        if (ntl > 0) {
+        if (nbig > 0) {
             P.run(KD_PROF_OTHER, 0, 0, [&] {
                 hipLaunchKernelGGL(k_tile_map, dim3(grid_for(ntl / NT + 1, 4096)), dim3(NT), 0, st,
-                                   c, level, nc, ntl);
+                                   c, level);
             });
             if (p->split_rule == KD_SPLIT_EXACT) {
                 for (uint32_t pass = 0; pass < uint32_t(BIG_PASSES); pass++) {
                     P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
                         hipLaunchKernelGGL(k_big_hist, dim3(grid_for(ntl, hist_grid)), dim3(NT), 0,
-                                           st, c, level, pass, nc, ntl);
+                                           st, c, level, pass);
                     });
                     P.run(KD_PROF_PICK, 0, 0, [&] {
                         hipLaunchKernelGGL(k_big_pick, dim3(grid_for(nbig, 65535)), dim3(NT), 0,
-                                           st, c, level, pass, nbig);
+                                           st, c, level, pass);
                     });
                 }
             } else if (p->split_rule == KD_SPLIT_FOURIER) {
                 P.run(KD_PROF_SELECT, bigp, 8 * bigp, [&] {
                     hipLaunchKernelGGL(k_big_minmax, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st,
-                                       c, level, nc, ntl);
+                                       c, level);
                     hipLaunchKernelGGL(k_big_moments, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st,
-                                       c, level, nc, ntl);
+                                       c, level);
                 });
                 P.run(KD_PROF_PICK, 0, 0, [&] {
-                    hipLaunchKernelGGL(k_big_fsolve, dim3((nbig + NW - 1) / NW), dim3(NT), 0, st,
-                                       c, level, nbig);
+                    hipLaunchKernelGGL(k_big_fsolve, dim3(grid_for((nbig + NW - 1) / NW, 65535)),
+                                       dim3(NT), 0, st, c, level);
                 });
             } else {
+                // subsets above SMALL_MAX points (at most one per SMALL_MAX + 1
+                // large-cell points): segmented passes over many workgroups,
+                // which read the list's length on the device; the rest: one
+                // workgroup or wave each, in LDS
+                const uint64_t nseg = std::min<uint64_t>(bigp / (SMALL_MAX + 1), nbig * c.S);
                 P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
                     hipLaunchKernelGGL(k_big_bounds, dim3(grid_for(nbig / NT + 1, 4096)), dim3(NT),
-                                       0, st, c, level, nbig);
-                    // subsets above SMALL_MAX points: segmented passes over many
-                    // workgroups; the rest: one workgroup each, in LDS
+                                       0, st, c, level);
                     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(NT), 0, st, c.seg_count, 1ull, 0u);
-                    hipLaunchKernelGGL(k_seg_list, dim3(grid_for(uint64_t(nbig) * c.S / NT + 1, 4096)),
-                                       dim3(NT), 0, st, c, nbig);
-                    uint32_t nseg = 0;
-                    if (hipMemcpyAsync(&nseg, c.seg_count, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                        hipStreamSynchronize(st) != hipSuccess)
-                        nseg = uint32_t(bigp / (SMALL_MAX + 1) + 1);  // bound; kernels read the count
+                    hipLaunchKernelGGL(k_seg_list, dim3(grid_for(nbig * c.S / NT + 1, 4096)),
+                                       dim3(NT), 0, st, c, level);
                     for (uint32_t pass = 0; nseg > 0 && pass < uint32_t(RPASSES); pass++) {
-                        hipLaunchKernelGGL(k_seg_hist, dim3(grid_for(uint64_t(nseg) * SEG_FAN, 65535)),
+                        hipLaunchKernelGGL(k_seg_hist, dim3(grid_for(nseg * SEG_FAN, 65535)),
                                            dim3(NT), 0, st, c, level, pass);
-                        hipLaunchKernelGGL(k_seg_pick, dim3(grid_for(nseg, 65535)), dim3(NT), 0, st, c,
-                                           pass);
+                        hipLaunchKernelGGL(k_seg_pick, dim3(grid_for(nseg, 65535)), dim3(NT), 0, st,
+                                           c, pass);
                     }
-                    hipLaunchKernelGGL(k_subset_select,
-                                       dim3(grid_for(uint64_t(nbig) * c.S / NW + 1, 65535)),
-                                       dim3(NT), 0, st, c, level, nbig);
+                    hipLaunchKernelGGL(k_subset_select, dim3(grid_for(nbig * c.S / NW + 1, 65535)),
+                                       dim3(NT), 0, st, c, level);
                 });
                 P.run(KD_PROF_PICK, 0, 0, [&] {
                     hipLaunchKernelGGL(k_subset_mean, dim3(grid_for(nbig / NT + 1, 4096)),
-                                       dim3(NT), 0, st, c, level, nbig);
+                                       dim3(NT), 0, st, c, level);
                 });
             }
             P.run(KD_PROF_COUNT, bigp, 4 * bigp, [&] {
                 hipLaunchKernelGGL(k_big_count, dim3(grid_for(ntl, tile_grid)), dim3(NT), 0, st, c,
-                                   level, nc, ntl);
+                                   level);
                 hipLaunchKernelGGL(k_big_decide, dim3(grid_for(nbig, 65535)), dim3(NT), 0, st, c,
-                                   level, nbig);
+                                   level);
             });
             P.run(KD_PROF_BIG_SCATTER, bigp, scatter_avg_bpp * bigp, [&] {
                 if (maxvar)
                     hipLaunchKernelGGL(k_big_scatter<true>, dim3(grid_for(ntl, tile_grid)), dim3(NT), 0,
-                                       st, c, level, ntl);
+                                       st, c, level);
                 else
                     hipLaunchKernelGGL(k_big_scatter<false>, dim3(grid_for(ntl, tile_grid)), dim3(NT),
-                                       0, st, c, level, ntl);
+                                       0, st, c, level);
             });
         }
         if (smallp > 0) {
             P.run(KD_PROF_SMALL, smallp, scatter_avg_bpp * smallp, [&] {
-                const uint32_t nbk = uint32_t((smallp + TILE - 1) / TILE);
-                const dim3 g(grid_for(nbk, small_grid));
-#define KD_SMALL(R, M)                                                                    \
-    hipLaunchKernelGGL((k_small<R, M>), g, dim3(NT), small_dyn, st, c, level, nc, nbk)
+                const dim3 g(grid_for((smallp + TILE - 1) / TILE, small_grid));
+#define KD_SMALL(R, M) hipLaunchKernelGGL((k_small<R, M>), g, dim3(NT), small_dyn, st, c, level)
                 switch (p->split_rule * 2 + (maxvar ? 1 : 0)) {
                     case 0: KD_SMALL(KD_SPLIT_EXACT, false); break;
                     case 1: KD_SMALL(KD_SPLIT_EXACT, true); break;
@@ -2376,20 +2479,20 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
 #undef KD_SMALL
             });
         }
-        const uint32_t nb = (nc + NT - 1) / NT;
+        const uint32_t nb = uint32_t((nc + NT - 1) / NT);
         P.run(KD_PROF_EMIT, 0, 0, [&] {
             if (nc <= EMIT_ONE_MAX) {
-                hipLaunchKernelGGL(k_emit_one, dim3(1), dim3(NT), 0, st, c, level, nc);
+                hipLaunchKernelGGL(k_emit_one, dim3(1), dim3(NT), 0, st, c, level);
                 return;
             }
-            hipLaunchKernelGGL(k_emit_sum, dim3(nb), dim3(NT), 0, st, c, level, nc);
-            hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(NT), 0, st, c, nc, nb);
-            hipLaunchKernelGGL(k_emit_prefix, dim3(nb), dim3(NT), 0, st, c, level, nc);
+            hipLaunchKernelGGL(k_emit_sum, dim3(nb), dim3(NT), 0, st, c, level);
+            hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(NT), 0, st, c, level, nb);
+            hipLaunchKernelGGL(k_emit_prefix, dim3(nb), dim3(NT), 0, st, c, level);
             hipLaunchKernelGGL(k_emit_trees, dim3(grid_for(ntrees / NT + 1, 1024)), dim3(NT), 0,
                                st, c, level);
-            hipLaunchKernelGGL(k_emit_write, dim3(nb), dim3(NT), 0, st, c, level, nc);
+            hipLaunchKernelGGL(k_emit_write, dim3(nb), dim3(NT), 0, st, c, level);
         });
-        KD_LAUNCH_CHECK();
+        if (hipGetLastError() != hipSuccess || !read_back(level + 1)) return fail();
     }
     P.run(KD_PROF_OTHER, 0, 0, [&] {
         for (int l = int(levels_run); l >= 0; l--)
