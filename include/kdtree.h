@@ -185,8 +185,8 @@ kd_status kd_query_leaf(const kd_tree *tree, const float *q, uint64_t nq, uint32
 /* Launch shapes of the level kernels.  They change only how work is spread
  * over workgroups, never the result: every setting builds the same tree bit
  * for bit.  0 in a field means the default (2048 workgroups per digit pass,
- * one workgroup per tile of 4096 points for count and scatter, one per
- * bucket of small cells).                                                  */
+ * one workgroup per tile of 4096 points for count and scatter, 1024
+ * workgroups taking buckets of small cells in turn).                       */
 typedef struct kd_tuning {
     uint32_t hist_blocks;      /* workgroups of a large-cell digit pass            */
     uint32_t scatter_blocks;   /* workgroups of the large-cell count and scatter   */

@@ -50,11 +50,21 @@ struct CellRes {
     uint32_t cand;    // candidate m of the split rule
     uint32_t lt;      // large cells, EXACT: keys below the selected prefix
     uint32_t le;      // ... and at or below the candidate once known
-    uint32_t pad[2];
+    uint32_t crec[2]; // record of each child made by the small-cell subtree kernel (REC_*), 0: none
 };
 constexpr uint32_t RES_SPLIT = 1u;       // the cell is split
 constexpr uint32_t RES_LEFT_LEAF = 2u;   // the left child stops here
 constexpr uint32_t RES_RIGHT_LEAF = 4u;  // the right child stops here
+
+// A cell below the current level whose split the small-cell subtree kernel
+// already found (REC_RESOLVED), or whose key coordinate it already chose.
+// Child links hold REC_RESOLVED | (record index + 1); 0 means no record.
+struct SubRec {
+    uint32_t dim, split, nl, flags;
+    uint32_t crec[2];
+};
+constexpr uint32_t REC_RESOLVED = 0x80000000u;
+constexpr uint32_t REC_INDEX = 0x7fffffffu;
 
 // One tile of a large cell, ready for the scatter (written once the cell's
 // split is known): positions of the tile and of its left and right runs.
@@ -100,7 +110,9 @@ struct TreeState {
 // Totals of the level about to run (read back by the host).
 struct LevelInfo {
     uint32_t num_cells, num_tiles, points, big_points;
-    uint32_t num_big, pad[3];
+    uint32_t num_big;
+    uint32_t resolved;  // points of cells already resolved by the subtree kernel
+    uint32_t pad[2];
 };
 
 // Pointers read from device-side descriptors are generic; accesses through

@@ -19,20 +19,49 @@ struct SelectResult {
     uint32_t le;   // keys smaller or equal
 };
 
-// Workgroup radix select.  KEYS(i) yields key i of n; h: NBINS words of LDS;
-// sh: NW+1 words; s3: 3 words.  Every thread gets the result.
+// The digits of a select start at the highest bit where the smallest and
+// largest key differ: the bits above it are common to every key and need no
+// pass, and the first pass then spreads the keys over at least two bins.
+// Digit p covers bits [pos - width, pos) with pos = top + 1 - RBITS * p.
+__device__ __forceinline__ uint32_t above_mask(int pos) { return pos >= 32 ? 0u : ~0u << pos; }
+
+// Workgroup radix select.  KEYS(i) yields key i of n (n >= 1); h: NBINS words
+// of LDS; sh: NW+1 words; s3: 3 words.  Every thread gets the result.
 template <class KEYS>
 __device__ SelectResult block_select(KEYS keys, uint32_t n, uint32_t k, uint32_t *h,
                                      uint32_t *sh, uint32_t *s3) {
-    uint32_t prefix = 0, lt = 0, cnt = 0;
-    for (int pass = 0; pass < RPASSES; pass++) {
-        const int shift = 32 - RBITS * (pass + 1);
-        const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
+    uint32_t mn = ~0u, mx = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += NT) {
+        const uint32_t u = keys(i);
+        mn = min(mn, u);
+        mx = max(mx, u);
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (threadIdx.x == 0) {
+        s3[0] = ~0u;
+        s3[1] = 0;
+    }
+    __syncthreads();
+    if (lane() == 0) {
+        atomicMin(&s3[0], mn);
+        atomicMax(&s3[1], mx);
+    }
+    __syncthreads();
+    mn = s3[0];
+    mx = s3[1];
+    __syncthreads();
+    if (mn == mx) return SelectResult{mn, 0u, n};
+    const int top = 31 - __builtin_clz(mn ^ mx);
+    uint32_t prefix = mn & above_mask(top + 1), lt = 0, cnt = 0;
+    for (int pos = top + 1; pos > 0; pos -= RBITS) {
+        const int width = pos < RBITS ? pos : RBITS, shift = pos - width;
+        const uint32_t mask = above_mask(pos), dmask = (1u << width) - 1u;
         for (int b = threadIdx.x; b < NBINS; b += NT) h[b] = 0;
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < n; i += NT) {
             uint32_t u = keys(i);
-            if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & (NBINS - 1)], 1u);
+            if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & dmask], 1u);
         }
         __syncthreads();
         uint32_t hv = h[threadIdx.x], tot;
@@ -94,20 +123,31 @@ __device__ uint32_t block_select_global(const uint32_t *col, uint32_t n, uint32_
 }
 
 // Wave radix select over keys[off .. off+n) of an LDS array stored with one
-// pad word per 32 (element i at i + i / 32); h: this wave's NBINS words.
+// pad word per 32 (element i at i + i / 32); h: this wave's NBINS words; n >= 1.
 __device__ uint32_t wave_select(const uint32_t *keys, uint32_t off, uint32_t n, uint32_t k,
                                 uint32_t *h) {
-    uint32_t prefix = 0;
     const int l = lane();
-    for (int pass = 0; pass < RPASSES; pass++) {
-        const int shift = 32 - RBITS * (pass + 1);
-        const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
+    uint32_t mn = ~0u, mx = 0;
+    for (uint32_t i = l; i < n; i += WAVE) {
+        const uint32_t g = off + i;
+        const uint32_t u = keys[g + (g >> 5)];
+        mn = min(mn, u);
+        mx = max(mx, u);
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (mn == mx) return mn;
+    const int top = 31 - __builtin_clz(mn ^ mx);
+    uint32_t prefix = mn & above_mask(top + 1);
+    for (int pos = top + 1; pos > 0; pos -= RBITS) {
+        const int width = pos < RBITS ? pos : RBITS, shift = pos - width;
+        const uint32_t mask = above_mask(pos), dmask = (1u << width) - 1u;
         for (int b = l; b < NBINS; b += WAVE) h[b] = 0;
         wave_sync();
         for (uint32_t i = l; i < n; i += WAVE) {
             const uint32_t g = off + i;
             uint32_t u = keys[g + (g >> 5)];
-            if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & (NBINS - 1)], 1u);
+            if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & dmask], 1u);
         }
         wave_sync();
         // lane l owns bins 4l .. 4l+3

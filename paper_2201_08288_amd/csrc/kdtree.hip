@@ -42,7 +42,7 @@ static_assert(2 * FCHUNK <= NT, "moment chunk fits one workgroup");
 
 namespace {
 
-constexpr int EMIT_COUNTERS = 8;
+constexpr int EMIT_COUNTERS = 9;
 constexpr int EMIT_STRIDE = 12;
 constexpr uint32_t WAVE_CELL_MAX = 1024;  // small cells up to this size: one wave per cell
 // emit counters: splits, active children, tiles, points, large-cell points,
@@ -68,7 +68,12 @@ struct Ctx {
     uint32_t *bucket_first;  // small cells: first cell of each bucket of TILE numbers
     // SUBSET: subsets of more than SMALL_MAX points of the level's large cells
     uint32_t *seg_count, *seg_job, *seg_prefix, *seg_rank, *seg_hist;
-    LevelInfo *info;
+    LevelInfo *info;  // totals of every level (MAX_LEVELS + 1)
+    // records of cells resolved ahead of their level by the subtree kernel
+    uint32_t *cell_rec[2];  // per cell of the level list: its record link (REC_*), 0: none
+    SubRec *subrec;
+    uint32_t *rec_count;
+    uint32_t rec_cap;
     const uint32_t *pool;
     uint32_t pool_entries;
     unsigned long long seed;
@@ -201,6 +206,7 @@ __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
                 const uint32_t voff = pre[2] - pre[3];
                 Cell cl{0u, n, 0u, pre[1], v[4] ? pre[4] : NONE, 0u, t, voff};
                 c.cells[0][pre[0]] = cl;
+                c.cell_rec[0][pre[0]] = 0;
                 if (v[4]) c.big_list[pre[4]] = pre[0];
                 else mark_buckets(c, voff, n, pre[0]);
             }
@@ -278,7 +284,22 @@ __global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level) {
         const Cell cl = c.cells[cur][ci];
         const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
         CellRes r{};
-        if (c.key_rule == KD_KEY_MAXVAR) {
+        const uint32_t link = c.cell_rec[cur][ci];
+        const SubRec R = link ? c.subrec[(link & REC_INDEX) - 1] : SubRec{};
+        if (link & REC_RESOLVED) {
+            // split already found by the subtree kernel
+            r.dim = R.dim;
+            r.split = R.split;
+            r.nl = R.nl;
+            r.flags = R.flags;
+            r.crec[0] = R.crec[0];
+            r.crec[1] = R.crec[1];
+            c.res[ci] = r;
+            continue;
+        }
+        if (link) {
+            r.dim = R.dim;  // key coordinate chosen by the subtree kernel
+        } else if (c.key_rule == KD_KEY_MAXVAR) {
             const unsigned long long *st = T.stats[cur] + uint64_t(cl.slot) * T.d * 3;
             const __int128 n_c = cl.end - cl.begin;
             __int128 best = -1;
@@ -1088,7 +1109,7 @@ __device__ void form_chunk(const Ctx &c, uint32_t cur, uint32_t ncells, uint32_t
         const bool valid = ci < ncells;
         Cell cl{};
         if (valid) cl = c.cells[cur][ci];
-        const bool small = valid && cl.big == NONE;
+        const bool small = valid && cl.big == NONE && cl.voff != NONE;  // not resolved ahead
         const uint32_t nk = cl.end - cl.begin;
         const bool beyond = !valid || (small && cl.voff >= v1);
         const unsigned long long bmask = __ballot(beyond);
@@ -1413,7 +1434,7 @@ __global__ __launch_bounds__(NT, MAXVAR ? (RULE != KD_SPLIT_FOURIER ? 3 : 1) : (
     const int w = wave(), l = lane();
     const LevelInfo I = c.info[level];
     const uint32_t ncells = I.num_cells;
-    const uint32_t nbuckets = (I.points - I.big_points + TILE - 1) / TILE;  // small-point buckets
+    const uint32_t nbuckets = (I.points - I.big_points - I.resolved + TILE - 1) / TILE;
     for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
         uint32_t pos = c.bucket_first[b];
         const uint32_t v1 = (b + 1) * uint32_t(TILE);
@@ -1659,6 +1680,452 @@ __global__ __launch_bounds__(NT, MAXVAR ? (RULE != KD_SPLIT_FOURIER ? 3 : 1) : (
     }
 }
 
+// ------------------------------------------------------------ kernels: small-cell subtrees
+
+// A chunk of small cells is finished in one pass: every remaining level of
+// its cells is split in LDS, and only the order of the chunk's numbers moves
+// between levels (the keys of each level are read through it).  The columns
+// and the permutation are moved once, at the end, to the outputs (points in
+// leaves) or to the working buffers of the level where splitting stops.
+// Splits below the current level go to records that the per-level loop
+// reads when it reaches them, so node ids stay breadth-first.
+
+// Active sub-cells of a chunk at one sub-depth (slot ranges, key coordinate,
+// record link), their splits once found, and the numbering of their
+// children.  CH >= SC: room for every child of SC sub-cells.
+template <int SC, int CH>
+struct SubTable {
+    uint32_t start[CH], end[CH], dim[CH], rec[CH];  // rec: record index + 1
+    uint32_t split[SC], nl[SC], flags[SC], base[SC];
+    uint32_t kid[SC][2];  // child number at the next sub-depth, NONE for a leaf
+    uint32_t wide[4];     // sub-cells above WAVE_CELL_MAX points (at most 3)
+    uint32_t count, nwide;
+};
+constexpr uint32_t SEG_LEAF = 0xffu;
+template <bool MAXVAR>
+constexpr int subtree_cells() { return MAXVAR ? 120 : 64; }
+
+template <int SC, int CH>
+__device__ __forceinline__ void sub_result(const Ctx &c, uint32_t depth, SubTable<SC, CH> &A,
+                                           uint32_t q, uint32_t m, uint32_t lt, uint32_t le) {
+    CellRes r{};
+    finish_cell(c, depth, A.end[q] - A.start[q], r, m, lt, le);
+    A.split[q] = r.split;
+    A.nl[q] = r.nl;
+    A.flags[q] = r.flags;
+}
+
+template <int RULE, bool MAXVAR>
+__global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_FOURIER ? 2 : 3) void k_subtree(
+    Ctx c, uint32_t level) {
+    constexpr int SC = subtree_cells<MAXVAR>();
+    constexpr int CH = MAXVAR ? 2 * SC : SC;
+    struct SelectScratch {
+        uint32_t h[NW][NBINS];
+        unsigned long long sh64[NW * 2 * FCHUNK];
+        long long mom[NW][RULE == KD_SPLIT_FOURIER ? 2 * FOURIER_JMAX : 1];
+    };
+    union ScratchOrInv {
+        SelectScratch sel;
+        uint16_t inv[TILE];  // final slot of each chunk number
+    };
+    __shared__ __attribute__((aligned(16))) uint32_t keys[PADDED];  // keys of a sub-depth; staged values
+    __shared__ __attribute__((aligned(16))) ScratchOrInv lds;
+    __shared__ __attribute__((aligned(16))) uint8_t seg[TILE];   // sub-cell of each slot, SEG_LEAF in a leaf
+    __shared__ __attribute__((aligned(16))) uint8_t seg0[TILE];  // chunk cell of each slot
+    __shared__ __attribute__((aligned(16))) uint16_t lp[TILE];   // chunk number held by each slot
+    __shared__ ChunkLds<SC> C;
+    __shared__ SubTable<SC, CH> Q[2];
+    __shared__ uint32_t sh[2 * NW + 1], s3[4];
+    // MAXVAR: chunk prefix sums (S1, hi, lo) at the first slot of every child
+    // and per-wave totals of the scan
+    __shared__ unsigned long long pat[MAXVAR ? CH : 1][3];
+    __shared__ unsigned long long wtot[MAXVAR ? NW : 1][3];
+    static_assert(CH < int(SEG_LEAF), "child numbers fit a byte below SEG_LEAF");
+    uint32_t(*const h)[NBINS] = lds.sel.h;
+    unsigned long long *const sh64 = lds.sel.sh64;
+    auto &mom = lds.sel.mom;
+    const uint32_t cur = level & 1;
+    const int w = wave(), l = lane();
+    const LevelInfo I = c.info[level];
+    const uint32_t ncells = I.num_cells;
+    const uint32_t nbuckets = (I.points - I.big_points - I.resolved + TILE - 1) / TILE;
+    for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
+        uint32_t pos = c.bucket_first[b];
+        const uint32_t v1 = (b + 1) * uint32_t(TILE);
+        for (;;) {
+            if (w == 0) form_chunk(c, cur, ncells, pos, v1, C);
+            __syncthreads();
+            const uint32_t K = C.count, tot = C.total;
+            pos = C.next;
+            const uint32_t tr = __builtin_amdgcn_readfirstlane(C.tree);
+            __syncthreads();
+            if (K == 0) break;
+            const KD_CONST TreeDesc &T = cref(&c.trees[tr]);
+            const uint32_t d = T.d, n = T.n;
+            for (uint32_t k = w; k < K; k += NW)
+                for (uint32_t e = C.start[k] + l; e < C.start[k + 1]; e += WAVE) {
+                    seg[e] = uint8_t(k);
+                    seg0[e] = uint8_t(k);
+                    lp[e] = uint16_t(e);
+                }
+            for (uint32_t k = threadIdx.x; k < K; k += NT) {
+                Q[0].start[k] = C.start[k];
+                Q[0].end[k] = C.start[k + 1];
+                Q[0].dim[k] = C.dim[k];
+                Q[0].rec[k] = 0;
+            }
+            if (threadIdx.x == 0) {
+                Q[0].count = K;
+                Q[0].nwide = C.nwide;
+                for (int q = 0; q < 4; q++) Q[0].wide[q] = C.wide[q];
+            }
+            __syncthreads();
+            uint32_t qa = 0, depth = level;  // depth of the sub-cells in Q[qa]
+            for (;;) {
+                SubTable<SC, CH> &A = Q[qa];
+                SubTable<SC, CH> &N = Q[qa ^ 1];
+                const uint32_t nq = A.count;
+                // keys of the active slots, read through the numbers they hold
+                {
+                    uint32_t u[PER_THREAD];
+#pragma unroll
+                    for (int jj = 0; jj < PER_THREAD; jj++) {
+                        const uint32_t e = jj * NT + threadIdx.x;
+                        u[jj] = 0;
+                        if (e < tot) {
+                            const uint32_t q = seg[e];
+                            if (q != SEG_LEAF) {
+                                const uint32_t o = lp[e];
+                                u[jj] = gp(T.cols[cur] + uint64_t(A.dim[q]) * n)[C.off[seg0[o]] + o];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < PER_THREAD; jj++) {
+                        const uint32_t e = jj * NT + threadIdx.x;
+                        if (e < tot) keys[px(e)] = key_of_bits(u[jj]);
+                    }
+                }
+                __syncthreads();
+                // split of every active sub-cell: wide ones by the workgroup,
+                // the others one per wave
+                for (uint32_t qq = 0; qq < A.nwide; qq++) {
+                    const uint32_t q = A.wide[qq];
+                    uint32_t m, lt, le;
+                    block_candidate<RULE>(c, depth, keys, A.start[q], A.end[q] - A.start[q], 0u, h,
+                                          sh, s3, sh64, mom[0], nullptr, m, lt, le);
+                    if (threadIdx.x == 0) sub_result(c, depth, A, q, m, lt, le);
+                }
+                for (uint32_t q = w; q < nq; q += NW) {
+                    const uint32_t s0 = A.start[q], nk = A.end[q] - s0;
+                    if (nk > WAVE_CELL_MAX) continue;
+                    uint32_t m, lt, le;
+                    wave_candidate<RULE>(c, keys, s0, nk, h[w], mom[w], m, lt, le);
+                    if (l == 0) sub_result(c, depth, A, q, m, lt, le);
+                }
+                __syncthreads();
+                // children that are split again, numbered in slot order; their
+                // records (wave 0)
+                if (w == 0) {
+                    uint32_t run = 0;
+                    for (uint32_t q0 = 0; q0 < nq; q0 += WAVE) {
+                        const uint32_t q = q0 + l;
+                        bool go0 = false, go1 = false;
+                        if (q < nq) {
+                            const uint32_t f = A.flags[q];
+                            go0 = (f & RES_SPLIT) && !(f & RES_LEFT_LEAF);
+                            go1 = (f & RES_SPLIT) && !(f & RES_RIGHT_LEAF);
+                        }
+                        const uint32_t cnt = uint32_t(go0) + uint32_t(go1);
+                        const uint32_t incl = wave_incl_scan(cnt);
+                        const uint32_t id0 = run + incl - cnt;
+                        if (q < nq) {
+                            A.kid[q][0] = go0 ? id0 : NONE;
+                            A.kid[q][1] = go1 ? id0 + uint32_t(go0) : NONE;
+                        }
+                        run += __shfl(incl, WAVE - 1, WAVE);
+                    }
+                    if (l == 0) {
+                        // more than SC children: they stop here and are split at
+                        // their own level (MAXVAR: with their key coordinate in
+                        // a record)
+                        const bool go_on = run > 0 && run <= uint32_t(SC);
+                        const bool need = run > 0 && (go_on || MAXVAR);
+                        uint32_t base = 0;
+                        bool ok = false;
+                        if (need) {
+                            base = atomicAdd(c.rec_count, run);
+                            ok = uint64_t(base) + run <= c.rec_cap;
+                            if (!ok) c.ts[tr].status = KD_ECAPACITY;
+                        }
+                        s3[0] = run;
+                        s3[1] = base;
+                        s3[2] = (go_on && ok ? 1u : 0u) | (ok ? 2u : 0u);
+                    }
+                }
+                __syncthreads();
+                const uint32_t nact = s3[0], rbase = s3[1];
+                const bool go_on = s3[2] & 1u, recs = s3[2] & 2u;
+                // results of the sub-cells with their child links; the table
+                // of the children
+                for (uint32_t q = threadIdx.x; q < nq; q += NT) {
+                    uint32_t link[2] = {0u, 0u};
+                    for (int sd = 0; sd < 2; sd++) {
+                        const uint32_t k = A.kid[q][sd];
+                        if (k == NONE || !recs) continue;
+                        link[sd] = (go_on ? REC_RESOLVED : 0u) | (rbase + k + 1);
+                        N.start[k] = sd ? A.start[q] + A.nl[q] : A.start[q];
+                        N.end[k] = sd ? A.end[q] : A.start[q] + A.nl[q];
+                        N.rec[k] = rbase + k + 1;
+                        N.dim[k] = (depth + 1) % d;
+                    }
+                    if (depth == level) {
+                        CellRes r{};
+                        r.dim = A.dim[q];
+                        r.split = A.split[q];
+                        r.nl = A.nl[q];
+                        r.flags = A.flags[q];
+                        r.rank = (A.end[q] - A.start[q] - 1) / 2;
+                        r.crec[0] = link[0];
+                        r.crec[1] = link[1];
+                        c.res[C.ci[q]] = r;
+                    } else {
+                        c.subrec[A.rec[q] - 1] =
+                            SubRec{A.dim[q], A.split[q], A.nl[q], A.flags[q], {link[0], link[1]}};
+                    }
+                }
+                // stable partition of every sub-cell: each slot's new place,
+                // and what goes there (its number and child)
+                {
+                    const uint32_t e0 = threadIdx.x * PER_THREAD;
+                    const uint4 sq = *reinterpret_cast<const uint4 *>(seg + e0);
+                    const uint32_t sw[4] = {sq.x, sq.y, sq.z, sq.w};
+                    const uint4 lq0 = *reinterpret_cast<const uint4 *>(lp + e0);
+                    const uint4 lq1 = *reinterpret_cast<const uint4 *>(lp + e0 + 8);
+                    const uint32_t lw[8] = {lq0.x, lq0.y, lq0.z, lq0.w, lq1.x, lq1.y, lq1.z, lq1.w};
+                    uint32_t nleft = 0, fl = 0;
+#pragma unroll
+                    for (int j = 0; j < PER_THREAD; j++) {
+                        const uint32_t e = e0 + j, q = (sw[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                        if (e < tot && q != SEG_LEAF && keys[px(e)] <= A.split[q]) {
+                            nleft++;
+                            fl |= 1u << j;
+                        }
+                    }
+                    uint32_t all;
+                    const uint32_t lbase = block_excl_scan(nleft, sh, &all);
+                    uint32_t run = lbase;
+#pragma unroll
+                    for (int j = 0; j < PER_THREAD; j++) {
+                        const uint32_t e = e0 + j, q = (sw[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                        if (e < tot && q != SEG_LEAF && e == A.start[q]) A.base[q] = run;
+                        run += (fl >> j) & 1u;
+                    }
+                    __syncthreads();
+                    uint32_t mv[PER_THREAD];
+                    run = lbase;
+#pragma unroll
+                    for (int j = 0; j < PER_THREAD; j++) {
+                        const uint32_t e = e0 + j, q = (sw[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                        const uint32_t num = (lw[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                        uint32_t dd = e, ns = SEG_LEAF;
+                        if (e < tot && q != SEG_LEAF) {
+                            const bool left = (fl >> j) & 1u;
+                            const uint32_t s = A.start[q], lr = run - A.base[q];
+                            dd = left ? s + lr : s + A.nl[q] + (e - s) - lr;
+                            const uint32_t k = A.kid[q][left ? 0 : 1];
+                            ns = k == NONE ? SEG_LEAF : k;
+                        }
+                        mv[j] = dd | (num << 12) | (ns << 24);
+                        run += (fl >> j) & 1u;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int j = 0; j < PER_THREAD; j++) {
+                        if (e0 + j < tot) {
+                            const uint32_t dd = mv[j] & 0xfffu;
+                            lp[dd] = uint16_t((mv[j] >> 12) & 0xfffu);
+                            seg[dd] = uint8_t(mv[j] >> 24);
+                        }
+                    }
+                    __syncthreads();
+                }
+                if (MAXVAR && recs) {
+                    // key coordinate of every child: the largest fixed-point
+                    // variance over the columns, ties to the lowest.  Thread t
+                    // holds slots 16t .. 16t+15 and takes a record of its
+                    // running sums at each child's first slot; slots outside
+                    // the children add nothing, so a child's sums are the
+                    // difference of its record and the next one.
+                    const int shift = maxvar_shift(c.ts[tr].maxabs);
+                    const uint32_t e0 = threadIdx.x * PER_THREAD;
+                    uint32_t amask = 0, rmask = 0, rid[4] = {0, 0, 0, 0}, pe[PER_THREAD];
+                    {
+                        const uint4 sq = *reinterpret_cast<const uint4 *>(seg + e0);
+                        const uint32_t sw[4] = {sq.x, sq.y, sq.z, sq.w};
+#pragma unroll
+                        for (int j = 0; j < PER_THREAD; j++) {
+                            const uint32_t e = e0 + j, k = (sw[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                            pe[j] = 0;
+                            if (e < tot && k != SEG_LEAF) {
+                                amask |= 1u << j;
+                                const uint32_t o = lp[e];
+                                pe[j] = C.off[seg0[o]] + o;
+                                if (e == N.start[k]) {
+                                    rmask |= 1u << j;
+                                    rid[j >> 2] |= k << (8 * (j & 3));
+                                }
+                            }
+                        }
+                    }
+                    const uint32_t mine = threadIdx.x;  // child whose coordinate this thread picks
+                    __int128 best = -1;
+                    uint32_t bd = 0;
+                    for (uint32_t col = 0; col < d; col++) {
+                        const KD_GLOBAL uint32_t *src = gp(T.cols[cur] + uint64_t(col) * n);
+                        uint32_t xv[PER_THREAD];
+#pragma unroll
+                        for (int j = 0; j < PER_THREAD; j++) xv[j] = (amask >> j) & 1u ? src[pe[j]] : 0u;
+                        VarSums a;
+#pragma unroll
+                        for (int j = 0; j < PER_THREAD; j++) {
+                            if ((rmask >> j) & 1u) {
+                                a.fold();
+                                const uint32_t r = (rid[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                                pat[r][0] = a.s1;
+                                pat[r][1] = a.hi;
+                                pat[r][2] = a.lo;
+                            }
+                            if ((amask >> j) & 1u) a.add(maxvar_q32(xv[j], shift));
+                            if (j == 7) a.fold();
+                        }
+                        a.fold();
+                        unsigned long long x[3] = {a.s1, a.hi, a.lo};
+#pragma unroll
+                        for (int i = 0; i < 3; i++) x[i] = wave_scan64(x[i]);
+                        if (rmask) {
+                            const unsigned long long ex[3] = {x[0] - a.s1, x[1] - a.hi, x[2] - a.lo};
+                            for (uint32_t mm = rmask; mm; mm &= mm - 1) {
+                                const int j = __builtin_ctz(mm);
+                                const uint32_t r = (rid[j >> 2] >> (8 * (j & 3))) & 0xffu;
+#pragma unroll
+                                for (int i = 0; i < 3; i++) pat[r][i] += ex[i];
+                            }
+                        }
+                        if (l == WAVE - 1)
+#pragma unroll
+                            for (int i = 0; i < 3; i++) wtot[w][i] = x[i];
+                        __syncthreads();
+                        if (mine < nact) {
+                            // chunk prefix at child r's first slot (r = nact: the end)
+                            auto prefix = [&](uint32_t r, int i) {
+                                unsigned long long v = r < nact ? pat[r][i] : 0ull;
+                                const uint32_t wr =
+                                    r < nact ? N.start[r] / (WAVE * PER_THREAD) : uint32_t(NW);
+                                for (uint32_t ww = 0; ww < wr; ww++) v += wtot[ww][i];
+                                return v;
+                            };
+                            const long long s1 =
+                                (long long)(prefix(mine + 1, 0) - prefix(mine, 0));
+                            const __int128 s2 =
+                                (__int128)(long long)(prefix(mine + 1, 1) - prefix(mine, 1)) *
+                                    ((__int128)1 << 32) +
+                                (__int128)(long long)(prefix(mine + 1, 2) - prefix(mine, 2));
+                            const __int128 nc = N.end[mine] - N.start[mine];
+                            const __int128 V = nc * s2 - (__int128)s1 * (__int128)s1;
+                            if (V > best) {
+                                best = V;
+                                bd = col;
+                            }
+                        }
+                        __syncthreads();
+                    }
+                    if (mine < nact) {
+                        N.dim[mine] = bd;
+                        // children that stop here take their coordinate along
+                        if (!go_on) c.subrec[rbase + mine] = SubRec{bd, 0u, 0u, 0u, {0u, 0u}};
+                    }
+                }
+                if (!go_on) break;
+                // the children become the next sub-depth
+                if (w == 0) {
+                    uint32_t nw = 0;
+                    for (uint32_t k0 = 0; k0 < nact; k0 += WAVE) {
+                        const uint32_t k = k0 + l;
+                        const bool wide = k < nact && N.end[k] - N.start[k] > WAVE_CELL_MAX;
+                        const unsigned long long bm = __ballot(wide);
+                        if (wide) N.wide[nw + __popcll(bm & ((1ull << l) - 1))] = k;
+                        nw += uint32_t(__popcll(bm));
+                    }
+                    if (l == 0) {
+                        N.count = nact;
+                        N.nwide = nw;
+                    }
+                }
+                __syncthreads();
+                qa ^= 1;
+                depth++;
+            }
+            // the final move: every column and the permutation, from the
+            // numbers' places to their slots' places; slots in a leaf go to the
+            // outputs, the others to the working buffers of the level below
+            // the last sub-depth
+            for (uint32_t e = threadIdx.x; e < tot; e += NT) lds.inv[lp[e]] = uint16_t(e);
+            __syncthreads();
+            const uint32_t op = (depth + 1) & 1;
+            uint32_t ps[PER_THREAD], leafm = 0;
+#pragma unroll
+            for (int jj = 0; jj < PER_THREAD; jj++) {
+                const uint32_t e = jj * NT + threadIdx.x;
+                ps[jj] = 0;
+                if (e < tot) {
+                    ps[jj] = C.off[seg0[e]] + e;  // place of number e, and of slot e
+                    if (seg[e] == SEG_LEAF) leafm |= 1u << jj;
+                }
+            }
+            uint32_t vn[PER_THREAD];
+            {
+                const KD_GLOBAL uint32_t *src = gp(T.cols[cur]);
+#pragma unroll
+                for (int jj = 0; jj < PER_THREAD; jj++)
+                    vn[jj] = jj * NT + threadIdx.x < tot ? src[ps[jj]] : 0u;
+            }
+            for (uint32_t col = 0; col <= d; col++) {
+                uint32_t v[PER_THREAD];
+#pragma unroll
+                for (int jj = 0; jj < PER_THREAD; jj++) v[jj] = vn[jj];
+                if (col < d) {
+                    const KD_GLOBAL uint32_t *src =
+                        gp(col + 1 == d ? T.perm[cur] : T.cols[cur] + uint64_t(col + 1) * n);
+#pragma unroll
+                    for (int jj = 0; jj < PER_THREAD; jj++)
+                        if (jj * NT + threadIdx.x < tot) vn[jj] = src[ps[jj]];
+                }
+#pragma unroll
+                for (int jj = 0; jj < PER_THREAD; jj++) {
+                    const uint32_t e = jj * NT + threadIdx.x;
+                    if (e < tot) keys[lds.inv[e]] = v[jj];
+                }
+                __syncthreads();
+                KD_GLOBAL uint32_t *nb = gp(col == d ? T.perm[op] : T.cols[op] + uint64_t(col) * n);
+                KD_GLOBAL uint32_t *ob =
+                    col == d ? gp(T.out_perm)
+                             : (T.pts_out ? gp(T.pts_out + uint64_t(col) * n) : nullptr);
+#pragma unroll
+                for (int jj = 0; jj < PER_THREAD; jj++) {
+                    const uint32_t e = jj * NT + threadIdx.x;
+                    if (e < tot) {
+                        KD_GLOBAL uint32_t *p = (leafm >> jj) & 1u ? ob : nb;
+                        if (p) p[ps[jj]] = keys[e];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------ kernels: emit
 
 __device__ __forceinline__ void emit_counts(const Ctx &c, uint32_t level, uint32_t ci,
@@ -1679,6 +2146,7 @@ __device__ __forceinline__ void emit_counts(const Ctx &c, uint32_t level, uint32
         if (leaf[s]) continue;
         cnt[1]++;
         cnt[3] += sz[s];
+        if (r.crec[s] & REC_RESOLVED) cnt[8] += sz[s];
         if (sz[s] > uint32_t(SMALL_MAX)) {
             cnt[2] += (sz[s] + TILE - 1) / TILE;
             cnt[4] += sz[s];
@@ -1702,7 +2170,7 @@ __global__ __launch_bounds__(NT) void k_emit_sum(Ctx c, uint32_t level) {
 __global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t level, uint32_t nblocks) {
     __shared__ uint32_t sh[NW + 1];
     const uint32_t ncells = c.info[level].num_cells;
-    uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t b0 = 0; b0 < nblocks; b0 += NT) {
         const uint32_t b = b0 + threadIdx.x;
         for (int k = 0; k < EMIT_COUNTERS; k++) {
@@ -1722,6 +2190,7 @@ __global__ __launch_bounds__(NT) void k_emit_scan(Ctx c, uint32_t level, uint32_
         in.points = base[3];
         in.big_points = base[4];
         in.num_big = base[5];
+        in.resolved = base[8];
         c.info[level + 1] = in;
     }
 }
@@ -1795,20 +2264,23 @@ __device__ __forceinline__ void emit_cell(const Ctx &c, uint32_t level, uint32_t
         T.node_begin[left + 1] = mid;
         T.node_end[left + 1] = cl.end;
     }
-    uint32_t slot = pre[1], tile = pre[2], big = pre[5], voff = pre[3] - pre[4];
+    // small cells resolved ahead stay out of the small-point numbering
+    uint32_t slot = pre[1], tile = pre[2], big = pre[5], voff = pre[3] - pre[4] - pre[8];
     const uint32_t b[2] = {cl.begin, mid}, e[2] = {mid, cl.end};
     const uint32_t leaf[2] = {r.flags & RES_LEFT_LEAF, r.flags & RES_RIGHT_LEAF};
     for (int s = 0; s < 2; s++) {
         if (leaf[s]) continue;
         const uint32_t sz = e[s] - b[s];
         const bool isbig = sz > uint32_t(SMALL_MAX);
+        const bool resolved = r.crec[s] & REC_RESOLVED;
         c.cells[nxt][slot] = Cell{b[s], e[s], left + s, tile, isbig ? big : NONE, 2 * li + s,
-                                  cl.tree, voff};
+                                  cl.tree, resolved ? NONE : voff};
+        c.cell_rec[nxt][slot] = r.crec[s];
         if (isbig) {
             c.big_list[big] = slot;
             big++;
             tile += (sz + TILE - 1) / TILE;
-        } else {
+        } else if (!resolved) {
             mark_buckets(c, voff, sz, slot);
             voff += sz;
         }
@@ -1854,6 +2326,7 @@ __global__ __launch_bounds__(NT) void k_emit_one(Ctx c, uint32_t level) {
         in.points = tot[3];
         in.big_points = tot[4];
         in.num_big = tot[5];
+        in.resolved = tot[8];
         c.info[level + 1] = in;
     }
     __threadfence_block();
@@ -1995,6 +2468,7 @@ struct TreeLayout {
 };
 
 struct Layout {
+    uint64_t cell_rec[2], subrec, rec_count, rec_cap;
     uint64_t trees, ts, cells[2], res, big_list, tile_lt, tile_le, tile_off, tile_cell, tiles, hist, mm, mom,
         bounds, med, pre, scan, buckets, segs, info, total;
     uint64_t max_cells, max_tiles, max_big, scan_blocks, all_points;
@@ -2014,6 +2488,13 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     L.trees = B.take(sizeof(TreeDesc) * T);
     L.ts = B.take(sizeof(TreeState) * T);
     for (int b = 0; b < 2; b++) L.cells[b] = B.take(L.max_cells * sizeof(Cell));
+    for (int b = 0; b < 2; b++) L.cell_rec[b] = B.take(L.max_cells * 4);
+    // records of cells resolved ahead: each is a node of its tree
+    uint64_t caps = 0;
+    for (uint32_t t = 0; t < T; t++) caps += cap[t];
+    L.rec_cap = p->split_rule == KD_SPLIT_SUBSET ? 0 : std::min<uint64_t>(caps, REC_INDEX - 1);
+    L.subrec = B.take(L.rec_cap * sizeof(SubRec));
+    L.rec_count = B.take(4);
     L.res = B.take(L.max_cells * sizeof(CellRes));
     L.big_list = B.take(L.max_big * 4);
     L.tile_lt = B.take(L.max_tiles * 4);
@@ -2189,12 +2670,14 @@ LevelBound level_bound(const LevelInfo &K, uint32_t gap, uint32_t leaf_size, con
     LevelBound b;
     if (gap == 0) {
         b = LevelBound{K.num_cells, K.num_tiles, K.num_big, K.big_points,
-                       uint64_t(K.points) - K.big_points};
+                       uint64_t(K.points) - K.big_points - K.resolved};
     } else {
         b.cells = std::min<uint64_t>(uint64_t(K.num_cells) << gap, K.points / (uint64_t(leaf_size) + 1));
         b.big = std::min<uint64_t>(uint64_t(K.num_big) << gap, K.big_points / (SMALL_MAX + 1));
         b.big_points = b.big ? K.big_points : 0;
         b.tiles = b.big ? b.big_points / TILE + b.big : 0;
+        // children of resolved cells can be handed back unresolved (a
+        // subtree that stops early), so every point counts here
         b.small_points = K.points;
     }
     b.cells = std::min(b.cells, L.max_cells);
@@ -2295,6 +2778,10 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         c.seg_hist = c.seg_rank + max_seg;
     }
     c.info = reinterpret_cast<LevelInfo *>(ws + L.info);
+    for (int b = 0; b < 2; b++) c.cell_rec[b] = reinterpret_cast<uint32_t *>(ws + L.cell_rec[b]);
+    c.subrec = reinterpret_cast<SubRec *>(ws + L.subrec);
+    c.rec_count = reinterpret_cast<uint32_t *>(ws + L.rec_count);
+    c.rec_cap = uint32_t(L.rec_cap);
     c.pool = p->subset_pool;
     c.pool_entries = p->pool_entries;
     c.seed = p->seed;
@@ -2319,6 +2806,7 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.max_big * BIG_BINS / NT + 1, 4096)),
                            dim3(NT), 0, st, c.hist, L.max_big * BIG_BINS, 0u);
         hipLaunchKernelGGL(k_init, per_tree_nodes, dim3(NT), 0, st, c);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(NT), 0, st, c.rec_count, 1ull, 0u);
         if (p->split_rule == KD_SPLIT_SUBSET) {
             const uint64_t words = (L.all_points / (SMALL_MAX + 1) + 2) * (3 + NBINS) + 64;
             hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words / NT + 1, 4096)), dim3(NT), 0, st,
@@ -2467,16 +2955,21 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         if (smallp > 0) {
             P.run(KD_PROF_SMALL, smallp, scatter_avg_bpp * smallp, [&] {
                 const dim3 g(grid_for((smallp + TILE - 1) / TILE, small_grid));
+#define KD_SUB(R, M) hipLaunchKernelGGL((k_subtree<R, M>), g, dim3(NT), 0, st, c, level)
 #define KD_SMALL(R, M) hipLaunchKernelGGL((k_small<R, M>), g, dim3(NT), small_dyn, st, c, level)
+                // EXACT and FOURIER finish small cells' subtrees in one pass;
+                // SUBSET's subset pool rows depend on a cell's rank within its
+                // level, which is known only level by level
                 switch (p->split_rule * 2 + (maxvar ? 1 : 0)) {
-                    case 0: KD_SMALL(KD_SPLIT_EXACT, false); break;
-                    case 1: KD_SMALL(KD_SPLIT_EXACT, true); break;
-                    case 2: KD_SMALL(KD_SPLIT_FOURIER, false); break;
-                    case 3: KD_SMALL(KD_SPLIT_FOURIER, true); break;
+                    case 0: KD_SUB(KD_SPLIT_EXACT, false); break;
+                    case 1: KD_SUB(KD_SPLIT_EXACT, true); break;
+                    case 2: KD_SUB(KD_SPLIT_FOURIER, false); break;
+                    case 3: KD_SUB(KD_SPLIT_FOURIER, true); break;
                     case 4: KD_SMALL(KD_SPLIT_SUBSET, false); break;
                     default: KD_SMALL(KD_SPLIT_SUBSET, true); break;
                 }
 #undef KD_SMALL
+#undef KD_SUB
             });
         }
         const uint32_t nb = uint32_t((nc + NT - 1) / NT);
