@@ -429,11 +429,23 @@ __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t
             const uint32_t i = v.tb + j * NT + threadIdx.x;
             u[j] = i < v.te ? key_of_bits(col[i]) : 0u;
         }
+        // a thread's keys often share a digit (the leading digits of a cell):
+        // one atomic per run of equal digits
+        uint32_t run_bin = NONE, run_cnt = 0;
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
             const uint32_t i = v.tb + j * NT + threadIdx.x;
-            if (i < v.te && (u[j] & pmask) == r.prefix) atomicAdd(&h[(u[j] >> shift) & dmask], 1u);
+            if (i < v.te && (u[j] & pmask) == r.prefix) {
+                const uint32_t bin = (u[j] >> shift) & dmask;
+                if (bin != run_bin) {
+                    if (run_cnt) atomicAdd(&h[run_bin], run_cnt);
+                    run_bin = bin;
+                    run_cnt = 0;
+                }
+                run_cnt++;
+            }
         }
+        if (run_cnt) atomicAdd(&h[run_bin], run_cnt);
         __syncthreads();
     }
     if (big != NONE) {
@@ -443,50 +455,58 @@ __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t
     }
 }
 
-// EXACT, large cells: pick the digit that holds the target rank.  After the
-// last pass the candidate is the lower median and lt / le are exact.
+// EXACT, large cells: pick the digit that holds the target rank (one wave
+// per cell, 32 bins per lane).  After the last pass the candidate is the
+// lower median and lt / le are exact.
 __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t pass) {
-    constexpr int PER = BIG_BINS / NT;
-    const uint32_t nbig = c.info[level].num_big;
-    __shared__ uint32_t sh[NW + 1];
-    __shared__ uint32_t s_bin, s_below, s_cnt;
+    constexpr int PER = BIG_BINS / WAVE;
     const int shift = big_shift(pass);
-    const uint32_t nb = 1u << big_bits(pass);
-    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+    const uint32_t nbig = c.info[level].num_big;
+    const int l = lane();
+    for (uint32_t b = blockIdx.x * NW + wave(); b < nbig; b += gridDim.x * NW) {
         const uint32_t ci = c.big_list[b];
         CellRes r = c.res[ci];
-        uint32_t *gh = c.hist + uint64_t(b) * BIG_BINS;
+        uint4 *gh = reinterpret_cast<uint4 *>(c.hist + uint64_t(b) * BIG_BINS) + l * (PER / 4);
         uint32_t hv[PER], local = 0;
 #pragma unroll
-        for (int j = 0; j < PER; j++) {
-            const uint32_t bin = threadIdx.x * PER + j;
-            hv[j] = bin < nb ? gh[bin] : 0u;
-            local += hv[j];
-            gh[bin] = 0;
+        for (int q = 0; q < PER / 4; q++) {
+            const uint4 x = gh[q];
+            hv[4 * q] = x.x;
+            hv[4 * q + 1] = x.y;
+            hv[4 * q + 2] = x.z;
+            hv[4 * q + 3] = x.w;
+            gh[q] = make_uint4(0u, 0u, 0u, 0u);
         }
-        uint32_t tot;
-        uint32_t ex = block_excl_scan(local, sh, &tot);
+#pragma unroll
+        for (int j = 0; j < PER; j++) local += hv[j];
+        const uint32_t ex = wave_incl_scan(local) - local;
+        const unsigned long long m = __ballot(ex <= r.rank && r.rank < ex + local);
+        const int src = __builtin_ctzll(m);  // exactly one lane holds the rank
+        uint32_t bin = 0, below = ex, cnt = 0;
+        bool found = false;
 #pragma unroll
         for (int j = 0; j < PER; j++) {
-            if (ex <= r.rank && r.rank < ex + hv[j]) {
-                s_bin = threadIdx.x * PER + j;
-                s_below = ex;
-                s_cnt = hv[j];
+            if (!found && r.rank < below + hv[j]) {
+                bin = uint32_t(l * PER + j);
+                cnt = hv[j];
+                found = true;
+            } else if (!found) {
+                below += hv[j];
             }
-            ex += hv[j];
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            r.prefix |= s_bin << shift;
-            r.rank -= s_below;
-            r.lt += s_below;  // keys below the selected digit
+        bin = __shfl(bin, src, WAVE);
+        below = __shfl(below, src, WAVE);
+        cnt = __shfl(cnt, src, WAVE);
+        if (l == 0) {
+            r.prefix |= bin << shift;
+            r.rank -= below;
+            r.lt += below;  // keys below the selected digit
             if (pass == BIG_PASSES - 1) {
                 r.cand = r.prefix;
-                r.le = r.lt + s_cnt;
+                r.le = r.lt + cnt;
             }
             c.res[ci] = r;
         }
-        __syncthreads();
     }
 }
 
@@ -2296,7 +2316,7 @@ __global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level) {
 // The whole emit step in one workgroup, for levels of at most EMIT_ONE_MAX
 // cells: counts and their prefix (each thread takes consecutive cells), the
 // totals, the per-tree update, then the node records and next cells.
-constexpr uint32_t EMIT_ONE_MAX = 2048;
+constexpr uint32_t EMIT_ONE_MAX = 1024;
 __global__ __launch_bounds__(NT) void k_emit_one(Ctx c, uint32_t level) {
     __shared__ uint32_t sh[NW + 1];
     const uint32_t ncells = c.info[level].num_cells;
@@ -2896,8 +2916,8 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                                            st, c, level, pass);
                     });
                     P.run(KD_PROF_PICK, 0, 0, [&] {
-                        hipLaunchKernelGGL(k_big_pick, dim3(grid_for(nbig, 65535)), dim3(NT), 0,
-                                           st, c, level, pass);
+                        hipLaunchKernelGGL(k_big_pick, dim3(grid_for((nbig + NW - 1) / NW, 65535)),
+                                           dim3(NT), 0, st, c, level, pass);
                     });
                 }
             } else if (p->split_rule == KD_SPLIT_FOURIER) {
