@@ -18,11 +18,18 @@ constexpr int SMALL_MAX = 4096;      // cells up to this size are done by one wo
 constexpr int RBITS = 8;             // radix-select digit width inside one workgroup
 constexpr int NBINS = 1 << RBITS;
 constexpr int RPASSES = 32 / RBITS;
-// large cells: three device-wide passes of 11, 11 and 10 bits
-constexpr int BIG_PASSES = 3;
-constexpr int BIG_BINS = 2048;
-__host__ __device__ constexpr int big_bits(int pass) { return pass < 2 ? 11 : 10; }
-__host__ __device__ constexpr int big_shift(int pass) { return pass == 0 ? 21 : (pass == 1 ? 10 : 0); }
+// large cells: device-wide passes of BIG_DIGIT-bit digits, most significant
+// first (the last may be narrower)
+#ifndef KD_BIG_DIGIT
+#define KD_BIG_DIGIT 11
+#endif
+constexpr int BIG_DIGIT = KD_BIG_DIGIT;
+constexpr int BIG_PASSES = (32 + BIG_DIGIT - 1) / BIG_DIGIT;
+constexpr int BIG_BINS = 1 << BIG_DIGIT;
+__host__ __device__ constexpr int big_shift(int pass) {
+    return 32 - BIG_DIGIT * (pass + 1) > 0 ? 32 - BIG_DIGIT * (pass + 1) : 0;
+}
+__host__ __device__ constexpr int big_bits(int pass) { return 32 - BIG_DIGIT * pass - big_shift(pass); }
 constexpr int MAX_SUBSETS = 4096;
 constexpr int MAX_LEVELS = 128;
 constexpr uint32_t NONE = 0xffffffffu;

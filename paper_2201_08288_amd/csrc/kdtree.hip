@@ -467,6 +467,7 @@ __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t
         const uint32_t ci = c.big_list[b];
         CellRes r = c.res[ci];
         uint4 *gh = reinterpret_cast<uint4 *>(c.hist + uint64_t(b) * BIG_BINS) + l * (PER / 4);
+        static_assert(PER % 4 == 0, "whole uint4 groups of bins per lane");
         uint32_t hv[PER], local = 0;
 #pragma unroll
         for (int q = 0; q < PER / 4; q++) {
