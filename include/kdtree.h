@@ -182,6 +182,33 @@ kd_status kd_build_batched(uint32_t count, const kd_batch_item *items, const kd_
 kd_status kd_query_leaf(const kd_tree *tree, const float *q, uint64_t nq, uint32_t d,
                         uint64_t ldq, uint32_t *leaf_out, void *stream);
 
+/* Queries that use a built tree (§1, §2: the cells of the tree answer
+ * nearest-neighbour and range questions).  Both need the tree's points in
+ * position order (tree->points_out, built with points_out set) and n, the
+ * tree's point count.  Stream-ordered; KD_EINVAL for a missing array, d == 0
+ * or a bad size, and no work is enqueued then.
+ *
+ * kd_query_knn: the k nearest points (1 <= k <= 64) of each query q (device
+ * [d][ldq] fp32, nq queries) by squared Euclidean distance, computed in fp64
+ * as the sum over coordinates in order of (x_c - q_c)^2 (NaN sums count as
+ * +inf), ascending, ties to the smaller point index.  idx_out: device
+ * [nq][k] original point indices; dist_out: device [nq][k] squared
+ * distances.  Fewer than k points: the list ends with (0xFFFFFFFF, +inf); a
+ * query with a NaN coordinate gets (0xFFFFFFFF, NaN) throughout.           */
+kd_status kd_query_knn(const kd_tree *tree, uint64_t n, const float *q, uint64_t nq, uint32_t d,
+                       uint64_t ldq, uint32_t k, uint32_t *idx_out, double *dist_out,
+                       void *stream);
+
+/* kd_query_box: for each box [lo, hi] (device [d][ldb] fp32 each, nb boxes,
+ * inclusive in every coordinate, -0 equal to +0) the number of points inside
+ * in count_out (device [nb]).  With ids_out (device), also their original
+ * indices, in tree position order, written from offsets[i] (device [nb],
+ * e.g. the exclusive prefix sum of the counts of a first call without
+ * ids_out).  A box with a NaN bound holds nothing.                          */
+kd_status kd_query_box(const kd_tree *tree, uint64_t n, const float *lo, const float *hi,
+                       uint64_t nb, uint32_t d, uint64_t ldb, uint32_t *count_out,
+                       const uint64_t *offsets, uint32_t *ids_out, void *stream);
+
 /* Launch shapes of the level kernels.  They change only how work is spread
  * over workgroups, never the result: every setting builds the same tree bit
  * for bit.  0 in a field means the default (2048 workgroups per digit pass,

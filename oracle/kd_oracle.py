@@ -291,3 +291,62 @@ def check_partition(points, tree, permuted=False):
                                      _ptr(arr["node_begin"]), _ptr(arr["node_end"]),
                                      _ptr(arr["node_child"]), _ptr(arr["node_dim"]),
                                      _ptr(arr["node_split"]))
+
+
+# ---------------------------------------------------------------- queries
+# The queries the cells of a tree serve (§1, §2: nearest neighbours, ranges),
+# written as their plain definitions: brute force over every point, no tree.
+
+QUERY_NONE = 0xFFFFFFFF
+
+
+def knn(points, queries, k, chunk=256):
+    """Exact k nearest neighbours by brute force.  points: float32 (d, n);
+    queries: float32 (d, nq).  Squared Euclidean distance in fp64, summed
+    over the coordinates in order ((x_c - q_c) rounded, squared and rounded,
+    added and rounded: no fused operations); a NaN sum counts as +inf.
+    Ascending by (distance, point index).  Returns (idx uint32 (nq, k),
+    dist float64 (nq, k)); fewer than k points: (QUERY_NONE, +inf); a query
+    with a NaN coordinate: (QUERY_NONE, NaN) throughout."""
+    p = np.asarray(points, dtype=np.float32)
+    q = np.asarray(queries, dtype=np.float32)
+    d, n = p.shape
+    nq = q.shape[1]
+    idx = np.full((nq, k), QUERY_NONE, dtype=np.uint32)
+    dist = np.full((nq, k), np.inf, dtype=np.float64)
+    ids = np.arange(n, dtype=np.int64)
+    m = min(k, n)
+    for a in range(0, nq, chunk):
+        b = min(nq, a + chunk)
+        D = np.zeros((b - a, n), dtype=np.float64)
+        for c in range(d):
+            t = p[c].astype(np.float64)[None, :] - q[c, a:b].astype(np.float64)[:, None]
+            D = D + t * t
+        D[np.isnan(D)] = np.inf
+        for r in range(b - a):
+            if np.isnan(q[:, a + r]).any():
+                idx[a + r] = QUERY_NONE
+                dist[a + r] = np.nan
+                continue
+            order = np.lexsort((ids, D[r]))[:m]
+            idx[a + r, :m] = order
+            dist[a + r, :m] = D[r, order]
+    return idx, dist
+
+
+def box_query(points, lo, hi):
+    """Original indices (ascending) of the points inside each box [lo, hi]:
+    every coordinate within its bounds, inclusive, compared as floats (-0
+    equals +0).  A box with a NaN bound holds nothing.  points: float32
+    (d, n); lo, hi: float32 (d, nb).  Returns a list of uint32 arrays."""
+    p = np.asarray(points, dtype=np.float32)
+    lo = np.asarray(lo, dtype=np.float32)
+    hi = np.asarray(hi, dtype=np.float32)
+    out = []
+    for i in range(lo.shape[1]):
+        if np.isnan(lo[:, i]).any() or np.isnan(hi[:, i]).any():
+            out.append(np.zeros(0, dtype=np.uint32))
+            continue
+        inside = np.all((p >= lo[:, i:i + 1]) & (p <= hi[:, i:i + 1]), axis=0)
+        out.append(np.nonzero(inside)[0].astype(np.uint32))
+    return out

@@ -32,6 +32,7 @@
 #include "kdtree.h"
 #include "kd_device.hpp"
 #include "kd_fourier.hpp"
+#include "kd_query.hpp"
 #include "kd_select.hpp"
 
 using namespace kd;
@@ -3087,6 +3088,41 @@ kd_status kd_query_leaf(const kd_tree *tree, const float *q, uint64_t nq, uint32
     hipLaunchKernelGGL(k_query, dim3(grid_for(nq / NT + 1, 65535)), dim3(NT), 0, st,
                        tree->node_child, tree->node_dim, tree->node_split, tree->node_leaf, q, nq,
                        ldq, leaf_out);
+    KD_LAUNCH_CHECK();
+    return KD_OK;
+}
+
+static bool query_tree_ok(const kd_tree *t) {
+    return t && t->perm && t->node_begin && t->node_end && t->node_child && t->node_dim &&
+           t->node_split && t->node_split_f && t->points_out;
+}
+
+kd_status kd_query_knn(const kd_tree *tree, uint64_t n, const float *q, uint64_t nq, uint32_t d,
+                       uint64_t ldq, uint32_t k, uint32_t *idx_out, double *dist_out,
+                       void *stream) {
+    if (!query_tree_ok(tree) || n == 0 || !q || !idx_out || !dist_out || d == 0 || ldq < nq ||
+        k == 0 || k > KNN_MAX)
+        return KD_EINVAL;
+    if (nq == 0) return KD_OK;
+    hipLaunchKernelGGL(k_knn, dim3(grid_for(nq / NT + 1, 65535)), dim3(NT), 0,
+                       reinterpret_cast<hipStream_t>(stream), tree->node_child, tree->node_dim,
+                       tree->node_split, tree->node_split_f, tree->node_begin, tree->node_end,
+                       tree->points_out, n, tree->perm, q, nq, d, ldq, k, idx_out, dist_out);
+    KD_LAUNCH_CHECK();
+    return KD_OK;
+}
+
+kd_status kd_query_box(const kd_tree *tree, uint64_t n, const float *lo, const float *hi,
+                       uint64_t nb, uint32_t d, uint64_t ldb, uint32_t *count_out,
+                       const uint64_t *offsets, uint32_t *ids_out, void *stream) {
+    if (!query_tree_ok(tree) || n == 0 || !lo || !hi || !count_out || d == 0 || ldb < nb ||
+        (ids_out && !offsets))
+        return KD_EINVAL;
+    if (nb == 0) return KD_OK;
+    hipLaunchKernelGGL(k_box, dim3(grid_for(nb / NT + 1, 65535)), dim3(NT), 0,
+                       reinterpret_cast<hipStream_t>(stream), tree->node_child, tree->node_dim,
+                       tree->node_split, tree->node_begin, tree->node_end, tree->points_out, n,
+                       tree->perm, lo, hi, nb, d, ldb, count_out, offsets, ids_out);
     KD_LAUNCH_CHECK();
     return KD_OK;
 }

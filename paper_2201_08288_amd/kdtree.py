@@ -95,6 +95,12 @@ def lib():
                                        _vp, _u64, _vp]
         L.kd_query_leaf.restype = st
         L.kd_query_leaf.argtypes = [ctypes.POINTER(TreeStruct), _vp, _u64, _u32, _u64, _vp, _vp]
+        L.kd_query_knn.restype = st
+        L.kd_query_knn.argtypes = [ctypes.POINTER(TreeStruct), _u64, _vp, _u64, _u32, _u64, _u32,
+                                   _vp, _vp, _vp]
+        L.kd_query_box.restype = st
+        L.kd_query_box.argtypes = [ctypes.POINTER(TreeStruct), _u64, _vp, _vp, _u64, _u32, _u64,
+                                   _vp, _vp, _vp, _vp]
         L.kd_set_tuning.restype = st
         L.kd_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
         L.kd_get_tuning.restype = st
@@ -278,6 +284,48 @@ def query_leaf(tree, queries, stream=None):
     _check(lib().kd_query_leaf(ctypes.byref(tree.struct), queries.data_ptr(), nq, d, ldq,
                                out.data_ptr(), _stream_ptr(stream)), "kd_query_leaf")
     return out
+
+
+def _query_cols(x):
+    assert x.is_cuda and x.dtype == torch.float32 and x.stride(1) == 1
+    d, m = x.shape
+    return d, m, (x.stride(0) if d > 1 else m)
+
+
+def query_knn(tree, queries, k, stream=None):
+    """kd_query_knn: (indices int32 [nq, k] holding uint32, squared distances
+    float64 [nq, k]) of the k nearest tree points of each query column.  The
+    tree must have been built with points_out."""
+    d, nq, ldq = _query_cols(queries)
+    idx = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+    dist = torch.empty((nq, k), dtype=torch.float64, device=queries.device)
+    _check(lib().kd_query_knn(ctypes.byref(tree.struct), tree.n, queries.data_ptr(), nq, d, ldq,
+                              k, idx.data_ptr(), dist.data_ptr(), _stream_ptr(stream)),
+           "kd_query_knn")
+    return idx, dist
+
+
+def query_box(tree, lo, hi, ids=False, stream=None):
+    """kd_query_box: points of the tree inside each box [lo, hi] (columns of
+    two [d, nb] tensors).  Returns counts (int32 [nb]); with ids=True also
+    (offsets int64 [nb], original indices int32 [total]) from a second call."""
+    d, nb, ldb = _query_cols(lo)
+    assert hi.shape == lo.shape and hi.stride() == lo.stride()
+    cnt = torch.empty(nb, dtype=torch.int32, device=lo.device)
+    L = lib()
+    _check(L.kd_query_box(ctypes.byref(tree.struct), tree.n, lo.data_ptr(), hi.data_ptr(), nb, d,
+                          ldb, cnt.data_ptr(), None, None, _stream_ptr(stream)), "kd_query_box")
+    if not ids:
+        return cnt
+    c64 = cnt.to(torch.int64)
+    off = torch.cumsum(c64, 0) - c64
+    total = int(c64.sum().item()) if nb else 0
+    out = torch.empty(max(total, 1), dtype=torch.int32, device=lo.device)
+    cnt2 = torch.empty_like(cnt)
+    _check(L.kd_query_box(ctypes.byref(tree.struct), tree.n, lo.data_ptr(), hi.data_ptr(), nb, d,
+                          ldb, cnt2.data_ptr(), off.data_ptr(), out.data_ptr(), _stream_ptr(stream)),
+           "kd_query_box")
+    return cnt, off, out[:total]
 
 
 def set_tuning(hist_blocks=0, scatter_blocks=0, small_blocks=0):
