@@ -146,6 +146,39 @@ def bench_batched(trees=512, reps=3):
                         "S=32, leaf 32, EXACT, cyclic"}
 
 
+def bench_queries(tree, xt, nq=1 << 20, nbox=1 << 16, k=8, reps=3):
+    """Queries on the built tree: k nearest neighbours of data points moved by
+    a small Gaussian step, and boxes of half-width 0.05 around data points
+    (counts only)."""
+    import torch
+
+    from paper_2201_08288_amd import kdtree, synth
+    gen = torch.Generator(device="cuda").manual_seed(synth.BASE_SEED + 6)
+    d, n = xt.shape
+    q = xt[:, torch.randint(0, n, (nq,), generator=gen, device="cuda")]
+    q = (q + 0.05 * torch.randn(q.shape, generator=gen, device="cuda")).contiguous()
+    c = xt[:, torch.randint(0, n, (nbox,), generator=gen, device="cuda")]
+    lo, hi = (c - 0.05).contiguous(), (c + 0.05).contiguous()
+    kdtree.query_knn(tree, q, k)
+    cnt = kdtree.query_box(tree, lo, hi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        kdtree.query_knn(tree, q, k)
+    torch.cuda.synchronize()
+    t_knn = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cnt = kdtree.query_box(tree, lo, hi)
+    torch.cuda.synchronize()
+    t_box = (time.perf_counter() - t0) / reps
+    return {"knn": {"queries": nq, "k": k, "ms": 1e3 * t_knn, "queries_per_s": nq / t_knn},
+            "box": {"boxes": nbox, "half_width": 0.05, "ms": 1e3 * t_box, "boxes_per_s": nbox / t_box,
+                    "mean_count": float(cnt.double().mean().item())},
+            "workload": "the benchmark tree; kNN of data points plus N(0, 0.05^2) steps, "
+                        "boxes of half-width 0.05 around data points"}
+
+
 def bench_serving(rates=(50, 200, 1000, 2000), per_rate=150, warm=20, workers=3):
     """Poisson build requests (n log-uniform [2^12, 2^22], d in {3,16},
     Gaussian mixture, S=64, leaf 64) each followed by 1,024 lookups of its
@@ -194,6 +227,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-queries", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch shapes instead of kd_autotune's choice")
     ap.add_argument("--tuning", default=None, metavar="HIST,SCATTER,SMALL",
@@ -222,6 +256,17 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: {m} bytes read, {m} bytes written")
         del a, b
+    # context for the roofline: what a plain device-to-device copy reaches
+    a = torch.empty(1 << 26, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    copy_gbps = 10 * 2 * a.numel() * 4 / (time.perf_counter() - t0) / 1e9
+    del a, b
     log(f"[bench] generating workload {args.workload}")
     w, x, pool = workload_arrays(args.workload)
     d, n = x.shape
@@ -294,6 +339,11 @@ def main():
     b_alg = 8 * d + 12
     level_gbps = b_alg * pl / (ms * 1e-3) / 1e9
 
+    queries = None
+    if not args.no_queries:
+        log("[bench] queries (kNN, boxes)")
+        queries = bench_queries(tree, xt)
+
     batched = serving = None
     kdtree.set_tuning()  # batched and serving run the default launch shapes
     if not args.no_batched:
@@ -322,7 +372,8 @@ def main():
         "whole_build_alg_GBps": round(level_gbps, 1),
         "whole_build_alg_frac": round(level_gbps / HBM_PEAK_GBPS, 4),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
-        "batched": batched, "serving": serving,
+        "copy_GBps": round(copy_gbps, 1),
+        "batched": batched, "serving": serving, "queries": queries,
     }
     print(json.dumps(out), flush=True)
 

@@ -1,7 +1,7 @@
 // kd_query.hpp -- queries that use a built tree (§1 and §2: the cells of the
 // tree answer nearest-neighbour and range questions): exact k nearest
-// neighbours and axis-aligned box search, one query per thread, by a
-// depth-first walk with an explicit stack.
+// neighbours (one wave per query) and axis-aligned box search (one thread
+// per box), by a depth-first walk with an explicit stack.
 //
 // Cells: a node with split key s sends points with key <= s left and the rest
 // right, so its left child's region along the node's coordinate is
@@ -15,65 +15,56 @@ namespace kd {
 constexpr uint32_t KNN_MAX = 64;             // largest k of a neighbour query
 constexpr int QUERY_STACK = MAX_LEVELS + 2;  // a walk holds at most one entry per depth
 
-// Squared Euclidean distance in fp64, summed in coordinate order (no fused
-// operations: the build compiles with contraction off).  A NaN sum (from
-// infinite coordinates) counts as +inf.
-__device__ __forceinline__ double knn_dist(const float *pts, uint64_t n, uint64_t p,
-                                           const float *q, uint64_t ldq, uint64_t i, uint32_t d) {
-    double s = 0.0;
-    for (uint32_t c = 0; c < d; c++) {
-        const double t = double(pts[uint64_t(c) * n + p]) - double(q[uint64_t(c) * ldq + i]);
-        s = s + t * t;
-    }
-    return s != s ? __builtin_inf() : s;
-}
-
 // (distance, point index) order of the neighbour lists.
 __device__ __forceinline__ bool knn_less(double da, uint32_t ia, double db, uint32_t ib) {
     return da < db || (da == db && ia < ib);
 }
 
-// One thread per query: the k nearest points of the tree, ascending by
-// (squared distance, original index).  pts: the tree's points in position
-// order [d][n]; perm: original index of each position.  Fewer than k points:
-// the rest of the list is (NONE, +inf).  A query with a NaN coordinate gets
-// (NONE, NaN) throughout.
-__global__ void k_knn(const int32_t *child, const uint32_t *dim, const uint32_t *split,
-                      const float *split_f, const uint32_t *nbeg, const uint32_t *nend,
-                      const float *pts, uint64_t n, const uint32_t *perm, const float *q,
-                      uint64_t nq, uint32_t d, uint64_t ldq, uint32_t k, uint32_t *idx_out,
-                      double *dist_out) {
-    for (uint64_t i = blockIdx.x * uint64_t(NT) + threadIdx.x; i < nq;
-         i += uint64_t(gridDim.x) * NT) {
-        uint32_t *io = idx_out + i * k;
-        double *dout = dist_out + i * k;
+// One wave per query: the k nearest points of the tree, ascending by
+// (squared distance, original index).  Lane j holds the j-th entry of the
+// list; the 64 lanes take a leaf's points 64 at a time (coalesced reads) and
+// the candidates that beat the current k-th entry are inserted one by one.
+// The walk's stack is the wave's part of LDS (every lane writes the same
+// entry, so each lane reads back its own store).  pts: the tree's points in
+// position order [d][n]; perm: original index of each position.  Fewer than
+// k points: the list ends with (NONE, +inf).  A query with a NaN coordinate
+// gets (NONE, NaN) throughout.
+__global__ __launch_bounds__(NT) void k_knn(const int32_t *child, const uint32_t *dim,
+                                            const uint32_t *split, const float *split_f,
+                                            const uint32_t *nbeg, const uint32_t *nend,
+                                            const float *pts, uint64_t n, const uint32_t *perm,
+                                            const float *q, uint64_t nq, uint32_t d, uint64_t ldq,
+                                            uint32_t k, uint32_t *idx_out, double *dist_out) {
+    __shared__ uint32_t snode_all[NW][QUERY_STACK];
+    __shared__ double slb_all[NW][QUERY_STACK];
+    uint32_t *snode = snode_all[wave()];
+    double *slb = slb_all[wave()];
+    const int l = lane();
+    for (uint64_t i = blockIdx.x * uint64_t(NW) + wave(); i < nq; i += uint64_t(gridDim.x) * NW) {
         bool nan = false;
-        for (uint32_t c = 0; c < d; c++) {
+        for (uint32_t c = l; c < d; c += WAVE) {
             const float v = q[uint64_t(c) * ldq + i];
             nan |= v != v;
         }
-        if (nan) {
-            for (uint32_t j = 0; j < k; j++) {
-                io[j] = NONE;
-                dout[j] = __builtin_nan("");
+        if (__any(nan)) {
+            for (uint32_t j = l; j < k; j += WAVE) {
+                idx_out[i * k + j] = NONE;
+                dist_out[i * k + j] = __builtin_nan("");
             }
             continue;
         }
-        double bd[KNN_MAX];
-        uint32_t bi[KNN_MAX];
-        uint32_t m = 0;  // entries in the list
-        uint32_t snode[QUERY_STACK];
-        double slb[QUERY_STACK];
-        int sp = 0;
-        snode[sp] = 0;
-        slb[sp] = 0.0;
-        sp++;
+        double bd = __builtin_inf();  // this lane's list entry
+        uint32_t bi = NONE;
+        double worst = __builtin_inf();  // the k-th entry (lane k - 1)
+        uint32_t worst_i = NONE;
+        snode[0] = 0;
+        slb[0] = 0.0;
+        int sp = 1;
         while (sp > 0) {
             sp--;
             uint32_t node = snode[sp];
             const double lb = slb[sp];
-            if (m == k && lb > bd[k - 1]) continue;
-            // down to a leaf, keeping each far child with its lower bound
+            if (lb > worst) continue;
             for (int step = 0; step <= MAX_LEVELS; step++) {
                 const int32_t ch = child[node];
                 if (ch < 0) break;
@@ -84,31 +75,54 @@ __global__ void k_knn(const int32_t *child, const uint32_t *dim, const uint32_t 
                 double flb = gap * gap;
                 flb = flb != flb ? 0.0 : flb;  // no bound from infinite coordinates
                 flb = flb > lb ? flb : lb;
-                const uint32_t far = uint32_t(ch) + (left ? 1u : 0u);
-                if ((m < k || flb <= bd[k - 1]) && sp < QUERY_STACK) {
-                    snode[sp] = far;
+                if (flb <= worst && sp < QUERY_STACK) {
+                    snode[sp] = uint32_t(ch) + (left ? 1u : 0u);
                     slb[sp] = flb;
                     sp++;
                 }
                 node = uint32_t(ch) + (left ? 0u : 1u);
             }
-            for (uint32_t p = nbeg[node]; p < nend[node]; p++) {
-                const double dv = knn_dist(pts, n, p, q, ldq, i, d);
-                const uint32_t id = perm[p];
-                if (m == k && !knn_less(dv, id, bd[k - 1], bi[k - 1])) continue;
-                uint32_t j = m < k ? m++ : k - 1;  // insertion from the end
-                while (j > 0 && knn_less(dv, id, bd[j - 1], bi[j - 1])) {
-                    bd[j] = bd[j - 1];
-                    bi[j] = bi[j - 1];
-                    j--;
+            const uint32_t pb = nbeg[node], pe = nend[node];
+            for (uint32_t p0 = pb; p0 < pe; p0 += WAVE) {
+                const uint32_t p = p0 + l;
+                double dv = __builtin_inf();
+                uint32_t id = NONE;
+                if (p < pe) {
+                    // squared distance in fp64, summed in coordinate order (no
+                    // fused operations: the build compiles with contraction
+                    // off); a NaN sum (infinite coordinates) counts as +inf
+                    dv = 0.0;
+                    for (uint32_t c = 0; c < d; c++) {
+                        const double t = double(pts[uint64_t(c) * n + p]) - double(q[uint64_t(c) * ldq + i]);
+                        dv = dv + t * t;
+                    }
+                    dv = dv != dv ? __builtin_inf() : dv;
+                    id = perm[p];
                 }
-                bd[j] = dv;
-                bi[j] = id;
+                bool cand = p < pe && knn_less(dv, id, worst, worst_i);
+                for (unsigned long long m = __ballot(cand); m; m = __ballot(cand)) {
+                    const int src = __builtin_ctzll(m);
+                    const double cd = __shfl(dv, src, WAVE);
+                    const uint32_t cidx = __shfl(id, src, WAVE);
+                    if (l == src) cand = false;
+                    if (!knn_less(cd, cidx, worst, worst_i)) continue;  // the list moved on
+                    // lanes at or after the candidate's place shift up by one
+                    const bool after = !knn_less(bd, bi, cd, cidx);
+                    const double ud = __shfl_up(bd, 1, WAVE);
+                    const uint32_t ui = __shfl_up(bi, 1, WAVE);
+                    const bool prev_after = __shfl_up(after ? 1 : 0, 1, WAVE) != 0 && l > 0;
+                    if (after) {
+                        bd = prev_after ? ud : cd;
+                        bi = prev_after ? ui : cidx;
+                    }
+                    worst = __shfl(bd, int(k) - 1, WAVE);
+                    worst_i = __shfl(bi, int(k) - 1, WAVE);
+                }
             }
         }
-        for (uint32_t j = 0; j < k; j++) {
-            io[j] = j < m ? bi[j] : NONE;
-            dout[j] = j < m ? bd[j] : __builtin_inf();
+        if (uint32_t(l) < k) {
+            idx_out[i * k + l] = bi;
+            dist_out[i * k + l] = bd;
         }
     }
 }

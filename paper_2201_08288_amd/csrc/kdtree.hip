@@ -3104,7 +3104,7 @@ kd_status kd_query_knn(const kd_tree *tree, uint64_t n, const float *q, uint64_t
         k == 0 || k > KNN_MAX)
         return KD_EINVAL;
     if (nq == 0) return KD_OK;
-    hipLaunchKernelGGL(k_knn, dim3(grid_for(nq / NT + 1, 65535)), dim3(NT), 0,
+    hipLaunchKernelGGL(k_knn, dim3(grid_for((nq + NW - 1) / NW, 65535)), dim3(NT), 0,
                        reinterpret_cast<hipStream_t>(stream), tree->node_child, tree->node_dim,
                        tree->node_split, tree->node_split_f, tree->node_begin, tree->node_end,
                        tree->points_out, n, tree->perm, q, nq, d, ldq, k, idx_out, dist_out);
