@@ -146,15 +146,17 @@ def bench_batched(trees=512, reps=3):
                         "S=32, leaf 32, EXACT, cyclic"}
 
 
-def bench_queries(tree, xt, nq=1 << 20, nbox=1 << 16, k=8, reps=3):
+def bench_queries(tree, xt, nbox=1 << 16, k=8, reps=3):
     """Queries on the built tree: k nearest neighbours of data points moved by
-    a small Gaussian step, and boxes of half-width 0.05 around data points
-    (counts only)."""
+    a small Gaussian step (2^20 queries up to 8 dimensions, 2^12 above, where
+    each query visits many more leaves), and boxes of half-width 0.05 around
+    data points (counts only)."""
     import torch
 
     from paper_2201_08288_amd import kdtree, synth
     gen = torch.Generator(device="cuda").manual_seed(synth.BASE_SEED + 6)
     d, n = xt.shape
+    nq = 1 << 20 if d <= 8 else 1 << 12
     q = xt[:, torch.randint(0, n, (nq,), generator=gen, device="cuda")]
     q = (q + 0.05 * torch.randn(q.shape, generator=gen, device="cuda")).contiguous()
     c = xt[:, torch.randint(0, n, (nbox,), generator=gen, device="cuda")]
