@@ -209,6 +209,40 @@ kd_status kd_query_box(const kd_tree *tree, uint64_t n, const float *lo, const f
                        uint64_t nb, uint32_t d, uint64_t ldb, uint32_t *count_out,
                        const uint64_t *offsets, uint32_t *ids_out, void *stream);
 
+/* The paper's global single-pass construction (§3.2, Eq. (1)-(2); App. C in
+ * its basic form), for p <= 3 coordinates.  Points: device [p][ld] fp32,
+ * assumed to lie in (0,1)^p (the paper's standing assumption; mapping data
+ * there is the caller's choice).  Stream-ordered; KD_EINVAL (nothing
+ * enqueued) for a null pointer, p outside 1..3, J outside 1..15, depth
+ * outside 1..12, n == 0 or ld < n.
+ *
+ * kd_global_moments: ADDS to moments (device int64 [(2J+1)^p], first
+ * coordinate slowest) the statistics sum_i prod_l q_{j_l}(x_il), where q_0 =
+ * Q_p and q_{2j-1}, q_{2j} = rint(Q_p cos((2j-1)x)), rint(Q_p sin((2j-1)x))
+ * (fp32, own series), Q_1 = 2^24, Q_2 = 2^15, Q_3 = 2^10.  The sums are exact,
+ * so calls on any split of the data into subsets add up to the statistics of
+ * the whole (the paper's map-reduce); zero moments before the first call.
+ * Exact up to 2^32 points in total.                                        */
+kd_status kd_global_moments(const float *pts, uint64_t n, uint32_t p, uint64_t ld, uint32_t J,
+                            long long *moments, void *stream);
+
+/* kd_global_solve: the 2^depth - 1 medians of a depth-`depth` tree from the
+ * statistics alone: node i (heap order; children 2i+1 on the low side and
+ * 2i+2) splits coordinate (level mod p) of its cell box (a, b) at the root of
+ * Eq. (2), F(m) = sum_j D_j (g_j(a_t, m) - g_j(m, b_t)) with D the statistics
+ * contracted with Lemma 3.1's g_j(a_l, b_l) of the other coordinates, found
+ * by fp64 bisection from (a_t, b_t) (if F(a_t) >= 0 the median is a_t).
+ * medians: device fp64 [2^depth - 1].                                      */
+kd_status kd_global_solve(const long long *moments, uint32_t p, uint32_t J, uint32_t depth,
+                          double *medians, void *stream);
+
+/* kd_global_counts: points in each of the 2^depth leaf cells (descent: x_t
+ * <= median goes to the low side); counts: device uint64 [2^depth],
+ * overwritten.                                                             */
+kd_status kd_global_counts(const float *pts, uint64_t n, uint32_t p, uint64_t ld,
+                           const double *medians, uint32_t depth, unsigned long long *counts,
+                           void *stream);
+
 /* Launch shapes of the level kernels.  They change only how work is spread
  * over workgroups, never the result: every setting builds the same tree bit
  * for bit.  0 in a field means the default (2048 workgroups per digit pass,

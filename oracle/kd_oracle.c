@@ -617,3 +617,208 @@ uint64_t kdo_check_partition(const float *pts, uint32_t d, uint64_t ld, const ui
     }
     return bad;
 }
+
+/* ------------------------------------------------------------------ */
+/* The paper's global single-pass construction (§3.2 with Eq. (1) and  */
+/* (2); App. C, basic form K = 1): one pass over the data gives the    */
+/* statistics C_j(X) = sum_i prod_l c_{j_l}(x_il) for j in {0..2J}^p;  */
+/* every median of a depth-D tree then comes from solving Eq. (2) for  */
+/* its cell box (a, b), without revisiting the data.                   */
+/*                                                                     */
+/* Readings: the points are given in (0,1)^p (the paper's standing     */
+/* assumption; how data get there is left to the caller); c_0 = 1,     */
+/* c_{2j-1} = cos((2j-1)u), c_{2j} = sin((2j-1)u) in fp32 (own series  */
+/* and the harmonic recurrence, as the per-level rule), each quantised */
+/* as rint(c * Q_p), Q_1 = 2^24, Q_2 = 2^15, Q_3 = 2^10, so that every */
+/* product is an integer of at most 2^30 and the sums over up to 2^32  */
+/* points are exact in int64; the sums are not standardised (dividing  */
+/* by |X| does not move a root).                                       */
+/* Levels cycle through the coordinates; node i's children are 2i+1    */
+/* (low side) and 2i+2.                                                */
+/* ------------------------------------------------------------------ */
+
+float kdo_global_quantum(uint32_t p) { return p == 1 ? 16777216.0f : (p == 2 ? 32768.0f : 1024.0f); }
+
+/* q[0..2J] of one coordinate value u, quantum Q */
+void kdo_global_basis(float u, uint32_t J, float Q, float *q)
+{
+    float s1, c1;
+    kdo_sincos_f32(u, &s1, &c1);
+    float ss = s1 * s1;
+    float C2 = 1.0f - 2.0f * ss;
+    float sc = s1 * c1;
+    float S2 = 2.0f * sc;
+    float cj = c1, sj = s1;
+    q[0] = Q;
+    for (uint32_t j = 0; j < J; j++) {
+        q[2 * j + 1] = rintf(cj * Q);
+        q[2 * j + 2] = rintf(sj * Q);
+        float a = cj * C2, b = sj * S2;
+        float g = sj * C2, h = cj * S2;
+        cj = a - b;
+        sj = g + h;
+    }
+}
+
+/* C[(2J+1)^p] += the statistics of n points (pts: [p][ld], in (0,1)). */
+void kdo_global_moments(const float *pts, uint64_t n, uint32_t p, uint64_t ld, uint32_t J,
+                        int64_t *C)
+{
+    uint32_t E = 2 * J + 1;
+    float q[3][64];
+    float Q = kdo_global_quantum(p);
+    for (uint64_t i = 0; i < n; i++) {
+        for (uint32_t c = 0; c < p; c++) kdo_global_basis(pts[c * ld + i], J, Q, q[c]);
+        if (p == 1) {
+            for (uint32_t a = 0; a < E; a++) C[a] += (int64_t)q[0][a];
+        } else if (p == 2) {
+            for (uint32_t a = 0; a < E; a++)
+                for (uint32_t b = 0; b < E; b++) C[a * E + b] += (int64_t)q[0][a] * (int64_t)q[1][b];
+        } else {
+            for (uint32_t a = 0; a < E; a++)
+                for (uint32_t b = 0; b < E; b++) {
+                    int64_t ab = (int64_t)q[0][a] * (int64_t)q[1][b];
+                    for (uint32_t d = 0; d < E; d++) C[(a * E + b) * E + d] += ab * (int64_t)q[2][d];
+                }
+        }
+    }
+}
+
+/* sin((2j-1)x), cos((2j-1)x) for j = 1..J (fp64, own series, recurrence) */
+static void global_harmonics(double x, uint32_t J, double *s, double *c)
+{
+    double s1, c1;
+    kdo_sincos_f64(x, &s1, &c1);
+    double ss = s1 * s1;
+    double C2 = 1.0 - 2.0 * ss;
+    double sc = s1 * c1;
+    double S2 = 2.0 * sc;
+    double cj = c1, sj = s1;
+    for (uint32_t j = 0; j < J; j++) {
+        s[j] = sj;
+        c[j] = cj;
+        double a = cj * C2, b = sj * S2;
+        double g = sj * C2, h = cj * S2;
+        cj = a - b;
+        sj = g + h;
+    }
+}
+
+/* g_0..g_{2J} of Lemma 3.1 for the interval (a, b) of (0, 1) */
+void kdo_global_g(double a, double b, uint32_t J, double *g)
+{
+    double sa[64], ca[64], sb[64], cb[64];
+    int ia = a > 0.0, ib = b < 1.0;
+    global_harmonics(a, J, sa, ca);
+    global_harmonics(b, J, sb, cb);
+    g[0] = 1.0 - 0.5 * (double)(ia + ib);
+    for (uint32_t j = 1; j <= J; j++) {
+        double k = 2.0 / (M_PI * (double)(2 * j - 1));
+        double s_b = ib ? sb[j - 1] : 0.0, s_a = ia ? sa[j - 1] : 0.0;
+        double c_a = ia ? ca[j - 1] : 0.0, c_b = ib ? cb[j - 1] : 0.0;
+        g[2 * j - 1] = k * (s_b - s_a);
+        g[2 * j] = k * (c_a - c_b);
+    }
+}
+
+/* Eq. (2) for one cell: F(m) = 1_J(X, a, b_t <- m) - 1_J(X, a_t <- m, b),
+ * given D_j = the statistics contracted with the g weights of the other
+ * coordinates. */
+static double global_F(const double *D, uint32_t J, double at, double bt, double m)
+{
+    double gl[129], gr[129];
+    kdo_global_g(at, m, J, gl);
+    kdo_global_g(m, bt, J, gr);
+    double F = 0.0;
+    for (uint32_t j = 0; j <= 2 * J; j++) F = F + D[j] * (gl[j] - gr[j]);
+    return F;
+}
+
+/* The 2^depth - 1 medians (mapped domain) in heap order. */
+void kdo_global_solve(const int64_t *C, uint32_t p, uint32_t J, uint32_t depth, double *med)
+{
+    uint32_t E = 2 * J + 1;
+    uint64_t nodes = ((uint64_t)1 << depth) - 1;
+    double *lo = calloc((2 * nodes + 1) * p, sizeof(double));
+    double *hi = calloc((2 * nodes + 1) * p, sizeof(double));
+    for (uint32_t c = 0; c < p; c++) hi[c] = 1.0;
+    double W[3][129], D[129];
+    for (uint64_t i = 0; i < nodes; i++) {
+        uint32_t dep = 0;
+        while ((((uint64_t)2 << dep) - 1) <= i) dep++;
+        uint32_t t = dep % p;
+        const double *a = lo + i * p, *b = hi + i * p;
+        for (uint32_t c = 0; c < p; c++)
+            if (c != t) kdo_global_g(a[c], b[c], J, W[c]);
+        uint32_t oth[2] = {0, 0}, no = 0;
+        for (uint32_t c = 0; c < p; c++)
+            if (c != t) oth[no++] = c;
+        for (uint32_t jt = 0; jt < E; jt++) {
+            if (p == 1) {
+                D[jt] = (double)C[jt];
+            } else if (p == 2) {
+                double acc = 0.0;
+                for (uint32_t ju = 0; ju < E; ju++) {
+                    uint32_t idx[2];
+                    idx[t] = jt;
+                    idx[oth[0]] = ju;
+                    acc = acc + (double)C[idx[0] * E + idx[1]] * W[oth[0]][ju];
+                }
+                D[jt] = acc;
+            } else {
+                double acc = 0.0;
+                for (uint32_t ju = 0; ju < E; ju++) {
+                    double inner = 0.0;
+                    for (uint32_t jv = 0; jv < E; jv++) {
+                        uint32_t idx[3];
+                        idx[t] = jt;
+                        idx[oth[0]] = ju;
+                        idx[oth[1]] = jv;
+                        inner = inner + (double)C[(idx[0] * E + idx[1]) * E + idx[2]] * W[oth[1]][jv];
+                    }
+                    acc = acc + inner * W[oth[0]][ju];
+                }
+                D[jt] = acc;
+            }
+        }
+        double l = a[t], h = b[t], m;
+        if (global_F(D, J, a[t], b[t], l) >= 0.0) {
+            m = l;
+        } else {
+            for (int it = 0; it < 200; it++) {
+                double mid = l + (h - l) * 0.5;
+                if (!(mid > l && mid < h)) break;
+                if (global_F(D, J, a[t], b[t], mid) < 0.0) l = mid;
+                else h = mid;
+            }
+            m = h;
+        }
+        med[i] = m;
+        uint64_t L = 2 * i + 1, R = 2 * i + 2;
+        for (uint32_t c = 0; c < p; c++) {
+            lo[L * p + c] = a[c];
+            hi[L * p + c] = b[c];
+            lo[R * p + c] = a[c];
+            hi[R * p + c] = b[c];
+        }
+        hi[L * p + t] = m;
+        lo[R * p + t] = m;
+    }
+    free(lo);
+    free(hi);
+}
+
+/* Points per leaf cell: descend with u_t <= m to the low side. */
+void kdo_global_counts(const float *pts, uint64_t n, uint32_t p, uint64_t ld, const double *med,
+                       uint32_t depth, uint64_t *counts)
+{
+    uint64_t nodes = ((uint64_t)1 << depth) - 1;
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t k = 0;
+        for (uint32_t d = 0; d < depth; d++) {
+            uint32_t t = d % p;
+            k = (double)pts[t * ld + i] <= med[k] ? 2 * k + 1 : 2 * k + 2;
+        }
+        counts[k - nodes]++;
+    }
+}

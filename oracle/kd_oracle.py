@@ -91,6 +91,18 @@ def lib():
         L.kdo_check_partition.argtypes = [vp, u32, u64, vp, u64, vp, vp, vp, vp, vp]
         L.kdo_query_leaf.restype = u32
         L.kdo_query_leaf.argtypes = [vp, vp, vp, vp, vp, u64]
+        L.kdo_global_quantum.restype = ctypes.c_float
+        L.kdo_global_quantum.argtypes = [u32]
+        L.kdo_global_basis.restype = None
+        L.kdo_global_basis.argtypes = [ctypes.c_float, u32, ctypes.c_float, vp]
+        L.kdo_global_g.restype = None
+        L.kdo_global_g.argtypes = [ctypes.c_double, ctypes.c_double, u32, vp]
+        L.kdo_global_moments.restype = None
+        L.kdo_global_moments.argtypes = [vp, u64, u32, u64, u32, vp]
+        L.kdo_global_solve.restype = None
+        L.kdo_global_solve.argtypes = [vp, u32, u32, u32, vp]
+        L.kdo_global_counts.restype = None
+        L.kdo_global_counts.argtypes = [vp, u64, u32, u64, vp, u32, vp]
         _lib = L
     return _lib
 
@@ -350,3 +362,62 @@ def box_query(points, lo, hi):
         inside = np.all((p >= lo[:, i:i + 1]) & (p <= hi[:, i:i + 1]), axis=0)
         out.append(np.nonzero(inside)[0].astype(np.uint32))
     return out
+
+
+# ---------------------------------------------------------------- global method
+# The paper's single-pass construction (§3.2, Eq. (1)-(2); App. C, K = 1).
+
+
+def global_quantum(p):
+    """Quantum Q_p of the basis values for p coordinates."""
+    return float(lib().kdo_global_quantum(p))
+
+
+def global_basis(u, J, p=3):
+    """Quantised basis rint(c_j(u) * Q_p), j = 0..2J, of one value in (0,1)."""
+    q = np.zeros(2 * J + 1, dtype=np.float32)
+    lib().kdo_global_basis(ctypes.c_float(u), J, ctypes.c_float(global_quantum(p)), _ptr(q))
+    return q
+
+
+def global_g(a, b, J):
+    """g_0..g_{2J}(a, b) of Lemma 3.1 (fp64)."""
+    g = np.zeros(2 * J + 1, dtype=np.float64)
+    lib().kdo_global_g(ctypes.c_double(a), ctypes.c_double(b), J, _ptr(g))
+    return g
+
+
+def global_moments(points, J=15):
+    """The statistics C_j, j in {0..2J}^p (int64, first coordinate slowest)
+    of points in (0,1)^p (float32 (p, n))."""
+    p = np.ascontiguousarray(points, dtype=np.float32)
+    d, n = p.shape
+    C = np.zeros((2 * J + 1) ** d, dtype=np.int64)
+    lib().kdo_global_moments(_ptr(p), n, d, n, J, _ptr(C))
+    return C
+
+
+def global_solve(C, p, J=15, depth=6):
+    """The 2^depth - 1 medians of Eq. (2), heap order (node i: children 2i+1
+    on the low side, 2i+2), cycling through the coordinates by level."""
+    C = np.ascontiguousarray(C, dtype=np.int64)
+    med = np.zeros((1 << depth) - 1, dtype=np.float64)
+    lib().kdo_global_solve(_ptr(C), p, J, depth, _ptr(med))
+    return med
+
+
+def global_counts(points, med, depth):
+    """Points of each leaf cell (u_t <= m goes to the low side)."""
+    p = np.ascontiguousarray(points, dtype=np.float32)
+    d, n = p.shape
+    cnt = np.zeros(1 << depth, dtype=np.uint64)
+    lib().kdo_global_counts(_ptr(p), n, d, n, _ptr(np.ascontiguousarray(med, dtype=np.float64)),
+                            depth, _ptr(cnt))
+    return cnt
+
+
+def global_build(points, J=15, depth=6):
+    """Moments, medians and leaf counts of the global construction."""
+    C = global_moments(points, J)
+    med = global_solve(C, np.asarray(points).shape[0], J, depth)
+    return {"moments": C, "medians": med, "counts": global_counts(points, med, depth)}

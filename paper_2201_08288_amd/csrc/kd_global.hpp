@@ -1,0 +1,269 @@
+// kd_global.hpp -- the paper's global single-pass construction (§3.2 with
+// Eq. (1) and (2); App. C, basic form): one pass over points in (0,1)^p sums
+// C_j = sum_i prod_l c_{j_l}(x_il) for every j in {0..2J}^p; each median of a
+// depth-D tree is then the solution of Eq. (2) for its cell box, computed
+// from the C_j alone.
+//
+// Map step: per point and coordinate the basis c_0 = 1, c_{2j-1} =
+// cos((2j-1)u), c_{2j} = sin((2j-1)u) in fp32 (own series and the harmonic
+// recurrence), each quantised as rint(c * Q_p) with Q_1 = 2^24, Q_2 = 2^15,
+// Q_3 = 2^10.  Every product of p quantised values is an integer of at most
+// 2^30; a workgroup adds at most 2^23 points' products in fp64 (exact: every
+// partial sum is an integer below 2^53), converts once to int64 and adds
+// atomically, so the statistics are exact and independent of how the points
+// are split (the paper's map-reduce).
+// Solve step: for a cell (a, b) split on coordinate t, the statistics are
+// contracted with the Lemma 3.1 weights g_j(a_l, b_l) of the other
+// coordinates (fp64, fixed order), and Eq. (2) becomes F(m) = 0 with
+//   F(m) = sum_j D_j (g_j(a_t, m) - g_j(m, b_t)),
+// solved by bisection in fp64 from (a_t, b_t).
+#pragma once
+#include "kd_fourier.hpp"
+
+namespace kd {
+
+constexpr int GLOBAL_JMAX = 15;
+constexpr int GLOBAL_EP = 32;           // basis entries per coordinate, padded (2J+1 <= 31)
+constexpr int GLOBAL_CHUNK = 64;        // points staged in LDS per step
+constexpr int GLOBAL_MAX_DEPTH = 12;
+constexpr uint64_t GLOBAL_EXACT_POINTS = 1ull << 23;  // per workgroup: fp64 sums stay exact
+
+__host__ __device__ constexpr float global_quantum(int p) {
+    return p == 1 ? 16777216.0f : (p == 2 ? 32768.0f : 1024.0f);
+}
+
+// Quantised basis of one coordinate value; q[2J+1 .. GLOBAL_EP) = 0.
+__device__ __forceinline__ void global_basis(float u, int J, float Q, const TrigTables &T,
+                                             float *q) {
+    float s1, c1;
+    sincos32(u, T, s1, c1);
+    const float ss = s1 * s1;
+    const float C2 = 1.0f - 2.0f * ss;
+    const float sc = s1 * c1;
+    const float S2 = 2.0f * sc;
+    float cj = c1, sj = s1;
+    q[0] = Q;
+    for (int j = 0; j < J; j++) {
+        q[2 * j + 1] = rintf(cj * Q);
+        q[2 * j + 2] = rintf(sj * Q);
+        const float a = cj * C2, b = sj * S2;
+        const float g = sj * C2, h = cj * S2;
+        cj = a - b;
+        sj = g + h;
+    }
+    for (int k = 2 * J + 1; k < GLOBAL_EP; k++) q[k] = 0.0f;
+}
+
+// Map step.  Thread item (a, b, blk): entries (a, b, 8 blk .. 8 blk + 7) of
+// the statistics for p = 3 (first coordinate slowest); for p = 2 the entries
+// (b, 8 blk ..), for p = 1 (8 blk ..).  Grid: (item groups, point ranges of
+// `per` points each, per <= GLOBAL_EXACT_POINTS).  C: int64 as uint64, added to.
+template <int P>
+__global__ __launch_bounds__(NT) void k_gmom(const float *pts, uint64_t n, uint64_t ld, uint32_t J,
+                                             uint64_t per, TrigTables T, unsigned long long *C) {
+    __shared__ __attribute__((aligned(16))) float q[P][GLOBAL_CHUNK][GLOBAL_EP];
+    const uint32_t E = 2 * J + 1;
+    const float Q = global_quantum(P);
+    const uint32_t items = (P >= 3 ? E : 1u) * (P >= 2 ? E : 1u) * 4u;
+    const uint32_t item = blockIdx.x * NT + threadIdx.x;
+    const bool active = item < items;
+    const uint32_t blk = item % 4u, ab = item / 4u;
+    const uint32_t b = P >= 2 ? ab % E : 0u, a = P >= 3 ? ab / E : 0u;
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) acc[k] = 0.0;
+    const uint64_t p0 = uint64_t(blockIdx.y) * per;
+    const uint64_t p1 = p0 + per < n ? p0 + per : n;
+    for (uint64_t c0 = p0; c0 < p1; c0 += GLOBAL_CHUNK) {
+        const uint32_t m = uint32_t(p1 - c0 < GLOBAL_CHUNK ? p1 - c0 : GLOBAL_CHUNK);
+        __syncthreads();  // the previous chunk is consumed
+        for (uint32_t w = threadIdx.x; w < uint32_t(P * GLOBAL_CHUNK); w += NT) {
+            const uint32_t c = w / GLOBAL_CHUNK, i = w % GLOBAL_CHUNK;
+            if (i < m) global_basis(pts[uint64_t(c) * ld + c0 + i], int(J), Q, T, q[c][i]);
+        }
+        __syncthreads();
+        if (active) {
+            for (uint32_t i = 0; i < m; i++) {
+                const double qa = P >= 3 ? double(q[0][i][a]) : 1.0;
+                const double qb = P >= 2 ? double(q[P - 2][i][b]) : 1.0;
+                const double qab = qa * qb;
+                const float4 x0 = *reinterpret_cast<const float4 *>(&q[P - 1][i][8 * blk]);
+                const float4 x1 = *reinterpret_cast<const float4 *>(&q[P - 1][i][8 * blk + 4]);
+                acc[0] = __fma_rn(qab, double(x0.x), acc[0]);
+                acc[1] = __fma_rn(qab, double(x0.y), acc[1]);
+                acc[2] = __fma_rn(qab, double(x0.z), acc[2]);
+                acc[3] = __fma_rn(qab, double(x0.w), acc[3]);
+                acc[4] = __fma_rn(qab, double(x1.x), acc[4]);
+                acc[5] = __fma_rn(qab, double(x1.y), acc[5]);
+                acc[6] = __fma_rn(qab, double(x1.z), acc[6]);
+                acc[7] = __fma_rn(qab, double(x1.w), acc[7]);
+            }
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const uint32_t c = 8 * blk + uint32_t(k);
+        if (c >= E || acc[k] == 0.0) continue;
+        const uint64_t e = P == 3 ? (uint64_t(a) * E + b) * E + c : (P == 2 ? uint64_t(b) * E + c : c);
+        atomicAdd(&C[e], (unsigned long long)(long long)acc[k]);
+    }
+}
+
+// sin((2j-1)x), cos((2j-1)x), j = 1..J (fp64, own series, recurrence).
+__device__ __forceinline__ void global_harmonics(double x, int J, const TrigTables &T, double *s,
+                                                 double *c) {
+    double s1, c1;
+    sincos64(x, T, s1, c1);
+    const double ss = s1 * s1;
+    const double C2 = 1.0 - 2.0 * ss;
+    const double sc = s1 * c1;
+    const double S2 = 2.0 * sc;
+    double cj = c1, sj = s1;
+    for (int j = 0; j < J; j++) {
+        s[j] = sj;
+        c[j] = cj;
+        const double a = cj * C2, b = sj * S2;
+        const double g = sj * C2, h = cj * S2;
+        cj = a - b;
+        sj = g + h;
+    }
+}
+
+// g_0 .. g_{2J} of Lemma 3.1 for the interval (a, b) of (0, 1).
+__device__ __forceinline__ void global_g(double a, double b, int J, const TrigTables &T, double *g) {
+    double sa[GLOBAL_JMAX], ca[GLOBAL_JMAX], sb[GLOBAL_JMAX], cb[GLOBAL_JMAX];
+    const bool ia = a > 0.0, ib = b < 1.0;
+    global_harmonics(a, J, T, sa, ca);
+    global_harmonics(b, J, T, sb, cb);
+    g[0] = 1.0 - 0.5 * double(int(ia) + int(ib));
+    for (int j = 1; j <= J; j++) {
+        const double k = 2.0 / (3.14159265358979323846 * double(2 * j - 1));
+        const double s_b = ib ? sb[j - 1] : 0.0, s_a = ia ? sa[j - 1] : 0.0;
+        const double c_a = ia ? ca[j - 1] : 0.0, c_b = ib ? cb[j - 1] : 0.0;
+        g[2 * j - 1] = k * (s_b - s_a);
+        g[2 * j] = k * (c_a - c_b);
+    }
+}
+
+__device__ __forceinline__ double global_F(const double *D, int J, const TrigTables &T, double at,
+                                           double bt, double m) {
+    double gl[2 * GLOBAL_JMAX + 1], gr[2 * GLOBAL_JMAX + 1];
+    global_g(at, m, J, T, gl);
+    global_g(m, bt, J, T, gr);
+    double F = 0.0;
+    for (int j = 0; j <= 2 * J; j++) F = F + D[j] * (gl[j] - gr[j]);
+    return F;
+}
+
+// Solve step for the cells of one level (one wave per cell).  The cell's
+// box comes from its ancestors' medians; node i's children are 2i+1 (low
+// side) and 2i+2; levels cycle through the coordinates.
+template <int P>
+__global__ __launch_bounds__(NT) void k_gsolve(const long long *C, uint32_t J, uint32_t level,
+                                               TrigTables T, double *med) {
+    __shared__ double sW[NW][P][GLOBAL_EP];
+    __shared__ double sD[NW][GLOBAL_EP];
+    const int w = wave(), l = lane();
+    const uint64_t cell = uint64_t(blockIdx.x) * NW + w;
+    if (cell >= (1ull << level)) return;  // whole wave
+    const uint64_t node = (1ull << level) - 1 + cell;
+    const uint32_t t = level % P;
+    const uint32_t E = 2 * J + 1;
+    double lo[P], hi[P];
+    for (int c = 0; c < P; c++) {
+        lo[c] = 0.0;
+        hi[c] = 1.0;
+    }
+    const uint64_t k1 = node + 1;  // 1-based heap index
+    for (uint32_t d = 0; d < level; d++) {
+        const uint64_t anc = (k1 >> (level - d)) - 1;
+        const bool right = (k1 >> (level - d - 1)) & 1ull;
+        const double m = med[anc];
+        if (right) lo[d % P] = m;
+        else hi[d % P] = m;
+    }
+    if (l == 0)
+        for (int c = 0; c < P; c++)
+            if (uint32_t(c) != t) global_g(lo[c], hi[c], int(J), T, sW[w][c]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t oth[2] = {0, 0}, no = 0;
+    for (uint32_t c = 0; c < uint32_t(P); c++)
+        if (c != t) oth[no++] = c;
+    if (uint32_t(l) < E) {
+        const uint32_t jt = uint32_t(l);
+        double D;
+        if (P == 1) {
+            D = double(C[jt]);
+        } else if (P == 2) {
+            double acc = 0.0;
+            for (uint32_t ju = 0; ju < E; ju++) {
+                uint32_t idx[2];
+                idx[t] = jt;
+                idx[oth[0]] = ju;
+                acc = acc + double(C[idx[0] * E + idx[1]]) * sW[w][oth[0]][ju];
+            }
+            D = acc;
+        } else {
+            double acc = 0.0;
+            for (uint32_t ju = 0; ju < E; ju++) {
+                double inner = 0.0;
+                for (uint32_t jv = 0; jv < E; jv++) {
+                    uint32_t idx[3];
+                    idx[t] = jt;
+                    idx[oth[0]] = ju;
+                    idx[oth[1]] = jv;
+                    inner = inner + double(C[(idx[0] * E + idx[1]) * E + idx[2]]) * sW[w][oth[1]][jv];
+                }
+                acc = acc + inner * sW[w][oth[0]][ju];
+            }
+            D = acc;
+        }
+        sD[w][jt] = D;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (l != 0) return;
+    const double at = lo[t], bt = hi[t];
+    double a = at, b = bt, m;
+    if (global_F(sD[w], int(J), T, at, bt, a) >= 0.0) {
+        m = a;
+    } else {
+        for (int it = 0; it < 200; it++) {
+            const double mid = a + (b - a) * 0.5;
+            if (!(mid > a && mid < b)) break;
+            if (global_F(sD[w], int(J), T, at, bt, mid) < 0.0) a = mid;
+            else b = mid;
+        }
+        m = b;
+    }
+    med[node] = m;
+}
+
+// Points per leaf cell (descent: u_t <= m to the low side).  counts must
+// start at zero.
+__global__ __launch_bounds__(NT) void k_gcount(const float *pts, uint64_t n, uint64_t ld, uint32_t P,
+                                               const double *med, uint32_t depth,
+                                               unsigned long long *counts) {
+    __shared__ uint32_t h[1 << GLOBAL_MAX_DEPTH];
+    const uint32_t leaves = 1u << depth;
+    const uint64_t nodes = uint64_t(leaves) - 1;
+    for (uint32_t k = threadIdx.x; k < leaves; k += NT) h[k] = 0;
+    __syncthreads();
+    for (uint64_t i = blockIdx.x * uint64_t(NT) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * NT) {
+        uint64_t k = 0;
+        for (uint32_t d = 0; d < depth; d++) {
+            const uint32_t t = d % P;
+            k = double(pts[uint64_t(t) * ld + i]) <= med[k] ? 2 * k + 1 : 2 * k + 2;
+        }
+        atomicAdd(&h[k - nodes], 1u);
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < leaves; k += NT)
+        if (h[k]) atomicAdd(&counts[k], (unsigned long long)h[k]);
+}
+
+}  // namespace kd

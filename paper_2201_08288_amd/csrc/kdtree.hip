@@ -32,6 +32,7 @@
 #include "kdtree.h"
 #include "kd_device.hpp"
 #include "kd_fourier.hpp"
+#include "kd_global.hpp"
 #include "kd_query.hpp"
 #include "kd_select.hpp"
 
@@ -3123,6 +3124,62 @@ kd_status kd_query_box(const kd_tree *tree, uint64_t n, const float *lo, const f
                        reinterpret_cast<hipStream_t>(stream), tree->node_child, tree->node_dim,
                        tree->node_split, tree->node_begin, tree->node_end, tree->points_out, n,
                        tree->perm, lo, hi, nb, d, ldb, count_out, offsets, ids_out);
+    KD_LAUNCH_CHECK();
+    return KD_OK;
+}
+
+kd_status kd_global_moments(const float *pts, uint64_t n, uint32_t p, uint64_t ld, uint32_t J,
+                            long long *moments, void *stream) {
+    if (!pts || !moments || n == 0 || n > 0xffffff00ull || ld < n || p < 1 || p > 3 || J < 1 ||
+        J > uint32_t(GLOBAL_JMAX))
+        return KD_EINVAL;
+    const uint32_t E = 2 * J + 1;
+    const uint32_t items = (p >= 3 ? E : 1u) * (p >= 2 ? E : 1u) * 4u;
+    const uint32_t groups = (items + NT - 1) / NT;
+    // point ranges: every workgroup's sums stay exact, and about 2048 workgroups
+    uint64_t splits = std::min<uint64_t>((2048 + groups - 1) / groups, (n + GLOBAL_CHUNK - 1) / GLOBAL_CHUNK);
+    splits = std::max<uint64_t>(splits, (n + GLOBAL_EXACT_POINTS - 1) / GLOBAL_EXACT_POINTS);
+    const uint64_t per = (n + splits - 1) / splits;
+    splits = (n + per - 1) / per;
+    const TrigTables T = make_trig();
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long *C = reinterpret_cast<unsigned long long *>(moments);
+    const dim3 g(groups, uint32_t(splits));
+    if (p == 1) hipLaunchKernelGGL(k_gmom<1>, g, dim3(NT), 0, st, pts, n, ld, J, per, T, C);
+    else if (p == 2) hipLaunchKernelGGL(k_gmom<2>, g, dim3(NT), 0, st, pts, n, ld, J, per, T, C);
+    else hipLaunchKernelGGL(k_gmom<3>, g, dim3(NT), 0, st, pts, n, ld, J, per, T, C);
+    KD_LAUNCH_CHECK();
+    return KD_OK;
+}
+
+kd_status kd_global_solve(const long long *moments, uint32_t p, uint32_t J, uint32_t depth,
+                          double *medians, void *stream) {
+    if (!moments || !medians || p < 1 || p > 3 || J < 1 || J > uint32_t(GLOBAL_JMAX) || depth < 1 ||
+        depth > uint32_t(GLOBAL_MAX_DEPTH))
+        return KD_EINVAL;
+    const TrigTables T = make_trig();
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    for (uint32_t level = 0; level < depth; level++) {
+        const dim3 g(((1u << level) + NW - 1) / NW);
+        if (p == 1) hipLaunchKernelGGL(k_gsolve<1>, g, dim3(NT), 0, st, moments, J, level, T, medians);
+        else if (p == 2) hipLaunchKernelGGL(k_gsolve<2>, g, dim3(NT), 0, st, moments, J, level, T, medians);
+        else hipLaunchKernelGGL(k_gsolve<3>, g, dim3(NT), 0, st, moments, J, level, T, medians);
+        KD_LAUNCH_CHECK();
+    }
+    return KD_OK;
+}
+
+kd_status kd_global_counts(const float *pts, uint64_t n, uint32_t p, uint64_t ld,
+                           const double *medians, uint32_t depth, unsigned long long *counts,
+                           void *stream) {
+    if (!pts || !medians || !counts || n == 0 || ld < n || p < 1 || p > 3 || depth < 1 ||
+        depth > uint32_t(GLOBAL_MAX_DEPTH))
+        return KD_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((2ull << depth) / NT + 1, 64)), dim3(NT), 0, st,
+                       reinterpret_cast<uint32_t *>(counts), 2ull << depth, 0u);
+    hipLaunchKernelGGL(k_gcount, dim3(grid_for(n / NT + 1, 2048)), dim3(NT), 0, st, pts, n, ld, p,
+                       medians, depth, counts);
     KD_LAUNCH_CHECK();
     return KD_OK;
 }

@@ -101,6 +101,12 @@ def lib():
         L.kd_query_box.restype = st
         L.kd_query_box.argtypes = [ctypes.POINTER(TreeStruct), _u64, _vp, _vp, _u64, _u32, _u64,
                                    _vp, _vp, _vp, _vp]
+        L.kd_global_moments.restype = st
+        L.kd_global_moments.argtypes = [_vp, _u64, _u32, _u64, _u32, _vp, _vp]
+        L.kd_global_solve.restype = st
+        L.kd_global_solve.argtypes = [_vp, _u32, _u32, _u32, _vp, _vp]
+        L.kd_global_counts.restype = st
+        L.kd_global_counts.argtypes = [_vp, _u64, _u32, _u64, _vp, _u32, _vp, _vp]
         L.kd_set_tuning.restype = st
         L.kd_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
         L.kd_get_tuning.restype = st
@@ -326,6 +332,35 @@ def query_box(tree, lo, hi, ids=False, stream=None):
                           ldb, cnt2.data_ptr(), off.data_ptr(), out.data_ptr(), _stream_ptr(stream)),
            "kd_query_box")
     return cnt, off, out[:total]
+
+
+def global_moments(points, J=15, moments=None, stream=None):
+    """kd_global_moments over the columns of a (p, ld)-strided float32 CUDA
+    tensor of points in (0,1)^p; adds to `moments` (int64 [(2J+1)^p], a new
+    zeroed tensor if None) and returns it."""
+    d, n, ld = _query_cols(points)
+    if moments is None:
+        moments = torch.zeros((2 * J + 1) ** d, dtype=torch.int64, device=points.device)
+    _check(lib().kd_global_moments(points.data_ptr(), n, d, ld, J, moments.data_ptr(),
+                                   _stream_ptr(stream)), "kd_global_moments")
+    return moments
+
+
+def global_solve(moments, p, J=15, depth=6, stream=None):
+    """kd_global_solve: the 2^depth - 1 medians (float64, heap order)."""
+    med = torch.empty((1 << depth) - 1, dtype=torch.float64, device=moments.device)
+    _check(lib().kd_global_solve(moments.data_ptr(), p, J, depth, med.data_ptr(),
+                                 _stream_ptr(stream)), "kd_global_solve")
+    return med
+
+
+def global_counts(points, medians, depth, stream=None):
+    """kd_global_counts: points per leaf cell (int64 [2^depth])."""
+    d, n, ld = _query_cols(points)
+    cnt = torch.empty(1 << depth, dtype=torch.int64, device=points.device)
+    _check(lib().kd_global_counts(points.data_ptr(), n, d, ld, medians.data_ptr(), depth,
+                                  cnt.data_ptr(), _stream_ptr(stream)), "kd_global_counts")
+    return cnt
 
 
 def set_tuning(hist_blocks=0, scatter_blocks=0, small_blocks=0):
