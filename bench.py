@@ -181,6 +181,51 @@ def bench_queries(tree, xt, nbox=1 << 16, k=8, reps=3):
                         "boxes of half-width 0.05 around data points"}
 
 
+def bench_global(n=1 << 26, J=15, depths=(6, 10), reps=3):
+    """The paper's global single-pass construction on its §5 workload shape:
+    trivariate normal, common correlation 0.5, each coordinate mapped into
+    (0,1) by the standard normal CDF (generated on the device)."""
+    import numpy as np
+    import torch
+
+    from paper_2201_08288_amd import kdtree, synth
+    gen = torch.Generator(device="cuda").manual_seed(synth.BASE_SEED + 7)
+    rho = 0.5
+    cov = torch.full((3, 3), rho, dtype=torch.float64, device="cuda")
+    cov.fill_diagonal_(1.0)
+    L = torch.linalg.cholesky(cov)
+    z = torch.randn((3, n), generator=gen, device="cuda", dtype=torch.float64)
+    u = torch.special.ndtr(L @ z).clamp(2.0 ** -24, 1 - 2.0 ** -24).to(torch.float32).contiguous()
+    del z
+    C = kdtree.global_moments(u, J)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        C = kdtree.global_moments(u, J)
+    torch.cuda.synchronize()
+    t_map = (time.perf_counter() - t0) / reps
+    flops = 2.0 * n * (2 * J + 1) ** 3
+    out = {"n": n, "p": 3, "J": J, "map_ms": 1e3 * t_map, "map_points_per_s": n / t_map,
+           "map_fp64_TFLOPs": flops / t_map / 1e12, "fp64_peak_TFLOPs": 78.6,
+           "workload": "trivariate normal, rho 0.5, mapped into (0,1) by the normal CDF"}
+    for depth in depths:
+        med = kdtree.global_solve(C, 3, J, depth)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        med = kdtree.global_solve(C, 3, J, depth)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        cnt = kdtree.global_counts(u, med, depth)
+        torch.cuda.synchronize()
+        rel = np.log2(cnt.cpu().numpy() / (n / 2 ** depth))
+        q1, q3 = np.percentile(rel, [25, 75])
+        out[f"depth{depth}"] = {"solve_ms": 1e3 * t_solve, "log2_rel_min": float(rel.min()),
+                                "log2_rel_max": float(rel.max()), "log2_rel_iqr": [float(q1), float(q3)]}
+    del u
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_serving(rates=(50, 200, 1000, 2000), per_rate=150, warm=20, workers=3):
     """Poisson build requests (n log-uniform [2^12, 2^22], d in {3,16},
     Gaussian mixture, S=64, leaf 64) each followed by 1,024 lookups of its
@@ -230,6 +275,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-queries", action="store_true")
+    ap.add_argument("--no-global", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch shapes instead of kd_autotune's choice")
     ap.add_argument("--tuning", default=None, metavar="HIST,SCATTER,SMALL",
@@ -346,6 +392,11 @@ def main():
         log("[bench] queries (kNN, boxes)")
         queries = bench_queries(tree, xt)
 
+    glob = None
+    if not args.no_global:
+        log("[bench] global single-pass construction")
+        glob = bench_global()
+
     batched = serving = None
     kdtree.set_tuning()  # batched and serving run the default launch shapes
     if not args.no_batched:
@@ -375,7 +426,7 @@ def main():
         "whole_build_alg_frac": round(level_gbps / HBM_PEAK_GBPS, 4),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "copy_GBps": round(copy_gbps, 1),
-        "batched": batched, "serving": serving, "queries": queries,
+        "batched": batched, "serving": serving, "queries": queries, "global": glob,
     }
     print(json.dumps(out), flush=True)
 

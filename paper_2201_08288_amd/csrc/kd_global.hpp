@@ -32,9 +32,10 @@ __host__ __device__ constexpr float global_quantum(int p) {
     return p == 1 ? 16777216.0f : (p == 2 ? 32768.0f : 1024.0f);
 }
 
-// Quantised basis of one coordinate value; q[2J+1 .. GLOBAL_EP) = 0.
-__device__ __forceinline__ void global_basis(float u, int J, float Q, const TrigTables &T,
-                                             float *q) {
+// Quantised basis of one coordinate value (integers, stored as OUT);
+// q[2J+1 .. GLOBAL_EP) = 0.
+template <class OUT>
+__device__ __forceinline__ void global_basis(float u, int J, float Q, const TrigTables &T, OUT *q) {
     float s1, c1;
     sincos32(u, T, s1, c1);
     const float ss = s1 * s1;
@@ -42,36 +43,37 @@ __device__ __forceinline__ void global_basis(float u, int J, float Q, const Trig
     const float sc = s1 * c1;
     const float S2 = 2.0f * sc;
     float cj = c1, sj = s1;
-    q[0] = Q;
+    q[0] = OUT(Q);
     for (int j = 0; j < J; j++) {
-        q[2 * j + 1] = rintf(cj * Q);
-        q[2 * j + 2] = rintf(sj * Q);
+        q[2 * j + 1] = OUT(rintf(cj * Q));
+        q[2 * j + 2] = OUT(rintf(sj * Q));
         const float a = cj * C2, b = sj * S2;
         const float g = sj * C2, h = cj * S2;
         cj = a - b;
         sj = g + h;
     }
-    for (int k = 2 * J + 1; k < GLOBAL_EP; k++) q[k] = 0.0f;
+    for (int k = 2 * J + 1; k < GLOBAL_EP; k++) q[k] = OUT(0);
 }
 
-// Map step.  Thread item (a, b, blk): entries (a, b, 8 blk .. 8 blk + 7) of
-// the statistics for p = 3 (first coordinate slowest); for p = 2 the entries
-// (b, 8 blk ..), for p = 1 (8 blk ..).  Grid: (item groups, point ranges of
-// `per` points each, per <= GLOBAL_EXACT_POINTS).  C: int64 as uint64, added to.
+// Map step.  Thread item (a, b): the row of entries (a, b, 0 .. 2J) of the
+// statistics for p = 3 (first coordinate slowest); for p = 2 the row (b, .),
+// for p = 1 the only row.  The staged basis is fp64 in LDS: the row's values
+// are the same for every lane (broadcast reads), a and b differ.  Grid: (row
+// groups, point ranges of `per` points each, per <= GLOBAL_EXACT_POINTS).
+// C: int64 as uint64, added to.
 template <int P>
 __global__ __launch_bounds__(NT) void k_gmom(const float *pts, uint64_t n, uint64_t ld, uint32_t J,
                                              uint64_t per, TrigTables T, unsigned long long *C) {
-    __shared__ __attribute__((aligned(16))) float q[P][GLOBAL_CHUNK][GLOBAL_EP];
+    __shared__ __attribute__((aligned(16))) double q[P][GLOBAL_CHUNK][GLOBAL_EP];
     const uint32_t E = 2 * J + 1;
     const float Q = global_quantum(P);
-    const uint32_t items = (P >= 3 ? E : 1u) * (P >= 2 ? E : 1u) * 4u;
+    const uint32_t rows = (P >= 3 ? E : 1u) * (P >= 2 ? E : 1u);
     const uint32_t item = blockIdx.x * NT + threadIdx.x;
-    const bool active = item < items;
-    const uint32_t blk = item % 4u, ab = item / 4u;
-    const uint32_t b = P >= 2 ? ab % E : 0u, a = P >= 3 ? ab / E : 0u;
-    double acc[8];
+    const bool active = item < rows;
+    const uint32_t b = P >= 2 ? item % E : 0u, a = P >= 3 ? item / E : 0u;
+    double acc[GLOBAL_EP];
 #pragma unroll
-    for (int k = 0; k < 8; k++) acc[k] = 0.0;
+    for (int k = 0; k < GLOBAL_EP; k++) acc[k] = 0.0;
     const uint64_t p0 = uint64_t(blockIdx.y) * per;
     const uint64_t p1 = p0 + per < n ? p0 + per : n;
     for (uint64_t c0 = p0; c0 < p1; c0 += GLOBAL_CHUNK) {
@@ -84,30 +86,25 @@ __global__ __launch_bounds__(NT) void k_gmom(const float *pts, uint64_t n, uint6
         __syncthreads();
         if (active) {
             for (uint32_t i = 0; i < m; i++) {
-                const double qa = P >= 3 ? double(q[0][i][a]) : 1.0;
-                const double qb = P >= 2 ? double(q[P - 2][i][b]) : 1.0;
+                const double qa = P >= 3 ? q[0][i][a] : 1.0;
+                const double qb = P >= 2 ? q[P - 2][i][b] : 1.0;
                 const double qab = qa * qb;
-                const float4 x0 = *reinterpret_cast<const float4 *>(&q[P - 1][i][8 * blk]);
-                const float4 x1 = *reinterpret_cast<const float4 *>(&q[P - 1][i][8 * blk + 4]);
-                acc[0] = __fma_rn(qab, double(x0.x), acc[0]);
-                acc[1] = __fma_rn(qab, double(x0.y), acc[1]);
-                acc[2] = __fma_rn(qab, double(x0.z), acc[2]);
-                acc[3] = __fma_rn(qab, double(x0.w), acc[3]);
-                acc[4] = __fma_rn(qab, double(x1.x), acc[4]);
-                acc[5] = __fma_rn(qab, double(x1.y), acc[5]);
-                acc[6] = __fma_rn(qab, double(x1.z), acc[6]);
-                acc[7] = __fma_rn(qab, double(x1.w), acc[7]);
+                const double2 *row = reinterpret_cast<const double2 *>(q[P - 1][i]);
+#pragma unroll
+                for (int k = 0; k < GLOBAL_EP / 2; k++) {
+                    const double2 x = row[k];
+                    acc[2 * k] = __fma_rn(qab, x.x, acc[2 * k]);
+                    acc[2 * k + 1] = __fma_rn(qab, x.y, acc[2 * k + 1]);
+                }
             }
         }
     }
     if (!active) return;
+    const uint64_t base = P == 3 ? (uint64_t(a) * E + b) * E : (P == 2 ? uint64_t(b) * E : 0u);
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
-        const uint32_t c = 8 * blk + uint32_t(k);
-        if (c >= E || acc[k] == 0.0) continue;
-        const uint64_t e = P == 3 ? (uint64_t(a) * E + b) * E + c : (P == 2 ? uint64_t(b) * E + c : c);
-        atomicAdd(&C[e], (unsigned long long)(long long)acc[k]);
-    }
+    for (int k = 0; k < GLOBAL_EP; k++)
+        if (uint32_t(k) < E && acc[k] != 0.0)
+            atomicAdd(&C[base + uint32_t(k)], (unsigned long long)(long long)acc[k]);
 }
 
 // sin((2j-1)x), cos((2j-1)x), j = 1..J (fp64, own series, recurrence).

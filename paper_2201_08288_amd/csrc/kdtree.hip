@@ -3134,8 +3134,8 @@ kd_status kd_global_moments(const float *pts, uint64_t n, uint32_t p, uint64_t l
         J > uint32_t(GLOBAL_JMAX))
         return KD_EINVAL;
     const uint32_t E = 2 * J + 1;
-    const uint32_t items = (p >= 3 ? E : 1u) * (p >= 2 ? E : 1u) * 4u;
-    const uint32_t groups = (items + NT - 1) / NT;
+    const uint32_t rows = (p >= 3 ? E : 1u) * (p >= 2 ? E : 1u);
+    const uint32_t groups = (rows + NT - 1) / NT;
     // point ranges: every workgroup's sums stay exact, and about 2048 workgroups
     uint64_t splits = std::min<uint64_t>((2048 + groups - 1) / groups, (n + GLOBAL_CHUNK - 1) / GLOBAL_CHUNK);
     splits = std::max<uint64_t>(splits, (n + GLOBAL_EXACT_POINTS - 1) / GLOBAL_EXACT_POINTS);
