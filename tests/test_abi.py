@@ -87,3 +87,34 @@ def test_tuning_round_trip(lib):
     assert kdtree.get_tuning() == before
     L = kdtree.lib()
     assert L.kd_set_tuning(None) == kdtree.KD_EINVAL and L.kd_get_tuning(None) == kdtree.KD_EINVAL
+
+
+def test_query_and_global_argument_checks(lib):
+    """Parameter errors are reported on the host, before any device work."""
+    from paper_2201_08288_amd import kdtree
+    L = kdtree.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the checks come first
+    t = kdtree.TreeStruct()
+    for f in kdtree.KDTree.FIELDS:
+        setattr(t, f, fake.value)
+    t.hdr = fake.value
+    t.points_out = fake.value
+    t.node_capacity = 16
+    E = kdtree.KD_EINVAL
+    for k in (0, 65):
+        assert L.kd_query_knn(ctypes.byref(t), 10, fake, 4, 2, 4, k, fake, fake, None) == E
+    assert L.kd_query_knn(ctypes.byref(t), 10, fake, 4, 0, 4, 1, fake, fake, None) == E  # d = 0
+    assert L.kd_query_knn(ctypes.byref(t), 10, fake, 4, 2, 3, 1, fake, fake, None) == E  # ldq < nq
+    t.points_out = None
+    assert L.kd_query_knn(ctypes.byref(t), 10, fake, 4, 2, 4, 1, fake, fake, None) == E
+    assert L.kd_query_box(ctypes.byref(t), 10, fake, fake, 4, 2, 4, fake, None, None, None) == E
+    t.points_out = fake.value
+    assert L.kd_query_box(ctypes.byref(t), 10, fake, fake, 4, 2, 4, fake, None, fake, None) == E
+    for p, J in ((0, 15), (4, 15), (3, 0), (3, 16)):
+        assert L.kd_global_moments(fake, 100, p, 100, J, fake, None) == E, (p, J)
+    assert L.kd_global_moments(fake, 0, 3, 100, 15, fake, None) == E
+    assert L.kd_global_moments(fake, 100, 3, 99, 15, fake, None) == E
+    for depth in (0, 13):
+        assert L.kd_global_solve(fake, 3, 15, depth, fake, None) == E
+        assert L.kd_global_counts(fake, 100, 3, 100, fake, depth, fake, None) == E
+    assert L.kd_global_solve(None, 3, 15, 6, fake, None) == E

@@ -15,6 +15,8 @@ def unit_points(n, p, seed, kind="uniform"):
         return rng.random((p, n)).astype(np.float32).clip(2.0 ** -24, 1 - 2.0 ** -24)
     if kind == "ties":
         return (rng.integers(1, 64, size=(p, n)) / 64.0).astype(np.float32)
+    if kind == "outside":  # not in (0,1): no clamping on either side, same results
+        return (rng.random((p, n)) * 2.0 - 0.5).astype(np.float32)
     from scipy.stats import norm
 
     from paper_2201_08288_amd import synth
@@ -24,7 +26,8 @@ def unit_points(n, p, seed, kind="uniform"):
 
 @pytest.mark.parametrize("p", [1, 2, 3])
 @pytest.mark.parametrize("n,J,depth,kind", [(1, 15, 3, "uniform"), (1000, 3, 5, "uniform"),
-                                            (70001, 15, 6, "normal"), (20000, 7, 8, "ties")])
+                                            (70001, 15, 6, "normal"), (20000, 7, 8, "ties"),
+                                            (5000, 15, 4, "outside")])
 def test_global_matches_oracle(p, n, J, depth, kind):
     import torch
 
