@@ -98,7 +98,7 @@ struct TreeDesc {
     float *node_split_f;
     uint32_t *node_leaf, *leaf_node, *leaf_offsets;
     kd_header *hdr;
-    uint32_t *leaf_cnt, *leaf_first;
+    uint64_t pbase;       // first bit of the tree's positions in the build's leaf-start bitmap
     uint64_t cap;
     uint32_t n, d;
 };

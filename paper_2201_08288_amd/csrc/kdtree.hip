@@ -71,6 +71,10 @@ struct Ctx {
     // SUBSET: subsets of more than SMALL_MAX points of the level's large cells
     uint32_t *seg_count, *seg_job, *seg_prefix, *seg_rank, *seg_hist;
     LevelInfo *info;  // totals of every level (MAX_LEVELS + 1)
+    // leaf numbering: a bit per position of every tree at each leaf's first
+    // position, and exclusive prefix counts of set bits per word (within a
+    // scan block) and per scan block
+    uint32_t *leafbits, *leafpre, *leafblk;
     // records of cells resolved ahead of their level by the subtree kernel
     uint32_t *cell_rec[2];  // per cell of the level list: its record link (REC_*), 0: none
     SubRec *subrec;
@@ -2364,33 +2368,62 @@ __global__ __launch_bounds__(NT) void k_emit_one(Ctx c, uint32_t level) {
 
 // ------------------------------------------------------------ kernels: leaves
 
-// Leaves in position order: subtree leaf counts bottom-up, first leaf index
-// top-down, one depth per launch over each tree's node-id range.
-__global__ void k_leaf_count(Ctx c, uint32_t depth) {
+// Leaves in position order.  Leaves tile a tree's positions and each holds
+// at least one point, so a leaf's index is the number of leaf starts before
+// its first position: one bit per position, popcount prefix sums.
+constexpr uint32_t LEAF_WPB = NT * 16;  // bitmap words per scan block
+
+__device__ __forceinline__ uint32_t leaf_rank(const Ctx &c, uint64_t pos) {
+    const uint64_t w = pos >> 5;
+    const uint32_t below = c.leafbits[w] & ((1u << (pos & 31)) - 1u);
+    return c.leafblk[w / LEAF_WPB] + c.leafpre[w] + uint32_t(__popc(below));
+}
+
+__global__ void k_leaf_mark(Ctx c) {
     const uint32_t t = blockIdx.y;
     const TreeState &S = c.ts[t];
-    if (S.status != KD_OK || depth > S.depth) return;
+    if (S.status != KD_OK) return;
     const KD_CONST TreeDesc &T = cref(&c.trees[t]);
-    const uint32_t a = S.depth_first[depth], b = S.depth_first[depth + 1];
-    for (uint32_t k = a + blockIdx.x * NT + threadIdx.x; k < b; k += gridDim.x * NT) {
-        const int32_t ch = T.node_child[k];
-        T.leaf_cnt[k] = ch < 0 ? 1u : T.leaf_cnt[ch] + T.leaf_cnt[ch + 1];
+    for (uint32_t k = blockIdx.x * NT + threadIdx.x; k < S.num_nodes; k += gridDim.x * NT) {
+        if (T.node_child[k] < 0) {
+            const uint64_t pos = T.pbase + T.node_begin[k];
+            atomicOr(&c.leafbits[pos >> 5], 1u << (pos & 31));
+        }
     }
 }
 
-__global__ void k_leaf_first(Ctx c, uint32_t depth) {
-    const uint32_t t = blockIdx.y;
-    const TreeState &S = c.ts[t];
-    if (S.status != KD_OK || depth > S.depth) return;
-    const KD_CONST TreeDesc &T = cref(&c.trees[t]);
-    const uint32_t a = S.depth_first[depth], b = S.depth_first[depth + 1];
-    for (uint32_t k = a + blockIdx.x * NT + threadIdx.x; k < b; k += gridDim.x * NT) {
-        const int32_t ch = T.node_child[k];
-        if (ch >= 0) {
-            const uint32_t f = k == 0 ? 0u : T.leaf_first[k];
-            T.leaf_first[ch] = f;
-            T.leaf_first[ch + 1] = f + T.leaf_cnt[ch];
-        }
+// Per scan block of LEAF_WPB words: each word's exclusive prefix of set bits
+// within the block, and the block's total.
+__global__ __launch_bounds__(NT) void k_leaf_scan1(Ctx c, uint64_t words) {
+    __shared__ uint32_t sh[NW + 1];
+    const uint64_t w0 = uint64_t(blockIdx.x) * LEAF_WPB + uint64_t(threadIdx.x) * 16;
+    uint32_t cnt[16], local = 0;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        cnt[j] = w0 + j < words ? uint32_t(__popc(c.leafbits[w0 + j])) : 0u;
+        local += cnt[j];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(local, sh, &tot);
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        if (w0 + j < words) c.leafpre[w0 + j] = run;
+        run += cnt[j];
+    }
+    if (threadIdx.x == 0) c.leafblk[blockIdx.x] = tot;
+}
+
+// Exclusive prefix of the block totals (one workgroup).
+__global__ __launch_bounds__(NT) void k_leaf_scan2(Ctx c, uint32_t nblocks) {
+    __shared__ uint32_t sh[NW + 1];
+    uint32_t base = 0;
+    for (uint32_t b0 = 0; b0 < nblocks; b0 += NT) {
+        const uint32_t b = b0 + threadIdx.x;
+        const uint32_t v = b < nblocks ? c.leafblk[b] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, sh, &tot);
+        if (b < nblocks) c.leafblk[b] = base + ex;
+        base += tot;
     }
 }
 
@@ -2400,10 +2433,11 @@ __global__ __launch_bounds__(NT) void k_leaf_write(Ctx c) {
     const TreeState &S = c.ts[t];
     if (S.status != KD_OK) return;
     const KD_CONST TreeDesc &T = cref(&c.trees[t]);
+    const uint32_t first = leaf_rank(c, T.pbase);
     unsigned long long over = 0;
     for (uint32_t k = blockIdx.x * NT + threadIdx.x; k < S.num_nodes; k += gridDim.x * NT) {
         if (T.node_child[k] < 0) {
-            const uint32_t f = k == 0 ? 0u : T.leaf_first[k];
+            const uint32_t f = leaf_rank(c, T.pbase + T.node_begin[k]) - first;
             T.leaf_node[f] = k;
             T.leaf_offsets[f] = T.node_begin[k];
             T.node_leaf[k] = f;
@@ -2419,7 +2453,8 @@ __global__ void k_header(Ctx c) {
          t += gridDim.x * blockDim.x) {
         const TreeState &S = c.ts[t];
         const KD_CONST TreeDesc &T = cref(&c.trees[t]);
-        const uint32_t leaves = S.status == KD_OK ? T.leaf_cnt[0] : 0u;
+        const uint32_t leaves =
+            S.status == KD_OK ? leaf_rank(c, T.pbase + T.n) - leaf_rank(c, T.pbase) : 0u;
         if (S.status == KD_OK) T.leaf_offsets[leaves] = T.n;
         kd_header h{};
         h.num_nodes = S.num_nodes;
@@ -2486,15 +2521,15 @@ struct Bump {
 };
 
 struct TreeLayout {
-    uint64_t cols[2], perm[2], stats[2], leaf_cnt, leaf_first;
+    uint64_t cols[2], perm[2], stats[2];
     uint64_t max_cells;
 };
 
 struct Layout {
     uint64_t cell_rec[2], subrec, rec_count, rec_cap;
     uint64_t trees, ts, cells[2], res, big_list, tile_lt, tile_le, tile_off, tile_cell, tiles, hist, mm, mom,
-        bounds, med, pre, scan, buckets, segs, info, total;
-    uint64_t max_cells, max_tiles, max_big, scan_blocks, all_points;
+        bounds, med, pre, scan, buckets, segs, info, leafbits, leafpre, leafblk, total;
+    uint64_t max_cells, max_tiles, max_big, scan_blocks, all_points, leaf_words, leaf_blocks;
     std::vector<TreeLayout> per_tree;
 };
 
@@ -2541,6 +2576,12 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     // at most one large subset per SMALL_MAX + 1 points
     L.segs = B.take(subset ? (all_points / (SMALL_MAX + 1) + 2) * 4 * (3 + NBINS) + 256 : 0);
     L.info = B.take(sizeof(LevelInfo) * (MAX_LEVELS + 1));
+    // one bit per position of every tree, plus the position after the last
+    L.leaf_words = all_points / 32 + 1;
+    L.leaf_blocks = (L.leaf_words + LEAF_WPB - 1) / LEAF_WPB;
+    L.leafbits = B.take(L.leaf_words * 4);
+    L.leafpre = B.take(L.leaf_words * 4);
+    L.leafblk = B.take(L.leaf_blocks * 4);
     L.per_tree.resize(T);
     for (uint32_t t = 0; t < T; t++) {
         TreeLayout &tl = L.per_tree[t];
@@ -2551,8 +2592,6 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
             tl.stats[b] = B.take(p->key_rule == KD_KEY_MAXVAR
                                      ? 2 * tl.max_cells * uint64_t(d[t]) * 3 * 8
                                      : 0);
-        tl.leaf_cnt = B.take(cap[t] * 4);
-        tl.leaf_first = B.take(cap[t] * 4);
     }
     L.total = B.o;
     return L;
@@ -2738,6 +2777,7 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     Prof P(prof, st);
 
     std::vector<TreeDesc> desc(ntrees);
+    uint64_t pbase = 0;
     for (uint32_t t = 0; t < ntrees; t++) {
         const TreeLayout &tl = L.per_tree[t];
         const kd_tree *o = ht[t].out;
@@ -2761,10 +2801,10 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         D.leaf_node = o->leaf_node;
         D.leaf_offsets = o->leaf_offsets;
         D.hdr = o->hdr;
-        D.leaf_cnt = reinterpret_cast<uint32_t *>(ws + tl.leaf_cnt);
-        D.leaf_first = reinterpret_cast<uint32_t *>(ws + tl.leaf_first);
         D.cap = cap[t];
         D.n = uint32_t(n[t]);
+        D.pbase = pbase;
+        pbase += n[t];
         D.d = d[t];
     }
     if (hipMemcpyAsync(ws + L.trees, desc.data(), sizeof(TreeDesc) * ntrees,
@@ -2801,6 +2841,9 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         c.seg_hist = c.seg_rank + max_seg;
     }
     c.info = reinterpret_cast<LevelInfo *>(ws + L.info);
+    c.leafbits = reinterpret_cast<uint32_t *>(ws + L.leafbits);
+    c.leafpre = reinterpret_cast<uint32_t *>(ws + L.leafpre);
+    c.leafblk = reinterpret_cast<uint32_t *>(ws + L.leafblk);
     for (int b = 0; b < 2; b++) c.cell_rec[b] = reinterpret_cast<uint32_t *>(ws + L.cell_rec[b]);
     c.subrec = reinterpret_cast<SubRec *>(ws + L.subrec);
     c.rec_count = reinterpret_cast<uint32_t *>(ws + L.rec_count);
@@ -2830,6 +2873,8 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                            dim3(NT), 0, st, c.hist, L.max_big * BIG_BINS, 0u);
         hipLaunchKernelGGL(k_init, per_tree_nodes, dim3(NT), 0, st, c);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(NT), 0, st, c.rec_count, 1ull, 0u);
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.leaf_words / NT + 1, 4096)), dim3(NT), 0,
+                           st, c.leafbits, L.leaf_words, 0u);
         if (p->split_rule == KD_SPLIT_SUBSET) {
             const uint64_t words = (L.all_points / (SMALL_MAX + 1) + 2) * (3 + NBINS) + 64;
             hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words / NT + 1, 4096)), dim3(NT), 0, st,
@@ -3011,10 +3056,10 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         if (hipGetLastError() != hipSuccess || !read_back(level + 1)) return fail();
     }
     P.run(KD_PROF_OTHER, 0, 0, [&] {
-        for (int l = int(levels_run); l >= 0; l--)
-            hipLaunchKernelGGL(k_leaf_count, per_tree_nodes, dim3(NT), 0, st, c, uint32_t(l));
-        for (uint32_t l = 0; l <= levels_run; l++)
-            hipLaunchKernelGGL(k_leaf_first, per_tree_nodes, dim3(NT), 0, st, c, l);
+        hipLaunchKernelGGL(k_leaf_mark, per_tree_nodes, dim3(NT), 0, st, c);
+        hipLaunchKernelGGL(k_leaf_scan1, dim3(uint32_t(L.leaf_blocks)), dim3(NT), 0, st, c,
+                           L.leaf_words);
+        hipLaunchKernelGGL(k_leaf_scan2, dim3(1), dim3(NT), 0, st, c, uint32_t(L.leaf_blocks));
         hipLaunchKernelGGL(k_leaf_write, per_tree_nodes, dim3(NT), 0, st, c);
         hipLaunchKernelGGL(k_header, dim3(grid_for(ntrees / NT + 1, 1024)), dim3(NT), 0, st, c);
     });
@@ -3278,7 +3323,7 @@ kd_status kd_autotune(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return KD_EDEVICE;
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return KD_EDEVICE;
     }
     auto timed = [&](const kd_tuning &t, float &ms, bool &same) -> kd_status {
@@ -3320,8 +3365,8 @@ kd_status kd_autotune(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (s == KD_OK && !same) s = KD_EDEVICE;
     if (s != KD_OK) return s;
     kd_set_tuning(&cur);
