@@ -246,8 +246,9 @@ kd_status kd_global_counts(const float *pts, uint64_t n, uint32_t p, uint64_t ld
 /* Launch shapes of the level kernels.  They change only how work is spread
  * over workgroups, never the result: every setting builds the same tree bit
  * for bit.  0 in a field means the default (2048 workgroups per digit pass,
- * one workgroup per tile of 4096 points for count and scatter, 1024
- * workgroups taking buckets of small cells in turn).                       */
+ * one workgroup per tile of 4096 points for count and scatter, one
+ * workgroup per bucket of small cells, a bucket holding about 4096
+ * points).  A smaller grid takes tiles or buckets in turn.                 */
 typedef struct kd_tuning {
     uint32_t hist_blocks;      /* workgroups of a large-cell digit pass            */
     uint32_t scatter_blocks;   /* workgroups of the large-cell count and scatter   */

@@ -2238,15 +2238,17 @@ __global__ __launch_bounds__(NT) void k_emit_prefix(Ctx c, uint32_t level) {
 
 // Per tree: node-id base of the new children, next level's cell range and
 // the tree's counters.
-__device__ __forceinline__ void emit_tree(const Ctx &c, uint32_t level, uint32_t t) {
+// pre: the prefix rows (row ci at pre + ci * stride; row ncells the totals).
+__device__ __forceinline__ void emit_tree(const Ctx &c, uint32_t level, uint32_t t,
+                                          const uint32_t *pre, uint32_t stride) {
     const uint32_t cur = level & 1, nxt = cur ^ 1;
     {
         TreeState &S = c.ts[t];
         const uint32_t f = S.first[cur], n = S.count[cur];
         S.nodes_base = S.num_nodes;
         if (n > 0) {
-            const uint32_t *pf = c.pre + uint64_t(f) * EMIT_STRIDE;
-            const uint32_t *pe = c.pre + uint64_t(f + n) * EMIT_STRIDE;
+            const uint32_t *pf = pre + uint64_t(f) * stride;
+            const uint32_t *pe = pre + uint64_t(f + n) * stride;
             const uint32_t splits = pe[0] - pf[0];
             S.split_base = pf[0];
             if (uint64_t(S.num_nodes) + 2ull * splits > c.trees[t].cap) S.status = KD_ECAPACITY;
@@ -2265,17 +2267,18 @@ __device__ __forceinline__ void emit_tree(const Ctx &c, uint32_t level, uint32_t
 __global__ void k_emit_trees(Ctx c, uint32_t level) {
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < c.ntrees;
          t += gridDim.x * blockDim.x)
-        emit_tree(c, level, t);
+        emit_tree(c, level, t, c.pre, EMIT_STRIDE);
 }
 
-__device__ __forceinline__ void emit_cell(const Ctx &c, uint32_t level, uint32_t ci) {
+// pre: the cell's prefix row.
+__device__ __forceinline__ void emit_cell(const Ctx &c, uint32_t level, uint32_t ci,
+                                          const uint32_t *pre) {
     const uint32_t cur = level & 1, nxt = cur ^ 1;
     const CellRes r = c.res[ci];
     if (!(r.flags & RES_SPLIT)) return;
     const Cell cl = c.cells[cur][ci];
     const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
     const TreeState &S = c.ts[cl.tree];
-    const uint32_t *pre = c.pre + uint64_t(ci) * EMIT_STRIDE;
     const uint32_t left = S.nodes_base + 2 * (pre[0] - S.split_base);
     const uint32_t li = ci - S.first[cur];
     const uint32_t mid = cl.begin + r.nl;
@@ -2317,36 +2320,59 @@ __device__ __forceinline__ void emit_cell(const Ctx &c, uint32_t level, uint32_t
 __global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level) {
     const uint32_t ncells = c.info[level].num_cells;
     const uint32_t ci = blockIdx.x * NT + threadIdx.x;
-    if (ci < ncells) emit_cell(c, level, ci);
+    if (ci < ncells) emit_cell(c, level, ci, c.pre + uint64_t(ci) * EMIT_STRIDE);
 }
 
-// The whole emit step in one workgroup, for levels of at most EMIT_ONE_MAX
-// cells: counts and their prefix (each thread takes consecutive cells), the
-// totals, the per-tree update, then the node records and next cells.
-constexpr uint32_t EMIT_ONE_MAX = 1024;
-__global__ __launch_bounds__(NT) void k_emit_one(Ctx c, uint32_t level) {
-    __shared__ uint32_t sh[NW + 1];
+// The whole emit step in one workgroup of EMIT_NT threads, for levels of at
+// most EMIT_ONE_MAX cells (each thread takes EMIT_PER consecutive cells): the
+// counts and their prefix rows in LDS, the totals, the per-tree update, then
+// the node records and next cells.
+constexpr int EMIT_NT = 1024;
+constexpr int EMIT_NW = EMIT_NT / WAVE;
+constexpr uint32_t EMIT_ONE_MAX = 2048;
+constexpr uint32_t EMIT_PER = EMIT_ONE_MAX / EMIT_NT;
+__global__ __launch_bounds__(EMIT_NT) void k_emit_one(Ctx c, uint32_t level) {
+    __shared__ uint32_t spre[(EMIT_ONE_MAX + 1) * EMIT_COUNTERS];
+    __shared__ uint32_t swave[EMIT_NW][EMIT_COUNTERS];
     const uint32_t ncells = c.info[level].num_cells;
-    constexpr uint32_t PER = EMIT_ONE_MAX / NT;
-    const uint32_t c0 = threadIdx.x * PER;
-    uint32_t cnt[PER][EMIT_COUNTERS];
+    const uint32_t c0 = threadIdx.x * EMIT_PER;
+    const int w = threadIdx.x / WAVE;
+    uint32_t cnt[EMIT_PER][EMIT_COUNTERS];
 #pragma unroll
-    for (uint32_t j = 0; j < PER; j++) emit_counts(c, level, c0 + j, ncells, cnt[j]);
-    uint32_t tot[EMIT_COUNTERS];
+    for (uint32_t j = 0; j < EMIT_PER; j++) emit_counts(c, level, c0 + j, ncells, cnt[j]);
+    uint32_t local[EMIT_COUNTERS], incl[EMIT_COUNTERS];
+#pragma unroll
     for (int k = 0; k < EMIT_COUNTERS; k++) {
-        uint32_t local = 0;
+        local[k] = 0;
 #pragma unroll
-        for (uint32_t j = 0; j < PER; j++) local += cnt[j][k];
-        uint32_t run = block_excl_scan(local, sh, &tot[k]);
+        for (uint32_t j = 0; j < EMIT_PER; j++) local[k] += cnt[j][k];
+        incl[k] = wave_incl_scan(local[k]);
+        if (lane() == WAVE - 1) swave[w][k] = incl[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < uint32_t(EMIT_COUNTERS)) {
+        const int k = threadIdx.x;
+        uint32_t run = 0;
+        for (int v = 0; v < EMIT_NW; v++) {
+            const uint32_t t = swave[v][k];
+            swave[v][k] = run;
+            run += t;
+        }
+        spre[ncells * EMIT_COUNTERS + k] = run;
+    }
+    __syncthreads();
 #pragma unroll
-        for (uint32_t j = 0; j < PER; j++) {
-            if (c0 + j < ncells) c.pre[uint64_t(c0 + j) * EMIT_STRIDE + k] = run;
+    for (int k = 0; k < EMIT_COUNTERS; k++) {
+        uint32_t run = swave[w][k] + incl[k] - local[k];
+#pragma unroll
+        for (uint32_t j = 0; j < EMIT_PER; j++) {
+            if (c0 + j < ncells) spre[(c0 + j) * EMIT_COUNTERS + k] = run;
             run += cnt[j][k];
         }
     }
-    if (threadIdx.x < EMIT_COUNTERS)
-        c.pre[uint64_t(ncells) * EMIT_STRIDE + threadIdx.x] = tot[threadIdx.x];
+    __syncthreads();
     if (threadIdx.x == 0) {
+        const uint32_t *tot = spre + ncells * EMIT_COUNTERS;
         LevelInfo in{};
         in.num_cells = tot[1];
         in.num_tiles = tot[2];
@@ -2356,14 +2382,13 @@ __global__ __launch_bounds__(NT) void k_emit_one(Ctx c, uint32_t level) {
         in.resolved = tot[8];
         c.info[level + 1] = in;
     }
-    __threadfence_block();
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < c.ntrees; t += NT) emit_tree(c, level, t);
+    for (uint32_t t = threadIdx.x; t < c.ntrees; t += EMIT_NT)
+        emit_tree(c, level, t, spre, EMIT_COUNTERS);
     __threadfence_block();
     __syncthreads();
 #pragma unroll
-    for (uint32_t j = 0; j < PER; j++)
-        if (c0 + j < ncells) emit_cell(c, level, c0 + j);
+    for (uint32_t j = 0; j < EMIT_PER; j++)
+        if (c0 + j < ncells) emit_cell(c, level, c0 + j, spre + (c0 + j) * EMIT_COUNTERS);
 }
 
 // ------------------------------------------------------------ kernels: leaves
@@ -3043,7 +3068,7 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         const uint32_t nb = uint32_t((nc + NT - 1) / NT);
         P.run(KD_PROF_EMIT, 0, 0, [&] {
             if (nc <= EMIT_ONE_MAX) {
-                hipLaunchKernelGGL(k_emit_one, dim3(1), dim3(NT), 0, st, c, level);
+                hipLaunchKernelGGL(k_emit_one, dim3(1), dim3(EMIT_NT), 0, st, c, level);
                 return;
             }
             hipLaunchKernelGGL(k_emit_sum, dim3(nb), dim3(NT), 0, st, c, level);
