@@ -462,48 +462,54 @@ __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t
 }
 
 // EXACT, large cells: pick the digit that holds the target rank (one wave
-// per cell, 32 bins per lane).  After the last pass the candidate is the
-// lower median and lt / le are exact.
+// per cell).  The histogram is read (and zeroed for the next pass) in rows of
+// 256 bins, lane l holding bins 4l .. 4l+3 of each row, so that every load and
+// store of the wave covers 1 KB; the rank is found row by row.  After the
+// last pass the candidate is the lower median and lt / le are exact.
 __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t pass) {
-    constexpr int PER = BIG_BINS / WAVE;
+    constexpr int ROWS = BIG_BINS / (4 * WAVE);
+    static_assert(ROWS * 4 * WAVE == BIG_BINS, "whole rows of bins");
     const int shift = big_shift(pass);
     const uint32_t nbig = c.info[level].num_big;
     const int l = lane();
     for (uint32_t b = blockIdx.x * NW + wave(); b < nbig; b += gridDim.x * NW) {
         const uint32_t ci = c.big_list[b];
         CellRes r = c.res[ci];
-        uint4 *gh = reinterpret_cast<uint4 *>(c.hist + uint64_t(b) * BIG_BINS) + l * (PER / 4);
-        static_assert(PER % 4 == 0, "whole uint4 groups of bins per lane");
-        uint32_t hv[PER], local = 0;
+        uint4 *gh = reinterpret_cast<uint4 *>(c.hist + uint64_t(b) * BIG_BINS);
+        uint4 hv[ROWS];
 #pragma unroll
-        for (int q = 0; q < PER / 4; q++) {
-            const uint4 x = gh[q];
-            hv[4 * q] = x.x;
-            hv[4 * q + 1] = x.y;
-            hv[4 * q + 2] = x.z;
-            hv[4 * q + 3] = x.w;
-            gh[q] = make_uint4(0u, 0u, 0u, 0u);
-        }
+        for (int q = 0; q < ROWS; q++) hv[q] = gh[q * WAVE + l];
 #pragma unroll
-        for (int j = 0; j < PER; j++) local += hv[j];
-        const uint32_t ex = wave_incl_scan(local) - local;
-        const unsigned long long m = __ballot(ex <= r.rank && r.rank < ex + local);
-        const int src = __builtin_ctzll(m);  // exactly one lane holds the rank
-        uint32_t bin = 0, below = ex, cnt = 0;
-        bool found = false;
+        for (int q = 0; q < ROWS; q++) gh[q * WAVE + l] = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t base = 0, bin = 0, below = 0, cnt = 0;
 #pragma unroll
-        for (int j = 0; j < PER; j++) {
-            if (!found && r.rank < below + hv[j]) {
-                bin = uint32_t(l * PER + j);
-                cnt = hv[j];
-                found = true;
-            } else if (!found) {
-                below += hv[j];
+        for (int q = 0; q < ROWS; q++) {
+            const uint32_t v[4] = {hv[q].x, hv[q].y, hv[q].z, hv[q].w};
+            const uint32_t local = v[0] + v[1] + v[2] + v[3];
+            const uint32_t incl = wave_incl_scan(local);
+            const uint32_t tot = __shfl(incl, WAVE - 1, WAVE);
+            if (base <= r.rank && r.rank < base + tot) {  // uniform: the rank's row
+                const uint32_t ex = base + incl - local;
+                const unsigned long long m = __ballot(ex <= r.rank && r.rank < ex + local);
+                const int src = __builtin_ctzll(m);  // exactly one lane holds the rank
+                uint32_t lb = 0, lbelow = ex, lcnt = 0;
+                bool found = false;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (!found && r.rank < lbelow + v[j]) {
+                        lb = uint32_t(q * 4 * WAVE + 4 * l + j);
+                        lcnt = v[j];
+                        found = true;
+                    } else if (!found) {
+                        lbelow += v[j];
+                    }
+                }
+                bin = __shfl(lb, src, WAVE);
+                below = __shfl(lbelow, src, WAVE);
+                cnt = __shfl(lcnt, src, WAVE);
             }
+            base += tot;
         }
-        bin = __shfl(bin, src, WAVE);
-        below = __shfl(below, src, WAVE);
-        cnt = __shfl(cnt, src, WAVE);
         if (l == 0) {
             r.prefix |= bin << shift;
             r.rank -= below;
@@ -864,12 +870,13 @@ __global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level) {
                 le += u[j] <= r.cand;
             }
         }
-        uint32_t tlt, tle;
-        block_excl_scan(lt, sh, &tlt);
-        block_excl_scan(le, sh, &tle);
+        // one workgroup sum of both counts (each at most TILE < 2^16)
+        static_assert(TILE < (1 << 16), "tile counts fit 16 bits");
+        uint32_t both;
+        block_excl_scan(lt | (le << 16), sh, &both);
         if (threadIdx.x == 0) {
-            c.tile_lt[t] = tlt;
-            c.tile_le[t] = tle;
+            c.tile_lt[t] = both & 0xffffu;
+            c.tile_le[t] = both >> 16;
         }
     }
 }
