@@ -1772,9 +1772,9 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_FOURIER ? 2 : 3) voi
     __shared__ SubTable<SC, CH> Q[2];
     __shared__ uint32_t sh[2 * NW + 1], s3[4];
     // MAXVAR: chunk prefix sums (S1, hi, lo) at the first slot of every child
-    // and per-wave totals of the scan
-    __shared__ unsigned long long pat[MAXVAR ? CH : 1][3];
-    __shared__ unsigned long long wtot[MAXVAR ? NW : 1][3];
+    // and per-wave totals of the scan, double-buffered over the columns
+    __shared__ unsigned long long pat[2][MAXVAR ? CH : 1][3];
+    __shared__ unsigned long long wtot[2][MAXVAR ? NW : 1][3];
     static_assert(CH < int(SEG_LEAF), "child numbers fit a byte below SEG_LEAF");
     uint32_t(*const h)[NBINS] = lds.sel.h;
     unsigned long long *const sh64 = lds.sel.sh64;
@@ -2016,20 +2016,35 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_FOURIER ? 2 : 3) voi
                     const uint32_t mine = threadIdx.x;  // child whose coordinate this thread picks
                     __int128 best = -1;
                     uint32_t bd = 0;
+                    // the next column's values are loaded while this one is
+                    // summed; the records alternate between two buffers, so one
+                    // barrier per column separates their writes and reads
+                    uint32_t xn[PER_THREAD];
+                    {
+                        const KD_GLOBAL uint32_t *src = gp(T.cols[cur]);
+#pragma unroll
+                        for (int j = 0; j < PER_THREAD; j++) xn[j] = (amask >> j) & 1u ? src[pe[j]] : 0u;
+                    }
                     for (uint32_t col = 0; col < d; col++) {
-                        const KD_GLOBAL uint32_t *src = gp(T.cols[cur] + uint64_t(col) * n);
+                        const int pb = col & 1;
                         uint32_t xv[PER_THREAD];
 #pragma unroll
-                        for (int j = 0; j < PER_THREAD; j++) xv[j] = (amask >> j) & 1u ? src[pe[j]] : 0u;
+                        for (int j = 0; j < PER_THREAD; j++) xv[j] = xn[j];
+                        if (col + 1 < d) {
+                            const KD_GLOBAL uint32_t *src = gp(T.cols[cur] + uint64_t(col + 1) * n);
+#pragma unroll
+                            for (int j = 0; j < PER_THREAD; j++)
+                                xn[j] = (amask >> j) & 1u ? src[pe[j]] : 0u;
+                        }
                         VarSums a;
 #pragma unroll
                         for (int j = 0; j < PER_THREAD; j++) {
                             if ((rmask >> j) & 1u) {
                                 a.fold();
                                 const uint32_t r = (rid[j >> 2] >> (8 * (j & 3))) & 0xffu;
-                                pat[r][0] = a.s1;
-                                pat[r][1] = a.hi;
-                                pat[r][2] = a.lo;
+                                pat[pb][r][0] = a.s1;
+                                pat[pb][r][1] = a.hi;
+                                pat[pb][r][2] = a.lo;
                             }
                             if ((amask >> j) & 1u) a.add(maxvar_q32(xv[j], shift));
                             if (j == 7) a.fold();
@@ -2044,20 +2059,20 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_FOURIER ? 2 : 3) voi
                                 const int j = __builtin_ctz(mm);
                                 const uint32_t r = (rid[j >> 2] >> (8 * (j & 3))) & 0xffu;
 #pragma unroll
-                                for (int i = 0; i < 3; i++) pat[r][i] += ex[i];
+                                for (int i = 0; i < 3; i++) pat[pb][r][i] += ex[i];
                             }
                         }
                         if (l == WAVE - 1)
 #pragma unroll
-                            for (int i = 0; i < 3; i++) wtot[w][i] = x[i];
+                            for (int i = 0; i < 3; i++) wtot[pb][w][i] = x[i];
                         __syncthreads();
                         if (mine < nact) {
                             // chunk prefix at child r's first slot (r = nact: the end)
                             auto prefix = [&](uint32_t r, int i) {
-                                unsigned long long v = r < nact ? pat[r][i] : 0ull;
+                                unsigned long long v = r < nact ? pat[pb][r][i] : 0ull;
                                 const uint32_t wr =
                                     r < nact ? N.start[r] / (WAVE * PER_THREAD) : uint32_t(NW);
-                                for (uint32_t ww = 0; ww < wr; ww++) v += wtot[ww][i];
+                                for (uint32_t ww = 0; ww < wr; ww++) v += wtot[pb][ww][i];
                                 return v;
                             };
                             const long long s1 =
@@ -2073,7 +2088,6 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_FOURIER ? 2 : 3) voi
                                 bd = col;
                             }
                         }
-                        __syncthreads();
                     }
                     if (mine < nact) {
                         N.dim[mine] = bd;
