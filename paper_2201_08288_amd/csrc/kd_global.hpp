@@ -55,9 +55,9 @@ __device__ __forceinline__ void global_basis(float u, int J, float Q, const Trig
     for (int k = 2 * J + 1; k < GLOBAL_EP; k++) q[k] = OUT(0);
 }
 
-// Map step.  Thread item (a, b): the row of entries (a, b, 0 .. 2J) of the
-// statistics for p = 3 (first coordinate slowest); for p = 2 the row (b, .),
-// for p = 1 the only row.  The staged basis is fp64 in LDS: the row's values
+// Map step for p = 1 and 2 (p = 3 runs on the matrix cores, below).  Thread
+// item (a, b): the row of entries (a, b, 0 .. 2J) of the statistics for p = 3
+// (first coordinate slowest); for p = 2 the row (b, .), for p = 1 the only row.  The staged basis is fp64 in LDS: the row's values
 // are the same for every lane (broadcast reads), a and b differ.  Grid: (row
 // groups, point ranges of `per` points each, per <= GLOBAL_EXACT_POINTS).
 // C: int64 as uint64, added to.
@@ -105,6 +105,82 @@ __global__ __launch_bounds__(NT) void k_gmom(const float *pts, uint64_t n, uint6
     for (int k = 0; k < GLOBAL_EP; k++)
         if (uint32_t(k) < E && acc[k] != 0.0)
             atomicAdd(&C[base + uint32_t(k)], (unsigned long long)(long long)acc[k]);
+}
+
+// Map step for p = 3 on the matrix cores.  The statistics are the product
+// C[(a, b), c] = sum_i A[(a, b), i] B[i, c] of A = q_a(x_i) q_b(y_i) (E^2 rows,
+// E = 2J + 1) and B = q_c(z_i) (E columns, padded to 32).  One workgroup of
+// 16 waves holds every row: wave w owns rows 64w .. 64w + 63 (four 16-row
+// tiles) and both 16-column tiles; each fp64 16x16x4 MFMA adds four points.
+// Operand layout of that instruction: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16], and its accumulator register r holds row l / 16 + 4r,
+// column l % 16.  Every operand, product and partial sum is an integer below
+// 2^53 (at most GLOBAL_EXACT_POINTS points per workgroup), so the sums are
+// exact whatever order the matrix core adds them in.  Grid: (1, point ranges
+// of `per` points each).  C: int64 as uint64, added to.
+constexpr int GMM_NT = 1024;
+constexpr int GMM_STRIDE = GLOBAL_EP + 2;  // LDS row stride in doubles: a step's four points fall in different banks
+typedef double gmm_acc __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(GMM_NT) void k_gmom3_mfma(const float *pts, uint64_t n, uint64_t ld,
+                                                      uint32_t J, uint64_t per, TrigTables T,
+                                                      unsigned long long *C) {
+    __shared__ __attribute__((aligned(16))) double q[3][GLOBAL_CHUNK][GMM_STRIDE];
+    const uint32_t E = 2 * J + 1, rows = E * E;
+    const float Q = global_quantum(3);
+    const uint32_t w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    const uint32_t lr = l % 16, lk = l / 16;
+    uint32_t ra[4], rb[4];
+    bool rv[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const uint32_t R = 64 * w + 16 * t + lr;
+        rv[t] = R < rows;
+        ra[t] = rv[t] ? R / E : 0u;
+        rb[t] = rv[t] ? R % E : 0u;
+    }
+    gmm_acc acc[4][2];
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int u = 0; u < 2; u++) acc[t][u] = gmm_acc{0.0, 0.0, 0.0, 0.0};
+    const uint64_t p0 = uint64_t(blockIdx.y) * per;
+    const uint64_t p1 = p0 + per < n ? p0 + per : n;
+    for (uint64_t c0 = p0; c0 < p1; c0 += GLOBAL_CHUNK) {
+        const uint32_t m = uint32_t(p1 - c0 < GLOBAL_CHUNK ? p1 - c0 : GLOBAL_CHUNK);
+        __syncthreads();  // the previous chunk is consumed
+        for (uint32_t wk = threadIdx.x; wk < uint32_t(3 * GLOBAL_CHUNK); wk += GMM_NT) {
+            const uint32_t c = wk / GLOBAL_CHUNK, i = wk % GLOBAL_CHUNK;
+            double *row = q[c][i];
+            if (i < m) {
+                global_basis(pts[uint64_t(c) * ld + c0 + i], int(J), Q, T, row);
+            } else {  // past the range: a zero row adds nothing
+                for (int e = 0; e < GLOBAL_EP; e++) row[e] = 0.0;
+            }
+        }
+        __syncthreads();
+        for (uint32_t s = 0; s < uint32_t(GLOBAL_CHUNK / 4); s++) {
+            const uint32_t i = 4 * s + lk;
+            const double b0 = q[2][i][lr], b1 = q[2][i][16 + lr];
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const double a = rv[t] ? q[0][i][ra[t]] * q[1][i][rb[t]] : 0.0;
+                acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[t][0], 0, 0, 0);
+                acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[t][1], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int u = 0; u < 2; u++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const uint32_t R = 64 * w + 16 * t + lk + 4 * r, col = 16 * u + lr;
+                const double v = acc[t][u][r];
+                if (R < rows && col < E && v != 0.0)
+                    atomicAdd(&C[uint64_t(R) * E + col], (unsigned long long)(long long)v);
+            }
 }
 
 // sin((2j-1)x), cos((2j-1)x), j = 1..J (fp64, own series, recurrence).

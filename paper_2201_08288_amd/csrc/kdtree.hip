@@ -3236,9 +3236,19 @@ kd_status kd_global_moments(const float *pts, uint64_t n, uint32_t p, uint64_t l
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     unsigned long long *C = reinterpret_cast<unsigned long long *>(moments);
     const dim3 g(groups, uint32_t(splits));
-    if (p == 1) hipLaunchKernelGGL(k_gmom<1>, g, dim3(NT), 0, st, pts, n, ld, J, per, T, C);
-    else if (p == 2) hipLaunchKernelGGL(k_gmom<2>, g, dim3(NT), 0, st, pts, n, ld, J, per, T, C);
-    else hipLaunchKernelGGL(k_gmom<3>, g, dim3(NT), 0, st, pts, n, ld, J, per, T, C);
+    if (p == 1) {
+        hipLaunchKernelGGL(k_gmom<1>, g, dim3(NT), 0, st, pts, n, ld, J, per, T, C);
+    } else if (p == 2) {
+        hipLaunchKernelGGL(k_gmom<2>, g, dim3(NT), 0, st, pts, n, ld, J, per, T, C);
+    } else {
+        // one workgroup per compute unit, each holding every row of the statistics
+        uint64_t s3 = std::min<uint64_t>(256, (n + GLOBAL_CHUNK - 1) / GLOBAL_CHUNK);
+        s3 = std::max<uint64_t>(s3, (n + GLOBAL_EXACT_POINTS - 1) / GLOBAL_EXACT_POINTS);
+        const uint64_t per3 = (n + s3 - 1) / s3;
+        s3 = (n + per3 - 1) / per3;
+        hipLaunchKernelGGL(k_gmom3_mfma, dim3(1, uint32_t(s3)), dim3(GMM_NT), 0, st, pts, n, ld, J,
+                           per3, T, C);
+    }
     KD_LAUNCH_CHECK();
     return KD_OK;
 }
