@@ -219,13 +219,52 @@ __device__ __forceinline__ void global_g(double a, double b, int J, const TrigTa
     }
 }
 
+// One point's harmonics sin((2j-1)x), cos((2j-1)x), advanced one j at a
+// time by the same recurrence as global_harmonics (identical values).
+struct GlobalHarm {
+    double s, c, C2, S2;
+    __device__ __forceinline__ GlobalHarm(double x, const TrigTables &T) {
+        double s1, c1;
+        sincos64(x, T, s1, c1);
+        const double ss = s1 * s1;
+        C2 = 1.0 - 2.0 * ss;
+        const double sc = s1 * c1;
+        S2 = 2.0 * sc;
+        s = s1;
+        c = c1;
+    }
+    __device__ __forceinline__ void next() {
+        const double a = c * C2, b = s * S2;
+        const double g = s * C2, h = c * S2;
+        c = a - b;
+        s = g + h;
+    }
+};
+
+// F(m) = sum_j D_j (g_j(at, m) - g_j(m, bt)), the terms of g taken as in
+// global_g and summed in order j = 0 .. 2J, one harmonic at a time (no
+// arrays, so nothing is spilled).
 __device__ __forceinline__ double global_F(const double *D, int J, const TrigTables &T, double at,
                                            double bt, double m) {
-    double gl[2 * GLOBAL_JMAX + 1], gr[2 * GLOBAL_JMAX + 1];
-    global_g(at, m, J, T, gl);
-    global_g(m, bt, J, T, gr);
+    GlobalHarm ha(at, T), hm(m, T), hb(bt, T);
+    const bool la = at > 0.0, lb = m < 1.0;  // left interval (at, m)
+    const bool ra = m > 0.0, rb = bt < 1.0;  // right interval (m, bt)
+    const double gl0 = 1.0 - 0.5 * double(int(la) + int(lb));
+    const double gr0 = 1.0 - 0.5 * double(int(ra) + int(rb));
     double F = 0.0;
-    for (int j = 0; j <= 2 * J; j++) F = F + D[j] * (gl[j] - gr[j]);
+    F = F + D[0] * (gl0 - gr0);
+    for (int j = 1; j <= J; j++) {
+        const double k = 2.0 / (3.14159265358979323846 * double(2 * j - 1));
+        const double gl1 = k * ((lb ? hm.s : 0.0) - (la ? ha.s : 0.0));
+        const double gl2 = k * ((la ? ha.c : 0.0) - (lb ? hm.c : 0.0));
+        const double gr1 = k * ((rb ? hb.s : 0.0) - (ra ? hm.s : 0.0));
+        const double gr2 = k * ((ra ? hm.c : 0.0) - (rb ? hb.c : 0.0));
+        F = F + D[2 * j - 1] * (gl1 - gr1);
+        F = F + D[2 * j] * (gl2 - gr2);
+        ha.next();
+        hm.next();
+        hb.next();
+    }
     return F;
 }
 
@@ -299,21 +338,52 @@ __global__ __launch_bounds__(NT) void k_gsolve(const long long *C, uint32_t J, u
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (l != 0) return;
+    // Bisection of F on (at, bt): while F(a) < 0, halve at mid = a + (b - a)/2
+    // (a = mid where F(mid) < 0, else b = mid) until no double lies strictly
+    // between a and b or 200 halvings; the median is b.  The wave takes six
+    // halvings per round: lane j (1 .. 63) is node j of the six-level tree of
+    // halvings below (a, b) and finds its interval by the same halvings along
+    // its path, so every midpoint is the one the sequence would compute; the
+    // signs of F there then decide the path of the round.
     const double at = lo[t], bt = hi[t];
     double a = at, b = bt, m;
     if (global_F(sD[w], int(J), T, at, bt, a) >= 0.0) {
         m = a;
     } else {
-        for (int it = 0; it < 200; it++) {
-            const double mid = a + (b - a) * 0.5;
-            if (!(mid > a && mid < b)) break;
-            if (global_F(sD[w], int(J), T, at, bt, mid) < 0.0) a = mid;
-            else b = mid;
+        int it = 0;
+        bool done = false;
+        while (!done) {
+            double la = a, lb = b;
+            const int depth = l > 0 ? 31 - __builtin_clz(uint32_t(l)) : 0;
+            for (int r = depth - 1; r >= 0; r--) {
+                const double mid = la + (lb - la) * 0.5;
+                if ((l >> r) & 1) la = mid;
+                else lb = mid;
+            }
+            const double mj = la + (lb - la) * 0.5;
+            const bool valid = l > 0 && mj > la && mj < lb;
+            const bool neg = valid && global_F(sD[w], int(J), T, at, bt, mj) < 0.0;
+            const unsigned long long vm = __ballot(valid), nm = __ballot(neg);
+            int nd = 1;
+            for (int r = 0; r < 6; r++) {
+                if (it == 200 || !((vm >> nd) & 1ull)) {
+                    done = true;
+                    break;
+                }
+                const double mid = __shfl(mj, nd, WAVE);
+                if ((nm >> nd) & 1ull) {
+                    a = mid;
+                    nd = 2 * nd + 1;
+                } else {
+                    b = mid;
+                    nd = 2 * nd;
+                }
+                it++;
+            }
         }
         m = b;
     }
-    med[node] = m;
+    if (l == 0) med[node] = m;
 }
 
 // Points per leaf cell (descent: u_t <= m to the low side).  counts must
