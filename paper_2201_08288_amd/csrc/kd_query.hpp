@@ -29,17 +29,34 @@ __device__ __forceinline__ bool knn_less(double da, uint32_t ia, double db, uint
 // position order [d][n]; perm: original index of each position.  Fewer than
 // k points: the list ends with (NONE, +inf).  A query with a NaN coordinate
 // gets (NONE, NaN) throughout.
+//
+// Bound of a far child: with d <= 64, lane c holds the query's distance to
+// the current cell's box along coordinate c, and a far child's bound is the
+// squared distance to its box (the cell's bound with coordinate c's term
+// replaced by the gap to the split plane); a stack entry restores the
+// coordinate's distance once that subtree is done.  With larger d the bound
+// is the largest squared gap on the path.  A child is skipped only when its
+// bound exceeds the k-th distance by a relative margin far above the
+// rounding of these sums, so ties and rounding never drop a point.
+constexpr int KNN_BOX_DIMS = WAVE;
+__device__ __forceinline__ bool knn_visit(double lb, double worst) {
+    return lb <= worst + worst * 0x1p-30;
+}
+
 __global__ __launch_bounds__(NT) void k_knn(const int32_t *child, const uint32_t *dim,
                                             const uint32_t *split, const float *split_f,
                                             const uint32_t *nbeg, const uint32_t *nend,
                                             const float *pts, uint64_t n, const uint32_t *perm,
                                             const float *q, uint64_t nq, uint32_t d, uint64_t ldq,
                                             uint32_t k, uint32_t *idx_out, double *dist_out) {
-    __shared__ uint32_t snode_all[NW][QUERY_STACK];
-    __shared__ double slb_all[NW][QUERY_STACK];
-    uint32_t *snode = snode_all[wave()];
-    double *slb = slb_all[wave()];
+    // stack entry: a node to visit (with its bound, and the coordinate whose
+    // box distance changes there), or (NONE) a coordinate distance to restore
+    __shared__ uint32_t snode_all[NW][QUERY_STACK], sdim_all[NW][QUERY_STACK];
+    __shared__ double slb_all[NW][QUERY_STACK], soff_all[NW][QUERY_STACK];
+    uint32_t *snode = snode_all[wave()], *sdim = sdim_all[wave()];
+    double *slb = slb_all[wave()], *soff = soff_all[wave()];
     const int l = lane();
+    const bool box = d <= uint32_t(KNN_BOX_DIMS);
     for (uint64_t i = blockIdx.x * uint64_t(NW) + wave(); i < nq; i += uint64_t(gridDim.x) * NW) {
         bool nan = false;
         for (uint32_t c = l; c < d; c += WAVE) {
@@ -57,27 +74,55 @@ __global__ __launch_bounds__(NT) void k_knn(const int32_t *child, const uint32_t
         uint32_t bi = NONE;
         double worst = __builtin_inf();  // the k-th entry (lane k - 1)
         uint32_t worst_i = NONE;
+        double off = 0.0;  // lane c: distance to the current cell's box along c
         snode[0] = 0;
         slb[0] = 0.0;
+        sdim[0] = 0;
+        soff[0] = 0.0;
         int sp = 1;
         while (sp > 0) {
             sp--;
             uint32_t node = snode[sp];
-            const double lb = slb[sp];
-            if (lb > worst) continue;
+            const uint32_t ec = sdim[sp];
+            const double eoff = soff[sp];
+            if (node == NONE) {  // leaving a far subtree
+                if (uint32_t(l) == ec) off = eoff;
+                continue;
+            }
+            double lb = slb[sp];
+            if (!knn_visit(lb, worst)) continue;
+            if (box && node != 0) {
+                // entering a far child: its box distance along ec; restore later
+                const double old = __shfl(off, int(ec), WAVE);
+                snode[sp] = NONE;
+                sdim[sp] = ec;
+                soff[sp] = old;
+                sp++;
+                if (uint32_t(l) == ec) off = eoff;
+            }
             for (int step = 0; step <= MAX_LEVELS; step++) {
                 const int32_t ch = child[node];
                 if (ch < 0) break;
                 const uint32_t c = dim[node];
                 const float qv = q[uint64_t(c) * ldq + i];
                 const bool left = key_of_bits(__float_as_uint(qv)) <= split[node];
-                const double gap = double(split_f[node]) - double(qv);
-                double flb = gap * gap;
-                flb = flb != flb ? 0.0 : flb;  // no bound from infinite coordinates
-                flb = flb > lb ? flb : lb;
-                if (flb <= worst && sp < QUERY_STACK) {
+                double gap = double(split_f[node]) - double(qv);
+                gap = gap < 0.0 ? -gap : gap;
+                gap = gap != gap ? 0.0 : gap;  // no bound from infinite coordinates
+                double flb;
+                if (box) {
+                    const double oc = __shfl(off, int(c), WAVE);
+                    flb = lb - oc * oc + gap * gap;
+                    flb = flb > lb ? flb : lb;
+                } else {
+                    flb = gap * gap;
+                    flb = flb > lb ? flb : lb;
+                }
+                if (knn_visit(flb, worst) && sp < QUERY_STACK) {
                     snode[sp] = uint32_t(ch) + (left ? 1u : 0u);
                     slb[sp] = flb;
+                    sdim[sp] = c;
+                    soff[sp] = gap;
                     sp++;
                 }
                 node = uint32_t(ch) + (left ? 0u : 1u);

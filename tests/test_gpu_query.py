@@ -14,6 +14,8 @@ pytestmark = pytest.mark.gpu
 CASES = [  # (n, d, leaf, generator)
     (1, 1, 8, "uniform"), (7, 2, 1, "uniform"), (1000, 3, 8, "uniform"),
     (20000, 3, 32, "gmm"), (5000, 8, 16, "ties"), (30000, 16, 64, "gmm"),
+    # the widest box bound (one coordinate per lane), and the plane bound beyond it
+    (4000, 64, 16, "ties"), (3000, 65, 16, "gmm"), (2000, 200, 8, "gmm"),
 ]
 
 
