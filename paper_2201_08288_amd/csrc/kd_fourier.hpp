@@ -88,8 +88,9 @@ __device__ __forceinline__ double fourier_scale(int e) {
 
 // Accumulate the quantized harmonics j0 .. j0+FCHUNK-1 of one key into
 // acc[0..FCHUNK) (cosines) and acc[FCHUNK..2*FCHUNK) (sines).
+template <class ACC>
 __device__ __forceinline__ void fourier_terms(uint32_t key, double xmin, double scale, int J,
-                                              int j0, const TrigTables &T, long long *acc) {
+                                              int j0, const TrigTables &T, ACC *acc) {
     const double diff = value_of_key(key) - xmin;
     const float u = float(diff * scale);
     float s1, c1;
@@ -108,8 +109,8 @@ __device__ __forceinline__ void fourier_terms(uint32_t key, double xmin, double 
 #pragma unroll
     for (int k = 0; k < FCHUNK; k++) {
         if (j0 + k < J) {
-            acc[k] += (long long)(int)rintf(cj * 16777216.0f);
-            acc[FCHUNK + k] += (long long)(int)rintf(sj * 16777216.0f);
+            acc[k] += ACC((int)rintf(cj * 16777216.0f));
+            acc[FCHUNK + k] += ACC((int)rintf(sj * 16777216.0f));
         }
         const float a = cj * C2, b = sj * S2;
         const float g = sj * C2, h = cj * S2;

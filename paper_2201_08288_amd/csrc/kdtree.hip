@@ -523,29 +523,52 @@ __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t
     }
 }
 
-// FOURIER, large cells: smallest and largest key of every cell.
+// FOURIER, large cells: smallest and largest key of every cell.  A
+// workgroup takes a run of consecutive tiles (a tile's keys loaded at once),
+// keeps its threads' extremes while the run stays in one cell and adds them
+// into the cell's pair when it moves on.
 __global__ __launch_bounds__(NT) void k_big_minmax(Ctx c, uint32_t level) {
     __shared__ uint32_t s_cell;
     __shared__ uint32_t sh[2 * NW];
     const uint32_t cur = level & 1;
     const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = blockIdx.x * per, t1 = min(t0 + per, ntiles);
+    uint32_t big = NONE, mn = NONE, mx = 0;
+    auto flush = [&]() {
+        block_minmax(mn, mx, sh);
+        if (threadIdx.x == 0) {
+            atomicMin(&c.mm[2 * big], mn);
+            atomicMax(&c.mm[2 * big + 1], mx);
+        }
+        mn = NONE;
+        mx = 0;
+    };
+    for (uint32_t t = t0; t < t1; t++) {
         const TileView v = tile_view(c, cur, ncells, t, &s_cell);
+        if (v.cl.big != big) {
+            if (big != NONE) flush();
+            big = v.cl.big;
+        }
         const CellRes r = c.res[v.ci];
         const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
         const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
-        uint32_t mn = NONE, mx = 0;
-        for (uint32_t i = v.tb + threadIdx.x; i < v.te; i += NT) {
-            const uint32_t u = key_of_bits(col[i]);
-            mn = min(mn, u);
-            mx = max(mx, u);
+        uint32_t u[PER_THREAD];
+#pragma unroll
+        for (int j = 0; j < PER_THREAD; j++) {
+            const uint32_t i = v.tb + j * NT + threadIdx.x;
+            u[j] = i < v.te ? key_of_bits(col[i]) : NONE;
         }
-        block_minmax(mn, mx, sh);
-        if (threadIdx.x == 0) {
-            atomicMin(&c.mm[2 * v.cl.big], mn);
-            atomicMax(&c.mm[2 * v.cl.big + 1], mx);
+#pragma unroll
+        for (int j = 0; j < PER_THREAD; j++) {
+            const uint32_t i = v.tb + j * NT + threadIdx.x;
+            if (i < v.te) {
+                mn = min(mn, u[j]);
+                mx = max(mx, u[j]);
+            }
         }
     }
+    if (big != NONE) flush();
 }
 
 // Sum one chunk of per-thread moment accumulators over the workgroup into
@@ -573,33 +596,57 @@ __device__ __forceinline__ void reduce_moments(long long *acc, unsigned long lon
 }
 
 // FOURIER, large cells: the map step (quantized harmonics summed per cell).
+// A workgroup takes a run of consecutive tiles (a tile's keys loaded at
+// once), keeps its threads' integer sums while the run stays in one cell and
+// adds them into the cell's moments when it moves on.
 __global__ __launch_bounds__(NT) void k_big_moments(Ctx c, uint32_t level) {
     __shared__ uint32_t s_cell;
     __shared__ unsigned long long sh64[NW * 2 * FCHUNK];
     const uint32_t cur = level & 1;
     const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
     const int J = int(c.J);
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const TileView v = tile_view(c, cur, ncells, t, &s_cell);
-        const uint32_t lo = c.mm[2 * v.cl.big], hi = c.mm[2 * v.cl.big + 1];
-        if (lo == hi) {
-            __syncthreads();
-            continue;
-        }
-        const CellRes r = c.res[v.ci];
-        const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
-        const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
-        const int e = fourier_exponent(lo, hi);
-        const double xmin = value_of_key(lo), scale = fourier_scale(e);
-        long long *dst = c.mom + uint64_t(v.cl.big) * 2 * FOURIER_JMAX;
-        for (int j0 = 0; j0 < J; j0 += FCHUNK) {
-            long long acc[2 * FCHUNK];
+    const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = blockIdx.x * per, t1 = min(t0 + per, ntiles);
+    for (int j0 = 0; j0 < J; j0 += FCHUNK) {
+        uint32_t big = NONE;
+        long long acc[2 * FCHUNK];
 #pragma unroll
-            for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
-            for (uint32_t i = v.tb + threadIdx.x; i < v.te; i += NT)
-                fourier_terms(key_of_bits(col[i]), xmin, scale, J, j0, c.trig, acc);
-            reduce_moments(acc, sh64, j0, J, dst, true);
+        for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
+        for (uint32_t t = t0; t < t1; t++) {
+            const TileView v = tile_view(c, cur, ncells, t, &s_cell);
+            if (v.cl.big != big) {
+                if (big != NONE) {
+                    reduce_moments(acc, sh64, j0, J, c.mom + uint64_t(big) * 2 * FOURIER_JMAX, true);
+#pragma unroll
+                    for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
+                }
+                big = v.cl.big;
+            }
+            const uint32_t lo = c.mm[2 * big], hi = c.mm[2 * big + 1];
+            if (lo == hi) continue;  // all keys equal: no moments needed
+            const CellRes r = c.res[v.ci];
+            const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
+            const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
+            const int e = fourier_exponent(lo, hi);
+            const double xmin = value_of_key(lo), scale = fourier_scale(e);
+            uint32_t u[PER_THREAD];
+#pragma unroll
+            for (int j = 0; j < PER_THREAD; j++) {
+                const uint32_t i = v.tb + j * NT + threadIdx.x;
+                u[j] = i < v.te ? key_of_bits(col[i]) : 0u;
+            }
+            // a tile's sums per thread fit 32 bits (16 terms of at most 2^24)
+            static_assert(PER_THREAD * (1ll << 24) < (1ll << 31), "per-tile sums fit int32");
+            int a32[2 * FCHUNK];
+#pragma unroll
+            for (int k = 0; k < 2 * FCHUNK; k++) a32[k] = 0;
+            for (int j = 0; j < PER_THREAD; j++)
+                if (v.tb + j * NT + threadIdx.x < v.te)
+                    fourier_terms(u[j], xmin, scale, J, j0, c.trig, a32);
+#pragma unroll
+            for (int k = 0; k < 2 * FCHUNK; k++) acc[k] += a32[k];
         }
+        if (big != NONE) reduce_moments(acc, sh64, j0, J, c.mom + uint64_t(big) * 2 * FOURIER_JMAX, true);
     }
 }
 
@@ -3016,10 +3063,10 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                 }
             } else if (p->split_rule == KD_SPLIT_FOURIER) {
                 P.run(KD_PROF_SELECT, bigp, 8 * bigp, [&] {
-                    hipLaunchKernelGGL(k_big_minmax, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st,
-                                       c, level);
-                    hipLaunchKernelGGL(k_big_moments, dim3(grid_for(ntl, 65535)), dim3(NT), 0, st,
-                                       c, level);
+                    hipLaunchKernelGGL(k_big_minmax, dim3(grid_for(ntl, hist_grid)), dim3(NT), 0,
+                                       st, c, level);
+                    hipLaunchKernelGGL(k_big_moments, dim3(grid_for(ntl, hist_grid)), dim3(NT), 0,
+                                       st, c, level);
                 });
                 P.run(KD_PROF_PICK, 0, 0, [&] {
                     hipLaunchKernelGGL(k_big_fsolve, dim3(grid_for((nbig + NW - 1) / NW, 65535)),
