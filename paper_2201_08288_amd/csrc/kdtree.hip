@@ -1281,14 +1281,17 @@ __device__ void wave_candidate(const Ctx &c, const uint32_t *keys, uint32_t s0, 
             const int e = fourier_exponent(mn, mx);
             const double xmin = value_of_key(mn), scale = fourier_scale(e);
             for (int j0 = 0; j0 < J; j0 += FCHUNK) {
-                long long acc[2 * FCHUNK];
+                // a lane's sums fit 32 bits: at most WAVE_CELL_MAX / WAVE terms of 2^24
+                static_assert((WAVE_CELL_MAX / WAVE) * (1ll << 24) < (1ll << 31), "int32 sums");
+                int acc[2 * FCHUNK];
 #pragma unroll
                 for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
                 for (uint32_t i = l; i < nk; i += WAVE)
                     fourier_terms(keys[px(s0 + i)], xmin, scale, J, j0, c.trig, acc);
 #pragma unroll
                 for (int k = 0; k < 2 * FCHUNK; k++) {
-                    const long long sum = (long long)wave_sum64((unsigned long long)acc[k]);
+                    const long long sum =
+                        (long long)wave_sum64((unsigned long long)(long long)acc[k]);
                     const int j = j0 + (k % FCHUNK);
                     if (l == k && j < J) mom[(k < FCHUNK ? 0 : FOURIER_JMAX) + j] = sum;
                 }
@@ -1336,11 +1339,16 @@ __device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *ke
             const int e = fourier_exponent(mn, mx);
             const double xmin = value_of_key(mn), scale = fourier_scale(e);
             for (int j0 = 0; j0 < J; j0 += FCHUNK) {
+                // a thread's sums fit 32 bits: at most TILE / NT terms of 2^24
+                static_assert((TILE / NT) * (1ll << 24) < (1ll << 31), "int32 sums");
+                int a32[2 * FCHUNK];
+#pragma unroll
+                for (int k = 0; k < 2 * FCHUNK; k++) a32[k] = 0;
+                for (uint32_t i = threadIdx.x; i < nk; i += NT)
+                    fourier_terms(keys[px(s0 + i)], xmin, scale, J, j0, c.trig, a32);
                 long long acc[2 * FCHUNK];
 #pragma unroll
-                for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
-                for (uint32_t i = threadIdx.x; i < nk; i += NT)
-                    fourier_terms(keys[px(s0 + i)], xmin, scale, J, j0, c.trig, acc);
+                for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = a32[k];
                 reduce_moments(acc, sh64, j0, J, mom, false);
             }
             if (wave() == 0) {
@@ -1797,7 +1805,7 @@ __device__ __forceinline__ void sub_result(const Ctx &c, uint32_t depth, SubTabl
 }
 
 template <int RULE, bool MAXVAR>
-__global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_FOURIER ? 2 : 3) void k_subtree(
+__global__ __launch_bounds__(NT, MAXVAR ? 2 : 3) void k_subtree(
     Ctx c, uint32_t level) {
     constexpr int SC = subtree_cells<MAXVAR>();
     constexpr int CH = MAXVAR ? 2 * SC : SC;
