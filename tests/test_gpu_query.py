@@ -86,6 +86,28 @@ def test_knn_nan_query_and_rules():
         assert np.array_equal(gd.cpu().numpy()[ok], od[ok])
 
 
+def test_knn_infinite_and_huge_query_coordinates():
+    """Queries with an infinite coordinate (every distance is +inf: the list is
+    the k lowest indices, so every leaf must be reached) and with coordinates
+    near the float limit."""
+    import torch
+
+    from paper_2201_08288_amd import kdtree
+    print("case knn infinite query coordinates", flush=True)
+    x = synth.gmm(8000, 3, seed=4)
+    q = queries_for(x, 20, seed=11)
+    q[0, 3] = np.inf
+    q[2, 4] = -np.inf
+    q[:, 5] = np.float32(3.0e38)
+    q[1, 6] = np.float32(-3.0e38)
+    t = built(x, 16)
+    for k in (1, 8, 64):
+        gi, gd = kdtree.query_knn(t, torch.from_numpy(q).cuda(), k)
+        oi, od = oracle.knn(x, q, k)
+        assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
+        assert np.array_equal(gd.cpu().numpy().view(np.uint64), od.view(np.uint64))
+
+
 def boxes_for(x, m, seed):
     rng = np.random.default_rng(seed)
     d, n = x.shape
