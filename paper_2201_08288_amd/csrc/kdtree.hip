@@ -1804,8 +1804,95 @@ __device__ __forceinline__ void sub_result(const Ctx &c, uint32_t depth, SubTabl
     A.flags[q] = r.flags;
 }
 
+// SUBSET with equal subsets, inside a subtree chunk: the candidates of all
+// active sub-cells, in groups whose subset bounds B[0..S] and medians
+// med[0..S) fit `dyn` (dyn_words words).  Equal subsets depend only on a
+// sub-cell's size, so no level-wide rank is needed.  Subsets of at most
+// RANK_MAX points find their lower median by counting ranks (ties broken by
+// slot, the stable order), larger ones by a wave radix select; the weighted
+// mean is one thread per sub-cell in subset order; then the counts around the
+// candidate and the tie rule, one wave per sub-cell.
+template <int SC, int CH>
+__device__ void subtree_subset(const Ctx &c, uint32_t depth, const uint32_t *keys,
+                               const uint8_t *seg, SubTable<SC, CH> &A, uint32_t *dyn,
+                               uint32_t dyn_words, uint32_t (*h)[NBINS]) {
+    const uint32_t S = c.S, stride = 2 * S + 1, nq = A.count;
+    const uint32_t G = dyn_words / stride;  // at least 1: dyn_words >= 2S + 1
+    const int w = wave(), l = lane();
+    for (uint32_t q0 = 0; q0 < nq; q0 += G) {
+        const uint32_t g1 = min(G, nq - q0);
+        for (uint32_t g = w; g < g1; g += NW) {
+            const uint32_t n = A.end[q0 + g] - A.start[q0 + g];
+            uint32_t *B = dyn + g * stride;
+            for (uint32_t r = l; r <= S; r += WAVE) B[r] = uint32_t((uint64_t(r) * n) / S);
+        }
+        __syncthreads();
+        const uint32_t e0 = A.start[q0], e1 = A.end[q0 + g1 - 1];
+        for (uint32_t e = e0 + threadIdx.x; e < e1; e += NT) {
+            const uint32_t q = seg[e];
+            if (q == SEG_LEAF || q < q0 || q >= q0 + g1) continue;
+            const uint32_t g = q - q0, i = e - A.start[q];
+            const uint32_t *B = dyn + g * stride;
+            uint32_t lo = 0, hi = S;  // the last r with B[r] <= i
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (B[mid] <= i) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t b = B[lo], m = B[lo + 1] - b;
+            if (m > RANK_MAX) continue;
+            const uint32_t s0 = A.start[q] + b, u = keys[px(e)];
+            uint32_t rank = 0;
+            for (uint32_t j = 0; j < m; j++) {
+                const uint32_t v = keys[px(s0 + j)];
+                rank += (v < u) || (v == u && s0 + j < e);
+            }
+            if (rank == (m - 1) / 2) dyn[g * stride + S + 1 + lo] = u;
+        }
+        for (uint32_t g = w; g < g1; g += NW) {
+            const uint32_t *B = dyn + g * stride;
+            uint32_t *med = dyn + g * stride + S + 1;
+            for (uint32_t r0 = 0; r0 < S; r0 += WAVE) {
+                const uint32_t r = r0 + l;
+                bool large = false;
+                if (r < S) {
+                    const uint32_t m = B[r + 1] - B[r];
+                    if (m == 0) med[r] = NONE;
+                    large = m > RANK_MAX;
+                }
+                for (unsigned long long mask = __ballot(large); mask; mask &= mask - 1) {
+                    const uint32_t rr = r0 + uint32_t(__builtin_ctzll(mask));
+                    const uint32_t b = B[rr], m = B[rr + 1] - b;
+                    const uint32_t v = wave_select(keys, A.start[q0 + g] + b, m, (m - 1) / 2, h[w]);
+                    if (l == 0) med[rr] = v;
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t g = threadIdx.x; g < g1; g += NT) {
+            const uint32_t q = q0 + g;
+            A.split[q] = subset_mean(dyn + g * stride, dyn + g * stride + S + 1, S,
+                                     A.end[q] - A.start[q]);
+        }
+        __syncthreads();
+        for (uint32_t g = w; g < g1; g += NW) {
+            const uint32_t q = q0 + g, s0 = A.start[q], nk = A.end[q] - s0, m = A.split[q];
+            uint32_t a = 0, b = 0;
+            for (uint32_t i = l; i < nk; i += WAVE) {
+                const uint32_t u = keys[px(s0 + i)];
+                a += u < m;
+                b += u <= m;
+            }
+            a = uint32_t(wave_sum64(a));
+            b = uint32_t(wave_sum64(b));
+            if (l == 0) sub_result(c, depth, A, q, m, a, b);
+        }
+        __syncthreads();
+    }
+}
+
 template <int RULE, bool MAXVAR>
-__global__ __launch_bounds__(NT, MAXVAR ? 2 : 3) void k_subtree(
+__global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void k_subtree(
     Ctx c, uint32_t level) {
     constexpr int SC = subtree_cells<MAXVAR>();
     constexpr int CH = MAXVAR ? 2 * SC : SC;
@@ -1831,6 +1918,9 @@ __global__ __launch_bounds__(NT, MAXVAR ? 2 : 3) void k_subtree(
     __shared__ unsigned long long pat[2][MAXVAR ? CH : 1][3];
     __shared__ unsigned long long wtot[2][MAXVAR ? NW : 1][3];
     static_assert(CH < int(SEG_LEAF), "child numbers fit a byte below SEG_LEAF");
+    // SUBSET: subset bounds and medians (dynamic LDS of max(4096, 2S + 1) words)
+    extern __shared__ uint32_t dyn_lds[];
+    const uint32_t dyn_words = RULE == KD_SPLIT_SUBSET ? max(SUBSET_DYN_WORDS, 2 * c.S + 1) : 0u;
     uint32_t(*const h)[NBINS] = lds.sel.h;
     unsigned long long *const sh64 = lds.sel.sh64;
     auto &mom = lds.sel.mom;
@@ -1898,20 +1988,24 @@ __global__ __launch_bounds__(NT, MAXVAR ? 2 : 3) void k_subtree(
                 }
                 __syncthreads();
                 // split of every active sub-cell: wide ones by the workgroup,
-                // the others one per wave
-                for (uint32_t qq = 0; qq < A.nwide; qq++) {
-                    const uint32_t q = A.wide[qq];
-                    uint32_t m, lt, le;
-                    block_candidate<RULE>(c, depth, keys, A.start[q], A.end[q] - A.start[q], 0u, h,
-                                          sh, s3, sh64, mom[0], nullptr, m, lt, le);
-                    if (threadIdx.x == 0) sub_result(c, depth, A, q, m, lt, le);
-                }
-                for (uint32_t q = w; q < nq; q += NW) {
-                    const uint32_t s0 = A.start[q], nk = A.end[q] - s0;
-                    if (nk > WAVE_CELL_MAX) continue;
-                    uint32_t m, lt, le;
-                    wave_candidate<RULE>(c, keys, s0, nk, h[w], mom[w], m, lt, le);
-                    if (l == 0) sub_result(c, depth, A, q, m, lt, le);
+                // the others one per wave (SUBSET: all of them in groups)
+                if constexpr (RULE == KD_SPLIT_SUBSET) {
+                    subtree_subset(c, depth, keys, seg, A, dyn_lds, dyn_words, h);
+                } else {
+                    for (uint32_t qq = 0; qq < A.nwide; qq++) {
+                        const uint32_t q = A.wide[qq];
+                        uint32_t m, lt, le;
+                        block_candidate<RULE>(c, depth, keys, A.start[q], A.end[q] - A.start[q],
+                                              0u, h, sh, s3, sh64, mom[0], nullptr, m, lt, le);
+                        if (threadIdx.x == 0) sub_result(c, depth, A, q, m, lt, le);
+                    }
+                    for (uint32_t q = w; q < nq; q += NW) {
+                        const uint32_t s0 = A.start[q], nk = A.end[q] - s0;
+                        if (nk > WAVE_CELL_MAX) continue;
+                        uint32_t m, lt, le;
+                        wave_candidate<RULE>(c, keys, s0, nk, h[w], mom[w], m, lt, le);
+                        if (l == 0) sub_result(c, depth, A, q, m, lt, le);
+                    }
                 }
                 __syncthreads();
                 // children that are split again, numbered in slot order; their
@@ -2651,7 +2745,11 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     // records of cells resolved ahead: each is a node of its tree
     uint64_t caps = 0;
     for (uint32_t t = 0; t < T; t++) caps += cap[t];
-    L.rec_cap = p->split_rule == KD_SPLIT_SUBSET ? 0 : std::min<uint64_t>(caps, REC_INDEX - 1);
+    // records of splits found ahead: the subtree path (every rule but SUBSET
+    // with a subset pool or the largest-variance key)
+    const bool per_level = p->split_rule == KD_SPLIT_SUBSET &&
+                           (p->subset_pool != nullptr || p->key_rule == KD_KEY_MAXVAR);
+    L.rec_cap = per_level ? 0 : std::min<uint64_t>(caps, REC_INDEX - 1);
     L.subrec = B.take(L.rec_cap * sizeof(SubRec));
     L.rec_count = B.take(4);
     L.res = B.take(L.max_cells * sizeof(CellRes));
@@ -3124,17 +3222,22 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         if (smallp > 0) {
             P.run(KD_PROF_SMALL, smallp, scatter_avg_bpp * smallp, [&] {
                 const dim3 g(grid_for((smallp + TILE - 1) / TILE, small_grid));
-#define KD_SUB(R, M) hipLaunchKernelGGL((k_subtree<R, M>), g, dim3(NT), 0, st, c, level)
+#define KD_SUB(R, M) hipLaunchKernelGGL((k_subtree<R, M>), g, dim3(NT), small_dyn, st, c, level)
 #define KD_SMALL(R, M) hipLaunchKernelGGL((k_small<R, M>), g, dim3(NT), small_dyn, st, c, level)
-                // EXACT and FOURIER finish small cells' subtrees in one pass;
-                // SUBSET's subset pool rows depend on a cell's rank within its
-                // level, which is known only level by level
+                // EXACT, FOURIER and SUBSET with equal subsets finish small
+                // cells' subtrees in one pass; a subset pool's rows depend on a
+                // cell's rank within its level, known only level by level
                 switch (p->split_rule * 2 + (maxvar ? 1 : 0)) {
                     case 0: KD_SUB(KD_SPLIT_EXACT, false); break;
                     case 1: KD_SUB(KD_SPLIT_EXACT, true); break;
                     case 2: KD_SUB(KD_SPLIT_FOURIER, false); break;
                     case 3: KD_SUB(KD_SPLIT_FOURIER, true); break;
-                    case 4: KD_SMALL(KD_SPLIT_SUBSET, false); break;
+                    case 4:
+                        // equal subsets depend only on a cell's size: the
+                        // subtree path; pool rows need the level-wide rank
+                        if (c.pool) KD_SMALL(KD_SPLIT_SUBSET, false);
+                        else KD_SUB(KD_SPLIT_SUBSET, false);
+                        break;
                     default: KD_SMALL(KD_SPLIT_SUBSET, true); break;
                 }
 #undef KD_SMALL
