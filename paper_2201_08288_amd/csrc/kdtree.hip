@@ -1379,7 +1379,7 @@ __device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *ke
 // position); larger subsets use a wave radix select.  The weighted mean runs
 // one thread per cell, in subset order.
 constexpr uint32_t RANK_MAX = 64;
-constexpr uint32_t SUBSET_DYN_WORDS = 4096;  // dynamic LDS of the SUBSET small-cell kernel
+constexpr uint32_t SUBSET_DYN_WORDS = 7680;  // dynamic LDS of the SUBSET small-cell kernels (30 KB)
 template <int SC>
 __device__ void subset_cells(const Ctx &c, uint32_t level, const uint32_t *keys,
                              const uint8_t *seg, ChunkLds<SC> &C, uint32_t k0, uint32_t G,
