@@ -283,7 +283,20 @@ __global__ __launch_bounds__(NT) void k_copy_leafroots(Ctx c) {
 // ------------------------------------------------------------ kernels: per level
 
 // a2 and per-level state: key coordinate, select start, zeroed accumulators.
-__global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level) {
+__device__ __forceinline__ uint32_t find_tile_cell(const Cell *cells, uint32_t ncells, uint32_t t) {
+    uint32_t lo = 0, hi = ncells;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (cells[mid].tile0 <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Per cell: its key coordinate and target rank (or the split a subtree
+// found ahead), and the large cells' accumulators cleared.  With map_tiles,
+// also the cell of every tile of the level's large cells.
+__global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level, uint32_t map_tiles) {
     const uint32_t cur = level & 1, nxt = cur ^ 1;
     const uint32_t ncells = c.info[level].num_cells;
     for (uint32_t ci = blockIdx.x * NT + threadIdx.x; ci < ncells; ci += gridDim.x * NT) {
@@ -339,16 +352,11 @@ __global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level) {
             }
         }
     }
-}
-
-__device__ __forceinline__ uint32_t find_tile_cell(const Cell *cells, uint32_t ncells, uint32_t t) {
-    uint32_t lo = 0, hi = ncells;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (cells[mid].tile0 <= t) lo = mid;
-        else hi = mid;
+    if (map_tiles) {
+        const uint32_t ntiles = c.info[level].num_tiles;
+        for (uint32_t t = blockIdx.x * NT + threadIdx.x; t < ntiles; t += gridDim.x * NT)
+            c.tile_cell[t] = find_tile_cell(c.cells[cur], ncells, t);
     }
-    return lo;
 }
 
 // Tie rule and leaf flags once the candidate and its counts are known.
@@ -391,13 +399,6 @@ __device__ __forceinline__ TileView tile_view(const Ctx &c, uint32_t cur, uint32
     return v;
 }
 
-// Cell of every tile of the level's large cells.
-__global__ __launch_bounds__(NT) void k_tile_map(Ctx c, uint32_t level) {
-    const uint32_t cur = level & 1;
-    const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
-    for (uint32_t t = blockIdx.x * NT + threadIdx.x; t < ntiles; t += gridDim.x * NT)
-        c.tile_cell[t] = find_tile_cell(c.cells[cur], ncells, t);
-}
 
 // EXACT, large cells: digit histograms of a run of consecutive tiles in LDS,
 // added into the cell's histogram whenever the run moves to another cell.
@@ -938,18 +939,24 @@ __global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level) {
         const Cell cl = c.cells[cur][ci];
         const uint32_t n_c = cl.end - cl.begin;
         const uint32_t nt = (n_c + TILE - 1) / TILE;
-        uint32_t lt = 0, le = 0;
-        for (uint32_t k0 = 0; k0 < nt; k0 += NT) {
-            const uint32_t k = k0 + threadIdx.x;
-            const uint32_t a = k < nt ? c.tile_lt[cl.tile0 + k] : 0u;
-            const uint32_t e = k < nt ? c.tile_le[cl.tile0 + k] : 0u;
-            uint32_t ta, te;
-            block_excl_scan(a, sh, &ta);
-            block_excl_scan(e, sh, &te);
-            lt += ta;
-            le += te;
-        }
         CellRes r = c.res[ci];
+        // EXACT: the last digit pick left the cell's exact counts around the
+        // candidate; the other rules add up the tiles' counts
+        uint32_t lt = r.lt, le = r.le;
+        if (c.split_rule != KD_SPLIT_EXACT) {
+            lt = 0;
+            le = 0;
+            for (uint32_t k0 = 0; k0 < nt; k0 += NT) {
+                const uint32_t k = k0 + threadIdx.x;
+                const uint32_t a = k < nt ? c.tile_lt[cl.tile0 + k] : 0u;
+                const uint32_t e = k < nt ? c.tile_le[cl.tile0 + k] : 0u;
+                uint32_t ta, te;
+                block_excl_scan(a, sh, &ta);
+                block_excl_scan(e, sh, &te);
+                lt += ta;
+                le += te;
+            }
+        }
         finish_cell(c, level, n_c, r, r.cand, lt, le);
         const bool use_le = (r.flags & RES_SPLIT) && r.split == r.cand;
         const uint32_t li = ci - c.ts[cl.tree].first[cur];
@@ -3148,14 +3155,10 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         const uint64_t nc = B.cells, ntl = B.tiles, nbig = B.big;
         const uint64_t bigp = B.big_points, smallp = B.small_points;
         P.run(KD_PROF_OTHER, 0, 0, [&] {
-            hipLaunchKernelGGL(k_level_init, dim3(grid_for(nc / NT + 1, 4096)), dim3(NT), 0, st,
-                               c, level);
+            hipLaunchKernelGGL(k_level_init, dim3(grid_for(std::max(nc, ntl) / NT + 1, 4096)),
+                               dim3(NT), 0, st, c, level, nbig > 0 ? 1u : 0u);
         });
         if (nbig > 0) {
-            P.run(KD_PROF_OTHER, 0, 0, [&] {
-                hipLaunchKernelGGL(k_tile_map, dim3(grid_for(ntl / NT + 1, 4096)), dim3(NT), 0, st,
-                                   c, level);
-            });
             if (p->split_rule == KD_SPLIT_EXACT) {
                 for (uint32_t pass = 0; pass < uint32_t(BIG_PASSES); pass++) {
                     P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
