@@ -8,8 +8,15 @@
  * header, table or constant generator with the GPU library: every formula
  * below is written out here on its own.
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
- * (contraction off: every a*b+c below is two rounded IEEE operations).
+ * Build: gcc -O2 -march=x86-64-v2 -std=gnu11 -fopenmp -ffp-contract=off -fno-fast-math -shared
+ * -fPIC (contraction off: every a*b+c below is two rounded IEEE operations).
+ *
+ * Threads (OpenMP) only share out independent work: the cells of a level,
+ * the trees of a batch, and inside a large cell its coordinates, subsets or
+ * points.  Every floating-point value is computed by the same operations in
+ * the same order whatever the thread count, and the only sums formed across
+ * threads are integer sums, which are exact; so the results do not depend
+ * on the number of threads.
  *
  * What is computed (one cell at a time, level by level, as in §2 and §4):
  *   - the cell's key coordinate: cyclic (§1, §2) or largest variance (§1);
@@ -32,6 +39,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
 
 #define KDO_OK 0
 #define KDO_EINVAL 1
@@ -90,10 +98,31 @@ uint64_t kdo_splitmix64(uint64_t x)
     return z ^ (z >> 31);
 }
 
-static int cmp_u32(const void *a, const void *b)
+/* Ascending sort of uint32 values: insertion sort below 64 values, else a
+ * least-significant-digit radix sort, four stable counting-sort passes over
+ * the bytes (lowest byte first).                                           */
+static void sort_u32(uint32_t *a, uint64_t n)
 {
-    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
-    return (x > y) - (x < y);
+    if (n < 64) {
+        for (uint64_t i = 1; i < n; i++) {
+            uint32_t v = a[i];
+            uint64_t j = i;
+            while (j > 0 && a[j - 1] > v) { a[j] = a[j - 1]; j--; }
+            a[j] = v;
+        }
+        return;
+    }
+    uint32_t *b = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    for (int shift = 0; shift < 32; shift += 8) {
+        uint64_t count[257];
+        memset(count, 0, sizeof(count));
+        for (uint64_t i = 0; i < n; i++) count[((a[i] >> shift) & 0xffu) + 1]++;
+        for (int v = 0; v < 256; v++) count[v + 1] += count[v];
+        for (uint64_t i = 0; i < n; i++) b[count[(a[i] >> shift) & 0xffu]++] = a[i];
+        uint32_t *t = a; a = b; b = t;
+    }
+    /* four passes: the sorted values are back in the caller's array */
+    free(b);
 }
 
 /* ------------------------------------------------------------------ */
@@ -105,7 +134,7 @@ uint32_t kdo_lower_median(const uint32_t *keys, uint64_t n)
 {
     uint32_t *tmp = (uint32_t *)malloc(n * sizeof(uint32_t));
     memcpy(tmp, keys, n * sizeof(uint32_t));
-    qsort(tmp, n, sizeof(uint32_t), cmp_u32);
+    sort_u32(tmp, n);
     uint32_t m = tmp[(n - 1) / 2];
     free(tmp);
     return m;
@@ -162,45 +191,57 @@ void kdo_subset_bounds(uint64_t n, uint32_t S, const uint32_t *pool, uint32_t P,
 /* V_c = n*sum(q^2) - (sum q)^2 = n^2 * variance, exact in 128 bits.   */
 /* The key is the smallest c with the largest V_c.                      */
 /* ------------------------------------------------------------------ */
+/* Work of at least this many points is shared among threads. */
+#define KDO_PAR_MIN 65536
+
 int kdo_maxvar_shift(const float *pts, uint64_t n, uint32_t d, uint64_t ld)
 {
     double mx = 0.0;
-    for (uint32_t c = 0; c < d; c++)
+    for (uint32_t c = 0; c < d; c++) {
+#pragma omp parallel for reduction(max : mx) if (n >= KDO_PAR_MIN)
         for (uint64_t i = 0; i < n; i++) {
             double a = fabs((double)pts[c * ld + i]);
             if (a > mx) mx = a;
         }
+    }
     if (mx == 0.0) return 0;
     int E;
     frexp(mx, &E);
     return 30 - E;
 }
 
-static int32_t fixed_q(float x, int shift)
+/* q = rint(x * 2^shift); the product by a power of two is exact in double
+ * (|x * 2^shift| < 2^30, far from the double range's ends). */
+static int32_t fixed_q(float x, double two_to_shift)
 {
-    double t = ldexp((double)x, shift);
+    double t = (double)x * two_to_shift;
     return (int32_t)nearbyint(t);
 }
 
 uint32_t kdo_maxvar_key(const float *pts, uint32_t d, uint64_t ld,
                         const uint32_t *idx, uint64_t n, int shift)
 {
-    uint32_t best = 0;
-    __int128 bestv = -1;
+    __int128 *V = (__int128 *)malloc(d * sizeof(__int128));
+    const double two_to_shift = ldexp(1.0, shift);
+#pragma omp parallel for schedule(dynamic, 1) if (n >= KDO_PAR_MIN)
     for (uint32_t c = 0; c < d; c++) {
         int64_t s1 = 0;
         uint64_t s2hi = 0, s2lo = 0;
         for (uint64_t i = 0; i < n; i++) {
-            int64_t q = fixed_q(pts[c * ld + idx[i]], shift);
+            int64_t q = fixed_q(pts[c * ld + (idx ? idx[i] : i)], two_to_shift);
             uint64_t q2 = (uint64_t)(q * q);
             s1 += q;
             s2hi += q2 >> 32;
             s2lo += q2 & 0xffffffffull;
         }
         __int128 S2 = ((__int128)s2hi << 32) + (__int128)s2lo;
-        __int128 V = (__int128)n * S2 - (__int128)s1 * (__int128)s1;
-        if (V > bestv) { bestv = V; best = c; }
+        V[c] = (__int128)n * S2 - (__int128)s1 * (__int128)s1;
     }
+    uint32_t best = 0;
+    __int128 bestv = -1;
+    for (uint32_t c = 0; c < d; c++)
+        if (V[c] > bestv) { bestv = V[c]; best = c; }
+    free(V);
     return best;
 }
 
@@ -212,12 +253,21 @@ uint32_t kdo_maxvar_key(const float *pts, uint32_t d, uint64_t ld,
 /* (f_k is exact for k <= 22), then rounded to the working precision.  */
 /* Each multiply and add is rounded separately.                          */
 /* ------------------------------------------------------------------ */
-static double inv_factorial(int k)
+static double inv_factorial_of(int k)
 {
     double f = 1.0;
     for (int i = 2; i <= k; i++) f *= (double)i;
     return 1.0 / f;
 }
+
+/* 1/k! for k = 0..25, formed once when the library is loaded */
+static double inv_fact_table[26];
+__attribute__((constructor)) static void make_inv_fact_table(void)
+{
+    for (int k = 0; k < 26; k++) inv_fact_table[k] = inv_factorial_of(k);
+}
+
+static double inv_factorial(int k) { return inv_fact_table[k]; }
 
 void kdo_sincos_f32(float x, float *s, float *c)
 {
@@ -263,11 +313,15 @@ void kdo_sincos_f64(double x, double *s, double *c)
 
 /* ------------------------------------------------------------------ */
 /* FOURIER rule: per-cell affine map of the key.                       */
-/* The paper scales the data (§2) without saying how.  Each cell maps   */
-/* its key by x -> (x - min) * 2^(1-e), 2^(e-1) <= max - min < 2^e, so  */
-/* the largest key lands in [1, 2) and every difference of two mapped  */
-/* values lies in (-2, 2), inside (-pi, pi) where the expansion of      */
-/* 1(x < c) used by Lemma 3.1 holds (App. A).  Returns e.               */
+/* §2 takes every observation to lie in (0, 1), and Lemma 3.1 states    */
+/* c_j and g_j there; how data are brought there is not said.  Each     */
+/* cell maps its key by x -> (x - min) * 2^-e with 2^(e-1) <= max - min  */
+/* < 2^e: a power of two, so the map is exact in double; the smallest    */
+/* key lands on 0 and the largest in [1/2, 1).  The cell is the whole    */
+/* unit interval (a = 0, b = 1), so the boundary terms of Lemma 3.1      */
+/* vanish, and every difference of two mapped values lies in (-1, 1),    */
+/* inside (-pi, pi) where the expansion of 1(x < c) holds (App. A).      */
+/* Returns e.                                                            */
 /* ------------------------------------------------------------------ */
 int kdo_fourier_exponent(uint32_t lo_key, uint32_t hi_key)
 {
@@ -288,7 +342,7 @@ void kdo_fourier_map(const uint32_t *keys, uint64_t n, uint32_t lo_key, int e,
                      uint32_t J, int64_t *Cc, int64_t *Cs)
 {
     double xmin = value_of_key(lo_key);
-    double scale = ldexp(1.0, 1 - e);
+    double scale = ldexp(1.0, -e);
     for (uint64_t i = 0; i < n; i++) {
         double diff = value_of_key(keys[i]) - xmin;
         float u = (float)(diff * scale);
@@ -352,7 +406,7 @@ uint32_t kdo_fourier_solve(const int64_t *Cc, const int64_t *Cs, uint32_t J,
                            uint32_t lo_key, uint32_t hi_key, int e)
 {
     double xmin = value_of_key(lo_key);
-    double scale = ldexp(1.0, 1 - e);
+    double scale = ldexp(1.0, -e);
     uint32_t lo = lo_key, hi = hi_key;
     if (kdo_fourier_F(Cc, Cs, J, 0.0) >= 0.0) return lo;
     while (hi - lo > 1u) {
@@ -366,8 +420,10 @@ uint32_t kdo_fourier_solve(const int64_t *Cc, const int64_t *Cs, uint32_t J,
 
 /* ------------------------------------------------------------------ */
 /* One cell: key choice, candidate, tie rule.                           */
-/* cell_idx[0..nc): original point indices of the cell, in its current */
-/* (stable) order.  Returns 1 if the cell splits (dim/split set).       */
+/* cell_idx[0..nc): indices into pts of the cell's points, in the      */
+/* cell's current (stable) order; NULL: the cell's points are           */
+/* pts[c * ld + i] for i < nc, already in that order.                   */
+/* Returns 1 if the cell splits (dim/split set).                        */
 /* ------------------------------------------------------------------ */
 int kdo_cell_split(const float *pts, uint32_t d, uint64_t ld, const kdo_params *p,
                    int maxvar_shift, const uint32_t *cell_idx, uint64_t nc,
@@ -382,8 +438,9 @@ int kdo_cell_split(const float *pts, uint32_t d, uint64_t ld, const kdo_params *
     *dim_out = t;
 
     uint32_t *keys = (uint32_t *)malloc(nc * sizeof(uint32_t));
+#pragma omp parallel for if (nc >= KDO_PAR_MIN)
     for (uint64_t i = 0; i < nc; i++)
-        keys[i] = kdo_key_of_bits(bits_of_float(pts[t * ld + cell_idx[i]]));
+        keys[i] = kdo_key_of_bits(bits_of_float(pts[t * ld + (cell_idx ? cell_idx[i] : i)]));
 
     uint32_t m;
     if (p->split_rule == KDO_SPLIT_EXACT) {
@@ -403,30 +460,37 @@ int kdo_cell_split(const float *pts, uint32_t d, uint64_t ld, const kdo_params *
             } else {
                 uint32_t J = p->fourier_J;
                 int e = kdo_fourier_exponent(lo, hi);
-                int64_t *Cc = (int64_t *)calloc(J, sizeof(int64_t));
-                int64_t *Cs = (int64_t *)calloc(J, sizeof(int64_t));
-                int64_t *pc = (int64_t *)malloc(J * sizeof(int64_t));
-                int64_t *ps = (int64_t *)malloc(J * sizeof(int64_t));
-                /* map per subset, reduce by addition (App. C.2) */
+                /* map per subset (each subset's own sums), then reduce by
+                 * addition (App. C.2); integer sums, so exact in any order */
+                int64_t Cc[64], Cs[64];
+                memset(Cc, 0, sizeof(Cc));
+                memset(Cs, 0, sizeof(Cs));
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : Cc, Cs) if (nc >= KDO_PAR_MIN)
                 for (uint32_t r = 0; r < S; r++) {
+                    int64_t pc[64], ps[64];
                     memset(pc, 0, J * sizeof(int64_t));
                     memset(ps, 0, J * sizeof(int64_t));
                     kdo_fourier_map(keys + B[r], B[r + 1] - B[r], lo, e, J, pc, ps);
                     for (uint32_t j = 0; j < J; j++) { Cc[j] += pc[j]; Cs[j] += ps[j]; }
                 }
                 m = kdo_fourier_solve(Cc, Cs, J, lo, hi, e);
-                free(Cc); free(Cs); free(pc); free(ps);
             }
         } else {
             /* SUBSET (not from the paper): weighted mean of subset lower medians */
+            uint32_t *med = (uint32_t *)malloc(S * sizeof(uint32_t));
+#pragma omp parallel for schedule(dynamic, 1) if (nc >= KDO_PAR_MIN)
+            for (uint32_t r = 0; r < S; r++) {
+                uint64_t ns = B[r + 1] - B[r];
+                med[r] = ns ? kdo_lower_median(keys + B[r], ns) : 0u;
+            }
             double acc = 0.0;
             for (uint32_t r = 0; r < S; r++) {
                 uint64_t ns = B[r + 1] - B[r];
                 if (ns == 0) continue;
-                uint32_t med = kdo_lower_median(keys + B[r], ns);
-                double prod = (double)ns * value_of_key(med);
+                double prod = (double)ns * value_of_key(med[r]);
                 acc = acc + prod;
             }
+            free(med);
             double mean = acc / (double)nc;
             /* the rounded mean stays within [smallest, largest] subset median:
              * the double sum errs by at most S * 2^-53 relative, far below
@@ -438,6 +502,7 @@ int kdo_cell_split(const float *pts, uint32_t d, uint64_t ld, const kdo_params *
     *cand_out = m;
 
     uint64_t lt = 0, le = 0;
+#pragma omp parallel for reduction(+ : lt, le) if (nc >= KDO_PAR_MIN)
     for (uint64_t i = 0; i < nc; i++) {
         lt += keys[i] < m;
         le += keys[i] <= m;
@@ -457,6 +522,7 @@ int kdo_cell_split(const float *pts, uint32_t d, uint64_t ld, const kdo_params *
 /*      [4] point_levels [5] unsplittable [6] oversize leaves           */
 /* ------------------------------------------------------------------ */
 typedef struct { uint64_t begin, end; uint32_t node, depth; } kdo_cell;
+typedef struct { int ok; uint32_t dim, split, cand; uint64_t nl; } kdo_split;
 
 static int cmp_leaf(const void *a, const void *b)
 {
@@ -475,16 +541,26 @@ int kdo_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const kdo_p
         (p->split_rule == KDO_SPLIT_FOURIER && (p->fourier_J == 0 || p->fourier_J > 64)) ||
         p->node_capacity == 0)
         return KDO_EINVAL;
-    for (uint32_t c = 0; c < d; c++)
-        for (uint64_t i = 0; i < n; i++)
-            if (!isfinite(pts[c * ld + i])) { hdr[3] = KDO_ENONFINITE; return KDO_ENONFINITE; }
+    uint64_t nonfinite = 0;
+    for (uint32_t c = 0; c < d; c++) {
+#pragma omp parallel for reduction(+ : nonfinite) if (n >= KDO_PAR_MIN)
+        for (uint64_t i = 0; i < n; i++) nonfinite += !isfinite(pts[c * ld + i]);
+    }
+    if (nonfinite) { hdr[3] = KDO_ENONFINITE; return KDO_ENONFINITE; }
 
     uint32_t max_depth = p->max_depth ? p->max_depth : 64;
     uint64_t cap = p->node_capacity;
     int shift = p->key_rule == KDO_KEY_MAXVAR ? kdo_maxvar_shift(pts, n, d, ld) : 0;
 
+    /* work: original index of the point at each position; wp: the points
+     * themselves in the same position order ([d][n]), moved with work by
+     * every partition, so a cell's points are always contiguous */
     uint32_t *work = (uint32_t *)malloc(n * sizeof(uint32_t));
     uint32_t *tmp = (uint32_t *)malloc(n * sizeof(uint32_t));
+    float *wp = (float *)malloc((size_t)d * n * sizeof(float));
+    float *wtmp = (float *)malloc((size_t)d * n * sizeof(float));
+    uint8_t *side_of = (uint8_t *)malloc(n);
+    for (uint32_t c = 0; c < d; c++) memcpy(wp + (size_t)c * n, pts + c * ld, n * sizeof(float));
     kdo_cell *cur = (kdo_cell *)malloc(sizeof(kdo_cell));
     uint64_t ncur = 0, num_nodes = 1, point_levels = 0, unsplittable = 0;
     uint32_t max_node_depth = 0;
@@ -501,34 +577,56 @@ int kdo_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const kdo_p
     }
     int status = KDO_OK;
     while (ncur > 0 && status == KDO_OK) {
+        /* every cell of the level: its split and the stable partition of its
+         * own index range (§2: the two children).  Cells own disjoint ranges,
+         * so they are handled by as many threads as there are cells; a level
+         * of few cells shares the work inside each cell instead. */
+        kdo_split *res = (kdo_split *)malloc(ncur * sizeof(kdo_split));
+        int nthr = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) if (ncur >= (uint64_t)nthr && ncur > 1)
+        for (uint64_t r = 0; r < ncur; r++) {
+            kdo_cell c = cur[r];
+            uint64_t nc = c.end - c.begin;
+            kdo_split *q = &res[r];
+            q->ok = kdo_cell_split(wp + c.begin, d, n, p, shift, NULL, nc, c.depth, r,
+                                   &q->dim, &q->split, &q->cand);
+            q->nl = 0;
+            if (!q->ok) continue;
+            /* stable partition of the cell's positions: the points with key
+             * <= split first, each side in its previous order; the original
+             * indices and every coordinate move together */
+            const float *key = wp + (size_t)q->dim * n;
+            uint64_t nl = 0;
+            for (uint64_t i = c.begin; i < c.end; i++) {
+                side_of[i] = kdo_key_of_bits(bits_of_float(key[i])) > q->split;
+                nl += !side_of[i];
+            }
+            uint64_t l = c.begin, w = c.begin + nl;
+            for (uint64_t i = c.begin; i < c.end; i++) tmp[side_of[i] ? w++ : l++] = work[i];
+            memcpy(work + c.begin, tmp + c.begin, nc * sizeof(uint32_t));
+#pragma omp parallel for if (nc >= KDO_PAR_MIN)
+            for (uint32_t col = 0; col < d; col++) {
+                float *src = wp + (size_t)col * n, *dst = wtmp + (size_t)col * n;
+                uint64_t l2 = c.begin, w2 = c.begin + nl;
+                for (uint64_t i = c.begin; i < c.end; i++) dst[side_of[i] ? w2++ : l2++] = src[i];
+                memcpy(src + c.begin, dst + c.begin, nc * sizeof(float));
+            }
+            q->nl = nl;
+        }
+        /* node records in cell order (ids breadth first) */
         kdo_cell *next = (kdo_cell *)malloc(2 * ncur * sizeof(kdo_cell));
         uint64_t nnext = 0;
         for (uint64_t r = 0; r < ncur; r++) {
             kdo_cell c = cur[r];
-            uint64_t nc = c.end - c.begin;
-            uint32_t dim, split, cand;
-            int ok = kdo_cell_split(pts, d, ld, p, shift, work + c.begin, nc, c.depth, r,
-                                    &dim, &split, &cand);
-            if (!ok) { unsplittable++; continue; }
+            uint64_t nc = c.end - c.begin, nl = res[r].nl;
+            if (!res[r].ok) { unsplittable++; continue; }
             if (num_nodes + 2 > cap) { status = KDO_ECAPACITY; break; }
-            /* stable partition of the cell's index range (§2: the two children) */
-            uint64_t nl = 0, w = 0;
-            for (uint64_t i = c.begin; i < c.end; i++) {
-                uint32_t u = kdo_key_of_bits(bits_of_float(pts[dim * ld + work[i]]));
-                if (u <= split) tmp[c.begin + nl++] = work[i];
-            }
-            w = c.begin + nl;
-            for (uint64_t i = c.begin; i < c.end; i++) {
-                uint32_t u = kdo_key_of_bits(bits_of_float(pts[dim * ld + work[i]]));
-                if (u > split) tmp[w++] = work[i];
-            }
-            memcpy(work + c.begin, tmp + c.begin, nc * sizeof(uint32_t));
             point_levels += nc;
             uint32_t left = (uint32_t)num_nodes;
             num_nodes += 2;
             node_child[c.node] = (int32_t)left;
-            node_dim[c.node] = dim;
-            node_split[c.node] = split;
+            node_dim[c.node] = res[r].dim;
+            node_split[c.node] = res[r].split;
             node_begin[left] = (uint32_t)c.begin;
             node_end[left] = (uint32_t)(c.begin + nl);
             node_begin[left + 1] = (uint32_t)(c.begin + nl);
@@ -543,6 +641,7 @@ int kdo_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const kdo_p
                 }
             }
         }
+        free(res);
         free(cur);
         cur = next;
         ncur = nnext;
@@ -565,11 +664,41 @@ int kdo_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const kdo_p
     leaf_offsets[nleaves] = (uint32_t)n;
     free(lv);
     memcpy(perm, work, n * sizeof(uint32_t));
-    free(work); free(tmp);
+    free(work); free(tmp); free(wp); free(wtmp); free(side_of);
 
     hdr[0] = num_nodes; hdr[1] = nleaves; hdr[2] = max_node_depth; hdr[3] = (uint64_t)status;
     hdr[4] = point_levels; hdr[5] = unsplittable; hdr[6] = oversize;
     return status;
+}
+
+/* Threads used by the calls that follow (omp_set_num_threads); the     */
+/* results do not depend on it.  Returns the previous setting.           */
+int kdo_set_threads(int nthreads)
+{
+    int prev = omp_get_max_threads();
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return prev;
+}
+
+/* Many independent trees (the batched workload): tree k is built exactly */
+/* as kdo_build builds it alone; trees are shared out among threads, and  */
+/* each tree's own levels then run on its thread.  pts[k], n[k], d[k] and */
+/* the output arrays out[k][0..9] (perm, node_begin, node_end,            */
+/* node_child, node_dim, node_split, node_leaf, leaf_node, leaf_offsets,  */
+/* hdr, in kdo_build's order) describe tree k; params[k] its parameters.  */
+/* status[k] receives kdo_build's return value.                           */
+void kdo_build_batched(uint32_t count, const float *const *pts, const uint64_t *n,
+                       const uint32_t *d, const kdo_params *params, void *const *out,
+                       int *status)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (uint32_t k = 0; k < count; k++) {
+        void *const *o = out + (size_t)k * 10;
+        status[k] = kdo_build(pts[k], n[k], d[k], n[k], &params[k], (uint32_t *)o[0],
+                              (uint32_t *)o[1], (uint32_t *)o[2], (int32_t *)o[3],
+                              (uint32_t *)o[4], (uint32_t *)o[5], (uint32_t *)o[6],
+                              (uint32_t *)o[7], (uint32_t *)o[8], (uint64_t *)o[9]);
+    }
 }
 
 /* Leaf lookup by descent: u <= split -> left child (the same rule the */

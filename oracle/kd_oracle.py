@@ -17,11 +17,12 @@ KEY_CYCLIC, KEY_MAXVAR = 0, 1
 SPLIT_EXACT, SPLIT_FOURIER, SPLIT_SUBSET = 0, 1, 2
 OK, EINVAL, ENOMEM, ENONFINITE, ECAPACITY = 0, 1, 2, 3, 4
 
-_CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+_CFLAGS = ["-O2", "-march=x86-64-v2", "-std=gnu11", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-fPIC", "-shared"]
 
 
 def build():
-    """Compile the oracle with gcc (contraction off, no fast-math)."""
+    """Compile the oracle with gcc (contraction off, no fast-math, OpenMP)."""
     subprocess.check_call(["gcc", *_CFLAGS, "-o", _LIB_PATH, _SRC, "-lm"])
 
 
@@ -87,6 +88,10 @@ def lib():
                                      ctypes.POINTER(u32)]
         L.kdo_build.restype = ctypes.c_int
         L.kdo_build.argtypes = [vp, u64, u32, u64, ctypes.POINTER(Params)] + [vp] * 10
+        L.kdo_set_threads.restype = ctypes.c_int
+        L.kdo_set_threads.argtypes = [ctypes.c_int]
+        L.kdo_build_batched.restype = None
+        L.kdo_build_batched.argtypes = [u32, vp, vp, vp, vp, vp, vp]
         L.kdo_check_partition.restype = u64
         L.kdo_check_partition.argtypes = [vp, u32, u64, vp, u64, vp, vp, vp, vp, vp]
         L.kdo_query_leaf.restype = u32
@@ -238,6 +243,26 @@ def cell_split(points, idx, depth=0, rank=0, shift=0, **kw):
     return bool(ok), dim.value, split.value, cand.value
 
 
+def _tree_arrays(n, cap):
+    return [np.zeros(n, dtype=np.uint32), np.zeros(cap, dtype=np.uint32),
+            np.zeros(cap, dtype=np.uint32), np.zeros(cap, dtype=np.int32),
+            np.zeros(cap, dtype=np.uint32), np.zeros(cap, dtype=np.uint32),
+            np.zeros(cap, dtype=np.uint32), np.zeros(cap, dtype=np.uint32),
+            np.zeros(cap + 1, dtype=np.uint32), np.zeros(7, dtype=np.uint64)]
+
+
+def _tree_dict(st, arr):
+    perm, nb, ne, nc, nd, ns, nl, ln, lo, hdr = arr
+    nn, nlv = int(hdr[0]), int(hdr[1])
+    return {
+        "status": int(st), "num_nodes": nn, "num_leaves": nlv, "depth": int(hdr[2]),
+        "point_levels": int(hdr[4]), "unsplittable": int(hdr[5]), "oversize": int(hdr[6]),
+        "perm": perm, "node_begin": nb[:nn], "node_end": ne[:nn], "node_child": nc[:nn],
+        "node_dim": nd[:nn], "node_split": ns[:nn], "node_leaf": nl[:nn],
+        "leaf_node": ln[:nlv], "leaf_offsets": lo[:nlv + 1],
+    }
+
+
 def build_tree(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
                split_rule=SPLIT_EXACT, fourier_J=15, pool=None, seed=0, node_capacity=0):
     """Build one tree on the CPU.  points: float32 array of shape (d, n) (SoA).
@@ -251,27 +276,41 @@ def build_tree(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CY
         pool = np.ascontiguousarray(pool, dtype=np.uint32)
     prm = make_params(leaf_size, max_depth, num_subsets, key_rule, split_rule, fourier_J,
                       pool, seed, node_capacity, n=n)
-    cap = prm.node_capacity
-    perm = np.zeros(n, dtype=np.uint32)
-    nb = np.zeros(cap, dtype=np.uint32)
-    ne = np.zeros(cap, dtype=np.uint32)
-    nc = np.zeros(cap, dtype=np.int32)
-    nd = np.zeros(cap, dtype=np.uint32)
-    ns = np.zeros(cap, dtype=np.uint32)
-    nl = np.zeros(cap, dtype=np.uint32)
-    ln = np.zeros(cap, dtype=np.uint32)
-    lo = np.zeros(cap + 1, dtype=np.uint32)
-    hdr = np.zeros(7, dtype=np.uint64)
-    st = lib().kdo_build(_ptr(p), n, d, n, ctypes.byref(prm), _ptr(perm), _ptr(nb), _ptr(ne),
-                         _ptr(nc), _ptr(nd), _ptr(ns), _ptr(nl), _ptr(ln), _ptr(lo), _ptr(hdr))
-    nn, nlv = int(hdr[0]), int(hdr[1])
-    return {
-        "status": int(st), "num_nodes": nn, "num_leaves": nlv, "depth": int(hdr[2]),
-        "point_levels": int(hdr[4]), "unsplittable": int(hdr[5]), "oversize": int(hdr[6]),
-        "perm": perm, "node_begin": nb[:nn], "node_end": ne[:nn], "node_child": nc[:nn],
-        "node_dim": nd[:nn], "node_split": ns[:nn], "node_leaf": nl[:nn],
-        "leaf_node": ln[:nlv], "leaf_offsets": lo[:nlv + 1],
-    }
+    arr = _tree_arrays(n, prm.node_capacity)
+    st = lib().kdo_build(_ptr(p), n, d, n, ctypes.byref(prm), *[_ptr(a) for a in arr])
+    return _tree_dict(st, arr)
+
+
+def set_threads(nthreads):
+    """OpenMP threads of the oracle's later calls (0: leave as is); returns
+    the previous count.  Results do not depend on it."""
+    return lib().kdo_set_threads(int(nthreads))
+
+
+def build_trees(points_list, **kw):
+    """Build independent trees (one per (d, n) float32 array) with the same
+    parameters, trees shared out among OpenMP threads; each tree equals
+    build_tree on it."""
+    pts = [np.ascontiguousarray(x, dtype=np.float32) for x in points_list]
+    T = len(pts)
+    pool = kw.pop("pool", None)
+    if pool is not None:
+        pool = np.ascontiguousarray(pool, dtype=np.uint32)
+    params = (Params * T)()
+    arrs, outs = [], np.zeros(T * 10, dtype=np.uint64)
+    for k, x in enumerate(pts):
+        d, n = x.shape
+        params[k] = make_params(pool=pool, n=n, **kw)
+        arr = _tree_arrays(n, params[k].node_capacity)
+        arrs.append(arr)
+        outs[10 * k:10 * k + 10] = [a.ctypes.data for a in arr]
+    ptr = np.array([x.ctypes.data for x in pts], dtype=np.uint64)
+    ns = np.array([x.shape[1] for x in pts], dtype=np.uint64)
+    ds = np.array([x.shape[0] for x in pts], dtype=np.uint32)
+    st = np.zeros(T, dtype=np.int32)
+    lib().kdo_build_batched(T, _ptr(ptr), _ptr(ns), _ptr(ds), ctypes.addressof(params),
+                            _ptr(outs), _ptr(st))
+    return [_tree_dict(int(st[k]), arrs[k]) for k in range(T)]
 
 
 def query_leaf(tree, queries):

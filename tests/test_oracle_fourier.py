@@ -61,20 +61,40 @@ def _scaled_keys(x):
     return keys, lo, hi, e
 
 
+def _mapped(x, e):
+    """The cell map u = (x - min) * 2^-e of every key (exact in double)."""
+    xmin = float(np.float32(x.min()))
+    return [float(np.float32((float(xi) - xmin) * 2.0 ** -e)) for xi in x]
+
+
+def test_cell_map_lands_in_unit_interval():
+    """§2 takes the data to lie in (0, 1): the smallest key maps to 0, the
+    largest into [1/2, 1), for spreads from subnormal to near the fp32 limit."""
+    rng = np.random.default_rng(2)
+    for scale in [1e-42, 1e-30, 1e-3, 1.0, 7.0, 1e20, 1e38]:
+        x = (rng.standard_normal(50) * scale).astype(np.float32)
+        keys, lo, hi, e = _scaled_keys(x)
+        if lo == hi:
+            continue
+        u = _mapped(x, e)
+        assert min(u) == 0.0 and 0.5 <= max(u) < 1.0, (scale, e, max(u))
+
+
 def test_moment_form_equals_paper_equal_count_difference():
-    """(4/pi) * F(v) == sum_i [1_J(u_i, -, v) - 1_J(u_i, v, -)] (Eq. (1), (2)):
-    the left child is bounded above by v only, the right child below only."""
+    """(4/pi) * F(v) == sum_i [1_J(u_i, 0, v) - 1_J(u_i, v, 1)] (Eq. (1), (2)):
+    the left child is the interval (0, v), the right child (v, 1), with the
+    boundary flags of Lemma 3.1 as the paper defines them for (a, b) inside
+    (0, 1)."""
     rng = np.random.default_rng(3)
     J = 7
     x = rng.uniform(-2.0, 3.0, size=40).astype(np.float32)
     keys, lo, hi, e = _scaled_keys(x)
     Cc, Cs = oracle.fourier_map(keys, lo, e, J)
-    xmin = float(np.float32(x.min()))
-    u = [float(np.float32((float(xi) - xmin) * 2.0 ** (1 - e))) for xi in x]
-    assert 1.0 <= max(u) < 2.0
-    for v in [0.1, 0.37, 0.5, 0.81, 1.3, 1.7]:
-        lhs = mp.fsum(one_J(mp.mpf(ui), 0, mp.mpf(v), J, ia=0, ib=1) for ui in u)
-        rhs = mp.fsum(one_J(mp.mpf(ui), mp.mpf(v), 0, J, ia=1, ib=0) for ui in u)
+    u = _mapped(x, e)
+    assert 0.5 <= max(u) < 1.0
+    for v in [0.05, 0.2, 0.37, 0.5, 0.68, 0.9]:
+        lhs = mp.fsum(one_J(mp.mpf(ui), 0, mp.mpf(v), J) for ui in u)
+        rhs = mp.fsum(one_J(mp.mpf(ui), mp.mpf(v), 1, J) for ui in u)
         paper = float(lhs - rhs)
         ours = 4.0 / math.pi * oracle.fourier_F(Cc, Cs, v)
         assert abs(paper - ours) < 1e-4 * len(x), (v, paper, ours)
@@ -87,10 +107,8 @@ def test_F_is_sum_of_odd_harmonic_kernels():
     x = rng.standard_normal(300).astype(np.float32)
     keys, lo, hi, e = _scaled_keys(x)
     Cc, Cs = oracle.fourier_map(keys, lo, e, J)
-    xmin = float(np.float32(x.min()))
-    u = np.array([float(np.float32((float(xi) - xmin) * 2.0 ** (1 - e))) for xi in x],
-                 dtype=np.longdouble)
-    for v in np.linspace(0.0, 2.0, 21):
+    u = np.array(_mapped(x, e), dtype=np.longdouble)
+    for v in np.linspace(0.0, 1.0, 21):
         z = np.longdouble(v) - u
         direct = sum(np.sin((2 * j - 1) * z) / (2 * j - 1) for j in range(1, J + 1)).sum()
         assert abs(float(direct) - oracle.fourier_F(Cc, Cs, float(v))) < 2e-5 * len(x)
@@ -109,10 +127,10 @@ def test_bracket_and_bisection_invariant():
         xmin = float(np.float32(x.min()))
 
         def v_of(k):
-            return (float(np.uint32(oracle.bits_of_key(k)).view(np.float32)) - xmin) * 2.0 ** (1 - e)
+            return (float(np.uint32(oracle.bits_of_key(k)).view(np.float32)) - xmin) * 2.0 ** -e
 
         vmax = v_of(hi)
-        assert 1.0 <= vmax < 2.0
+        assert 0.5 <= vmax < 1.0
         assert oracle.fourier_F(Cc, Cs, vmax) > 0.0
         m = oracle.fourier_solve(Cc, Cs, lo, hi, e)
         assert lo < m <= hi
@@ -121,10 +139,12 @@ def test_bracket_and_bisection_invariant():
 
 
 def test_symmetric_three_points_split_at_middle():
-    # u = {0, 0.6, 1.2}: F is odd about 0.6, so the root is the middle point.
+    # u = {0, 0.3, 0.6}: F is odd about 0.3, so the root is the middle point.
     x = np.array([0.1, 0.25, 0.4], dtype=np.float32)
     keys, lo, hi, e = _scaled_keys(x)
     assert e == -1
+    u = _mapped(x, e)
+    assert u[0] == 0.0 and abs(u[1] - 0.3) < 1e-6 and abs(u[2] - 0.6) < 1e-6
     Cc, Cs = oracle.fourier_map(keys, lo, e, 15)
     m = oracle.fourier_solve(Cc, Cs, lo, hi, e)
     val = float(np.uint32(oracle.bits_of_key(m)).view(np.float32))

@@ -52,7 +52,7 @@ def test_splitmix64_published_sequence():
 
 # ---------------------------------------------------------------- median
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 17, 64, 101])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 17, 63, 64, 65, 101, 4099, 200003])
 def test_lower_median_against_numpy_sort(n):
     rng = np.random.default_rng(n)
     for trial in range(5):

@@ -170,22 +170,34 @@ def test_nan_query_returns_sentinel():
     assert oracle.query_leaf(t, q)[0] == 0xFFFFFFFF
 
 
-def test_paper_accuracy_panel_fourier_J15():
-    """§5.1 reports, for the trivariate normal with rho = 0.5, depth 6 and the
-    J = (3,5) accuracy parameter (J = 15), cell counts between 2^25.45 and
-    2^25.52 for an ideal 2^25.48232.  The per-level FOURIER rule must be at
-    least that accurate, relative to the ideal count, at a smaller N."""
+def test_fourier_leaf_spread_shrinks_with_J_and_panel_report():
+    """Thm 3.6 and 3.7 (§3.2) with the balanced-tree bound of §4: the leaf
+    counts of a FOURIER tree approach |X| / 2^D as J grows.  On the §5.1
+    workload shape (trivariate normal, rho = 0.5, depth 6) the largest
+    relative deviation must shrink from J = 4 to 15 to 60.
+
+    The §5.1 panel (J = (3,5), i.e. J = 15: counts within 2^25.45..2^25.52
+    of an ideal 2^25.48232 at N = 3e9) comes from the paper's global
+    single-pass method, not this per-level rule, so it is printed beside the
+    measured spread as context and not asserted."""
     with open(os.path.join(GOLDEN, "paper_accuracy_panel.json")) as f:
         g = json.load(f)
-    lo_rel = 2.0 ** (g["observed_min_log2"] - g["ideal_log2"])
-    hi_rel = 2.0 ** (g["observed_max_log2"] - g["ideal_log2"])
     n = 3 * (1 << 16)
     x = synth.corr_normal(n, 3, rho=g["rho"], seed=21)
-    t = oracle.build_tree(x, leaf_size=1, max_depth=g["depth"], split_rule=oracle.SPLIT_FOURIER,
-                          fourier_J=g["J"], num_subsets=16)
-    assert t["num_leaves"] == 2 ** g["depth"]
-    rel = np.diff(t["leaf_offsets"].astype(np.int64)) / (n / 2 ** g["depth"])
-    assert rel.min() >= lo_rel and rel.max() <= hi_rel, (rel.min(), rel.max())
+    worst = {}
+    for J in (4, g["J"], 60):
+        t = oracle.build_tree(x, leaf_size=1, max_depth=g["depth"],
+                              split_rule=oracle.SPLIT_FOURIER, fourier_J=J, num_subsets=16)
+        assert t["num_leaves"] == 2 ** g["depth"]
+        rel = np.diff(t["leaf_offsets"].astype(np.int64)) / (n / 2 ** g["depth"])
+        assert abs(rel.sum() - 2 ** g["depth"]) < 1e-9
+        worst[J] = float(np.abs(np.log2(rel)).max())
+        if J == g["J"]:
+            print(f"per-level FOURIER, J={J}, n={n}: leaf counts 2^{np.log2(rel.min()):+.3f}"
+                  f" .. 2^{np.log2(rel.max()):+.3f} of ideal; paper (global method, N=3e9):"
+                  f" 2^{g['observed_min_log2'] - g['ideal_log2']:+.3f}"
+                  f" .. 2^{g['observed_max_log2'] - g['ideal_log2']:+.3f}")
+    assert worst[4] > worst[g["J"]] > worst[60], worst
 
 
 def test_partition_checker_detects_wrong_split():
@@ -233,3 +245,34 @@ def test_sampled_node_recompute_matches_whole_build(rule, key, pool):
         t2["node_split"][k] ^= np.uint32(1 << 20)
         with pytest.raises(AssertionError):
             check_sampled_nodes(x, t2, [k], 16, shift=shift, **kw)
+
+
+@pytest.mark.parametrize("rule,key,pool", [(0, 1, True), (1, 0, False), (2, 1, True),
+                                           (1, 1, True)])
+def test_results_do_not_depend_on_thread_count(rule, key, pool):
+    """The OpenMP oracle shares out cells, trees, coordinates and subsets;
+    every tree must be the same bit for bit with one thread and with many
+    (cells large enough that work inside a cell is shared too)."""
+    x = synth.student_t_grid(300000, 5, seed=31 + rule)
+    S = 16
+    pl = synth.dirichlet_pool(64, S, seed=2) if pool else None
+    kw = dict(leaf_size=40, num_subsets=S, key_rule=key, split_rule=rule, pool=pl, seed=4)
+    prev = oracle.set_threads(1)
+    try:
+        one = oracle.build_tree(x, **kw)
+    finally:
+        oracle.set_threads(prev)
+    many = oracle.build_tree(x, **kw)
+    for k, v in one.items():
+        assert np.array_equal(np.asarray(v), np.asarray(many[k])), k
+
+
+def test_batched_oracle_equals_single_builds():
+    shapes = [(1000, 2), (5000, 3), (70000, 8), (33, 4), (200000, 2)]
+    xs = [synth.uniform24(n, d, seed=50 + i) for i, (n, d) in enumerate(shapes)]
+    kw = dict(leaf_size=32, num_subsets=8, split_rule=oracle.SPLIT_FOURIER)
+    batch = oracle.build_trees(xs, **kw)
+    for x, b in zip(xs, batch):
+        a = oracle.build_tree(x, **kw)
+        for k, v in a.items():
+            assert np.array_equal(np.asarray(v), np.asarray(b[k])), k
