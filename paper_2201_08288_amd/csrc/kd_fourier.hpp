@@ -1,9 +1,12 @@
 // kd_fourier.hpp -- the paper's approximate median on one cell's key (§3.1
 // Lemma 3.1, §3.2 Eq. (1)-(2), p = 1), device side.
 //
-// Map step (App. C.2): each point's key is mapped onto [0, 2) by
-// u = (x - min) * 2^(1-e), 2^(e-1) <= max - min < 2^e, so every difference of
-// two mapped values lies in (-2, 2) where the expansion of 1(x < c) holds.
+// Map step (App. C.2): §2 takes every observation to lie in (0, 1), and
+// Lemma 3.1 states c_j and g_j there.  Each cell maps its key into that unit
+// interval by u = (x - min) * 2^-e, 2^(e-1) <= max - min < 2^e, a power of
+// two so the map is exact in fp64: the smallest key lands on 0 and the
+// largest in [1/2, 1).  The cell itself is the whole interval (a = 0, b = 1),
+// so the boundary terms 1(a > 0), 1(b < 1) of Lemma 3.1 vanish.
 // In fp32: sin u, cos u by Taylor series (Horner in u^2), then the odd
 // harmonics cos((2j-1)u), sin((2j-1)u) by the angle-addition recurrence with
 // the double angle; each term is quantized as rint(t * 2^24) and summed in
@@ -81,9 +84,9 @@ __device__ __forceinline__ int fourier_exponent(uint32_t lo, uint32_t hi) {
     return int((b >> 52) & 0x7ff) - 1022;
 }
 
-// Scale 2^(1-e) as an exact double.
+// Scale 2^-e as an exact double (e is within [-148, 129] for fp32 keys).
 __device__ __forceinline__ double fourier_scale(int e) {
-    return __longlong_as_double((long long)(uint64_t(1023 + 1 - e) << 52));
+    return __longlong_as_double((long long)(uint64_t(1023 - e) << 52));
 }
 
 // Accumulate the quantized harmonics j0 .. j0+FCHUNK-1 of one key into
