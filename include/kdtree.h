@@ -22,11 +22,14 @@
  *     pattern to uint32 (-0 folded onto +0).  Split values are stored in that
  *     key domain; descent is "key(x[dim]) <= split -> left child".
  *   - `stream` is a hipStream_t (NULL = the null stream).
- *   - A KD_E* return value means nothing was enqueued (bad arguments, a
- *     launch failure).  Data-dependent errors (non-finite input, node
- *     capacity) are written to hdr->status on the device.
+ *   - KD_EINVAL and KD_ENOMEM mean nothing was enqueued.  KD_EDEVICE means
+ *     a HIP call or launch failed part-way: work enqueued before the failure
+ *     may still run, so synchronize the stream before reusing the buffers.
+ *     Data-dependent errors (non-finite input, node capacity) are written to
+ *     hdr->status on the device.
  *   - Calls on distinct streams with distinct workspaces may run
- *     concurrently; the library has no mutable global state.
+ *     concurrently.  The library's only mutable global state is the
+ *     process-wide launch-shape setting (kd_set_tuning, kd_autotune).
  */
 #ifndef KDTREE_H
 #define KDTREE_H
@@ -108,6 +111,9 @@ typedef struct kd_tree {
     kd_header *hdr;            /* [1]                                              */
     float *points_out;         /* optional [d][n] points in perm order, or NULL    */
     uint64_t node_capacity;    /* entries in the node arrays                        */
+    uint64_t n;                /* points of the tree, and their dimension: kd_build */
+    uint32_t d;                /* writes both; kd_build_batched callers fill them   */
+    uint32_t reserved;         /* in (0 or the item's n and d); queries check them  */
 } kd_tree;
 
 /* Sizes to allocate for a build of n points in d dimensions (host only, no
@@ -178,15 +184,17 @@ kd_status kd_build_batched(uint32_t count, const kd_batch_item *items, const kd_
                            void *workspace, uint64_t ws_bytes, void *stream);
 
 /* Leaf of each query point by descent from the root (§2's cells).  q: device
- * [d][ldq] fp32; leaf_out: device [nq].  NaN query -> 0xFFFFFFFF.         */
+ * [d][ldq] fp32; leaf_out: device [nq].  NaN query -> 0xFFFFFFFF.  d must
+ * be the tree's dimension (tree->d), else KD_EINVAL and nothing enqueued.   */
 kd_status kd_query_leaf(const kd_tree *tree, const float *q, uint64_t nq, uint32_t d,
                         uint64_t ldq, uint32_t *leaf_out, void *stream);
 
 /* Queries that use a built tree (§1, §2: the cells of the tree answer
  * nearest-neighbour and range questions).  Both need the tree's points in
  * position order (tree->points_out, built with points_out set) and n, the
- * tree's point count.  Stream-ordered; KD_EINVAL for a missing array, d == 0
- * or a bad size, and no work is enqueued then.
+ * tree's point count.  Stream-ordered; KD_EINVAL for a missing array, an n
+ * or d other than the tree's (tree->n, tree->d) or a bad size, and no work
+ * is enqueued then.
  *
  * kd_query_knn: the k nearest points (1 <= k <= 64) of each query q (device
  * [d][ldq] fp32, nq queries) by squared Euclidean distance, computed in fp64

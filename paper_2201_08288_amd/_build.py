@@ -25,20 +25,37 @@ def sources():
         os.path.join(INCLUDE, "kdtree.h")]
 
 
+HASH = LIB + ".srchash"  # hash of the sources the library was built from
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in sources():
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose=False):
     cmd = ["/opt/rocm/bin/hipcc", *HIPCC_FLAGS, "-I", INCLUDE, "-o", LIB + ".tmp", SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
+    digest = source_hash()
     subprocess.check_call(cmd)
     os.replace(LIB + ".tmp", LIB)
+    with open(HASH, "w") as fh:
+        fh.write(digest + "\n")
     return LIB
 
 
 def stale():
-    if not os.path.exists(LIB):
+    """True when the library is missing or was built from other sources."""
+    if not os.path.exists(LIB) or not os.path.exists(HASH):
         return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(s) > t for s in sources())
+    with open(HASH) as fh:
+        return fh.read().strip() != source_hash()
 
 
 if __name__ == "__main__":

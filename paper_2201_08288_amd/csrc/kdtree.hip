@@ -3321,6 +3321,8 @@ kd_status kd_build_profiled(const float *pts, uint64_t n, uint32_t d, uint64_t l
                             void *stream, kd_profile *prof) {
     if (!params_ok(p) || !shape_ok(n, d) || !pts || ld < n || !workspace || !tree_ok(out))
         return KD_EINVAL;
+    out->n = n;
+    out->d = d;
     const HostTree ht{pts, n, ld, d, out};
     return run_build(1, &ht, p, workspace, ws_bytes, reinterpret_cast<hipStream_t>(stream), prof,
                      current_tuning());
@@ -3333,8 +3335,8 @@ kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const 
 
 kd_status kd_query_leaf(const kd_tree *tree, const float *q, uint64_t nq, uint32_t d,
                         uint64_t ldq, uint32_t *leaf_out, void *stream) {
-    if (!tree || !q || !leaf_out || d == 0 || ldq < nq || !tree->node_child || !tree->node_dim ||
-        !tree->node_split || !tree->node_leaf)
+    if (!tree || !q || !leaf_out || d == 0 || d != tree->d || ldq < nq || !tree->node_child ||
+        !tree->node_dim || !tree->node_split || !tree->node_leaf)
         return KD_EINVAL;
     if (nq == 0) return KD_OK;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -3353,8 +3355,8 @@ static bool query_tree_ok(const kd_tree *t) {
 kd_status kd_query_knn(const kd_tree *tree, uint64_t n, const float *q, uint64_t nq, uint32_t d,
                        uint64_t ldq, uint32_t k, uint32_t *idx_out, double *dist_out,
                        void *stream) {
-    if (!query_tree_ok(tree) || n == 0 || !q || !idx_out || !dist_out || d == 0 || ldq < nq ||
-        k == 0 || k > KNN_MAX)
+    if (!query_tree_ok(tree) || n == 0 || n != tree->n || !q || !idx_out || !dist_out || d == 0 ||
+        d != tree->d || ldq < nq || k == 0 || k > KNN_MAX)
         return KD_EINVAL;
     if (nq == 0) return KD_OK;
     hipLaunchKernelGGL(k_knn, dim3(grid_for((nq + NW - 1) / NW, 65535)), dim3(NT), 0,
@@ -3368,8 +3370,8 @@ kd_status kd_query_knn(const kd_tree *tree, uint64_t n, const float *q, uint64_t
 kd_status kd_query_box(const kd_tree *tree, uint64_t n, const float *lo, const float *hi,
                        uint64_t nb, uint32_t d, uint64_t ldb, uint32_t *count_out,
                        const uint64_t *offsets, uint32_t *ids_out, void *stream) {
-    if (!query_tree_ok(tree) || n == 0 || !lo || !hi || !count_out || d == 0 || ldb < nb ||
-        (ids_out && !offsets))
+    if (!query_tree_ok(tree) || n == 0 || n != tree->n || !lo || !hi || !count_out || d == 0 ||
+        d != tree->d || ldb < nb || (ids_out && !offsets))
         return KD_EINVAL;
     if (nb == 0) return KD_OK;
     hipLaunchKernelGGL(k_box, dim3(grid_for(nb / NT + 1, 65535)), dim3(NT), 0,
@@ -3469,7 +3471,8 @@ kd_status kd_build_batched(uint32_t count, const kd_batch_item *items, const kd_
     std::vector<HostTree> ht(count);
     for (uint32_t t = 0; t < count; t++) {
         const kd_batch_item &it = items[t];
-        if (!shape_ok(it.n, it.d) || !it.pts || it.ld < it.n || !tree_ok(&it.out))
+        if (!shape_ok(it.n, it.d) || !it.pts || it.ld < it.n || !tree_ok(&it.out) ||
+            (it.out.n != 0 && it.out.n != it.n) || (it.out.d != 0 && it.out.d != it.d))
             return KD_EINVAL;
         ht[t] = HostTree{it.pts, it.n, it.ld, it.d, &it.out};
     }

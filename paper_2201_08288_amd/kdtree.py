@@ -31,7 +31,8 @@ class TreeStruct(ctypes.Structure):
     _fields_ = [("perm", _vp), ("node_begin", _vp), ("node_end", _vp), ("node_child", _vp),
                 ("node_dim", _vp), ("node_split", _vp), ("node_split_f", _vp),
                 ("node_leaf", _vp), ("leaf_node", _vp), ("leaf_offsets", _vp), ("hdr", _vp),
-                ("points_out", _vp), ("node_capacity", _u64)]
+                ("points_out", _vp), ("node_capacity", _u64), ("n", _u64), ("d", _u32),
+                ("reserved", _u32)]
 
 
 PROF_KINDS = ("ingest", "select", "pick", "count", "big_scatter", "small", "emit", "other")
@@ -70,10 +71,11 @@ _lib = None
 
 
 def lib():
-    """Load libkdtree.so (building it first only if it does not exist)."""
+    """Load libkdtree.so, building it first when it is missing or was built
+    from other sources than the ones beside it."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        if _build.stale():
             _build.build()
         L = ctypes.CDLL(_build.LIB)
         st = ctypes.c_int32
@@ -184,6 +186,8 @@ class KDTree:
         self.struct.hdr = self.hdr.data_ptr()
         self.struct.points_out = self.points_out.data_ptr() if points_out else None
         self.struct.node_capacity = cap
+        self.struct.n = n
+        self.struct.d = d
 
     def header(self):
         h = self.hdr.cpu().numpy()
@@ -229,12 +233,14 @@ def build(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
     ld = points.stride(0) if d > 1 else n
     prm = make_params(leaf_size, max_depth, num_subsets, key_rule, split_rule, fourier_J,
                       subset_pool, seed, node_capacity)
-    cap, ws = tree_bounds(n, d, prm)
-    prm.node_capacity = cap
-    if workspace is None or workspace.numel() < ws:
-        workspace = torch.empty(ws, dtype=torch.uint8, device=points.device)
+    cap, _ = tree_bounds(n, d, prm)
     if tree is None or tree.cap < cap or tree.n != n or tree.d != d:
         tree = KDTree(n, d, cap, points.device, points_out)
+    # the build may use all of a reused tree's node arrays: size the workspace for them
+    prm.node_capacity = tree.cap
+    _, ws = tree_bounds(n, d, prm)
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(ws, dtype=torch.uint8, device=points.device)
     if profile is None:
         st = lib().kd_build(points.data_ptr(), n, d, ld, ctypes.byref(prm),
                             ctypes.byref(tree.struct), workspace.data_ptr(), workspace.numel(),
@@ -252,10 +258,11 @@ def build(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
 
 def build_batched(points_list, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
                   split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0,
-                  points_out=True, workspace=None, stream=None):
-    """kd_build_batched over a list of (d_t, n_t) float32 CUDA tensors."""
+                  node_capacity=0, points_out=True, workspace=None, stream=None):
+    """kd_build_batched over a list of (d_t, n_t) float32 CUDA tensors
+    (node_capacity: node-array entries of every tree, 0 = the default)."""
     prm = make_params(leaf_size, max_depth, num_subsets, key_rule, split_rule, fourier_J,
-                      subset_pool, seed, 0)
+                      subset_pool, seed, node_capacity)
     T = len(points_list)
     items = (BatchItem * T)()
     trees = []
@@ -285,6 +292,7 @@ def query_leaf(tree, queries, stream=None):
     """kd_query_leaf: leaf index (int32 storage of uint32) of each query column."""
     assert queries.is_cuda and queries.dtype == torch.float32 and queries.stride(1) == 1
     d, nq = queries.shape
+    assert d == tree.d, f"queries have {d} coordinates, the tree {tree.d}"
     out = torch.empty(nq, dtype=torch.int32, device=queries.device)
     ldq = queries.stride(0) if d > 1 else nq
     _check(lib().kd_query_leaf(ctypes.byref(tree.struct), queries.data_ptr(), nq, d, ldq,
@@ -303,6 +311,7 @@ def query_knn(tree, queries, k, stream=None):
     float64 [nq, k]) of the k nearest tree points of each query column.  The
     tree must have been built with points_out."""
     d, nq, ldq = _query_cols(queries)
+    assert d == tree.d, f"queries have {d} coordinates, the tree {tree.d}"
     idx = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
     dist = torch.empty((nq, k), dtype=torch.float64, device=queries.device)
     _check(lib().kd_query_knn(ctypes.byref(tree.struct), tree.n, queries.data_ptr(), nq, d, ldq,
@@ -316,6 +325,7 @@ def query_box(tree, lo, hi, ids=False, stream=None):
     two [d, nb] tensors).  Returns counts (int32 [nb]); with ids=True also
     (offsets int64 [nb], original indices int32 [total]) from a second call."""
     d, nb, ldb = _query_cols(lo)
+    assert d == tree.d, f"boxes have {d} coordinates, the tree {tree.d}"
     assert hi.shape == lo.shape and hi.stride() == lo.stride()
     cnt = torch.empty(nb, dtype=torch.int32, device=lo.device)
     L = lib()
