@@ -68,7 +68,10 @@ enum { KD_SPLIT_EXACT = 0, KD_SPLIT_FOURIER = 1, KD_SPLIT_SUBSET = 2 };
 
 typedef struct kd_params {
     uint32_t leaf_size;        /* cells with > leaf_size points are split (>= 1)   */
-    uint32_t max_depth;        /* cells at this depth stay leaves (0 -> 64)         */
+    uint32_t max_depth;        /* cells at this depth stay leaves; 0 -> h + 10, at
+                                * most 64, with h the depth of a balanced tree
+                                * (leaf_size * 2^h >= n); kd_build enqueues
+                                * that many levels                               */
     uint32_t num_subsets;      /* S: subsets per cell (1..4096)                     */
     uint32_t key_rule;         /* KD_KEY_*                                          */
     uint32_t split_rule;       /* KD_SPLIT_*                                        */
@@ -124,8 +127,12 @@ kd_status kd_tree_bounds(uint64_t n, uint32_t d, const kd_params *params,
 
 /* Build one tree (§4).  pts: device [d][ld] fp32, read only.  out: device
  * arrays of capacity out->node_capacity.  workspace: device, ws_bytes >=
- * kd_tree_bounds().  Enqueued on `stream`; the call returns when the tree is
- * complete on the device (it reads each level's cell count back).          */
+ * kd_tree_bounds().  Stream-ordered: every level up to the depth cap is
+ * enqueued on `stream` and the call returns without waiting for the device
+ * (it blocks only if the stream's hardware queue is full); levels the tree
+ * does not reach exit at once on the device.  Nothing on the host is read by
+ * the device after the call returns, so the call can be captured in a graph.
+ * Read the header and arrays after the stream has completed.               */
 kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
                    const kd_params *params, kd_tree *out, void *workspace,
                    uint64_t ws_bytes, void *stream);
@@ -159,7 +166,9 @@ typedef struct kd_profile {
 } kd_profile;
 
 /* kd_build with per-kernel timing written to *prof (host struct, zeroed by
- * the call).  Same results as kd_build; for measurement only.            */
+ * the call).  Same results as kd_build; for measurement only: it waits for
+ * every level's totals so launch shapes and byte counts are exact, and
+ * returns when the tree is complete.                                     */
 kd_status kd_build_profiled(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
                             const kd_params *params, kd_tree *out, void *workspace,
                             uint64_t ws_bytes, void *stream, kd_profile *prof);
@@ -179,7 +188,8 @@ kd_status kd_batch_bounds(uint32_t count, const kd_batch_item *items, const kd_p
                           uint64_t *workspace_bytes);
 
 /* Build `count` independent trees with one set of level launches over the
- * union of their cells.  Every tree is bit-identical to kd_build on it.    */
+ * union of their cells.  Every tree is bit-identical to kd_build on it
+ * (each tree keeps its own depth cap).  Stream-ordered like kd_build.      */
 kd_status kd_build_batched(uint32_t count, const kd_batch_item *items, const kd_params *params,
                            void *workspace, uint64_t ws_bytes, void *stream);
 

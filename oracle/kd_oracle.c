@@ -55,7 +55,7 @@
 
 typedef struct kdo_params {
     uint32_t leaf_size;     /* cells with more than leaf_size points are split  */
-    uint32_t max_depth;     /* cells at this depth are not split (0 -> 64)      */
+    uint32_t max_depth;     /* cells at this depth are not split (0 -> default) */
     uint32_t num_subsets;   /* S: subsets per cell (>= 1)                        */
     uint32_t key_rule;      /* KDO_KEY_*                                         */
     uint32_t split_rule;    /* KDO_SPLIT_*                                       */
@@ -548,7 +548,11 @@ int kdo_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const kdo_p
     }
     if (nonfinite) { hdr[3] = KDO_ENONFINITE; return KDO_ENONFINITE; }
 
-    uint32_t max_depth = p->max_depth ? p->max_depth : 64;
+    /* the default cap: ten levels beyond the depth h of a balanced tree with
+     * leaves of at most leaf_size points (leaf_size * 2^h >= n), at most 64 */
+    uint32_t h = 0;
+    while (h < 40 && ((uint64_t)p->leaf_size << h) < n) h++;
+    uint32_t max_depth = p->max_depth ? p->max_depth : (h + 10 < 64 ? h + 10 : 64);
     uint64_t cap = p->node_capacity;
     int shift = p->key_rule == KDO_KEY_MAXVAR ? kdo_maxvar_shift(pts, n, d, ld) : 0;
 

@@ -101,6 +101,8 @@ struct TreeDesc {
     uint64_t pbase;       // first bit of the tree's positions in the build's leaf-start bitmap
     uint64_t cap;
     uint32_t n, d;
+    uint32_t max_depth;   // cells at this depth stay leaves
+    uint32_t pad;
 };
 
 // Mutable per-tree counters of the level loop (device memory).

@@ -83,7 +83,7 @@ struct Ctx {
     const uint32_t *pool;
     uint32_t pool_entries;
     unsigned long long seed;
-    uint32_t leaf_size, max_depth, key_rule, split_rule, J, S;
+    uint32_t leaf_size, key_rule, split_rule, J, S;
     TrigTables trig;
 };
 
@@ -188,7 +188,8 @@ __global__ __launch_bounds__(NT) void k_roots(Ctx c) {
         uint32_t n = 0;
         if (t < c.ntrees) {
             n = c.trees[t].n;
-            const bool active = c.ts[t].status == KD_OK && n > c.leaf_size && c.max_depth > 0;
+            const bool active =
+                c.ts[t].status == KD_OK && n > c.leaf_size && c.trees[t].max_depth > 0;
             if (active) {
                 const bool big = n > uint32_t(SMALL_MAX);
                 v[0] = 1;
@@ -360,14 +361,15 @@ __global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level, uint32
 }
 
 // Tie rule and leaf flags once the candidate and its counts are known.
-__device__ __forceinline__ void finish_cell(const Ctx &c, uint32_t level, uint32_t n_c, CellRes &r,
-                                            uint32_t m, uint32_t lt, uint32_t le) {
+__device__ __forceinline__ void finish_cell(const Ctx &c, uint32_t level, uint32_t max_depth,
+                                            uint32_t n_c, CellRes &r, uint32_t m, uint32_t lt,
+                                            uint32_t le) {
     uint32_t split, nl;
     r.cand = m;
     if (tie_rule(n_c, lt, le, m, &split, &nl)) {
         r.split = split;
         r.nl = nl;
-        const bool deep = level + 1 >= c.max_depth;
+        const bool deep = level + 1 >= max_depth;
         r.flags = RES_SPLIT | ((nl <= c.leaf_size || deep) ? RES_LEFT_LEAF : 0u) |
                   ((n_c - nl <= c.leaf_size || deep) ? RES_RIGHT_LEAF : 0u);
     } else {
@@ -957,7 +959,7 @@ __global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level) {
                 le += te;
             }
         }
-        finish_cell(c, level, n_c, r, r.cand, lt, le);
+        finish_cell(c, level, c.trees[cl.tree].max_depth, n_c, r, r.cand, lt, le);
         const bool use_le = (r.flags & RES_SPLIT) && r.split == r.cand;
         const uint32_t li = ci - c.ts[cl.tree].first[cur];
         uint32_t base = 0;
@@ -1254,7 +1256,7 @@ __device__ __forceinline__ void store_cell(const Ctx &c, uint32_t level, ChunkLd
     CellRes r{};
     r.dim = C.dim[k];
     r.rank = (n_c - 1) / 2;
-    finish_cell(c, level, n_c, r, m, lt, le);
+    finish_cell(c, level, c.trees[C.tree].max_depth, n_c, r, m, lt, le);
     r.lt = lt;
     r.le = le;
     c.res[C.ci[k]] = r;
@@ -1802,10 +1804,11 @@ template <bool MAXVAR>
 constexpr int subtree_cells() { return MAXVAR ? 120 : 64; }
 
 template <int SC, int CH>
-__device__ __forceinline__ void sub_result(const Ctx &c, uint32_t depth, SubTable<SC, CH> &A,
-                                           uint32_t q, uint32_t m, uint32_t lt, uint32_t le) {
+__device__ __forceinline__ void sub_result(const Ctx &c, uint32_t depth, uint32_t max_depth,
+                                           SubTable<SC, CH> &A, uint32_t q, uint32_t m,
+                                           uint32_t lt, uint32_t le) {
     CellRes r{};
-    finish_cell(c, depth, A.end[q] - A.start[q], r, m, lt, le);
+    finish_cell(c, depth, max_depth, A.end[q] - A.start[q], r, m, lt, le);
     A.split[q] = r.split;
     A.nl[q] = r.nl;
     A.flags[q] = r.flags;
@@ -1820,7 +1823,7 @@ __device__ __forceinline__ void sub_result(const Ctx &c, uint32_t depth, SubTabl
 // mean is one thread per sub-cell in subset order; then the counts around the
 // candidate and the tie rule, one wave per sub-cell.
 template <int SC, int CH>
-__device__ void subtree_subset(const Ctx &c, uint32_t depth, const uint32_t *keys,
+__device__ void subtree_subset(const Ctx &c, uint32_t depth, uint32_t max_depth, const uint32_t *keys,
                                const uint8_t *seg, SubTable<SC, CH> &A, uint32_t *dyn,
                                uint32_t dyn_words, uint32_t (*h)[NBINS]) {
     const uint32_t S = c.S, stride = 2 * S + 1, nq = A.count;
@@ -1892,7 +1895,7 @@ __device__ void subtree_subset(const Ctx &c, uint32_t depth, const uint32_t *key
             }
             a = uint32_t(wave_sum64(a));
             b = uint32_t(wave_sum64(b));
-            if (l == 0) sub_result(c, depth, A, q, m, a, b);
+            if (l == 0) sub_result(c, depth, max_depth, A, q, m, a, b);
         }
         __syncthreads();
     }
@@ -1997,21 +2000,21 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                 // split of every active sub-cell: wide ones by the workgroup,
                 // the others one per wave (SUBSET: all of them in groups)
                 if constexpr (RULE == KD_SPLIT_SUBSET) {
-                    subtree_subset(c, depth, keys, seg, A, dyn_lds, dyn_words, h);
+                    subtree_subset(c, depth, T.max_depth, keys, seg, A, dyn_lds, dyn_words, h);
                 } else {
                     for (uint32_t qq = 0; qq < A.nwide; qq++) {
                         const uint32_t q = A.wide[qq];
                         uint32_t m, lt, le;
                         block_candidate<RULE>(c, depth, keys, A.start[q], A.end[q] - A.start[q],
                                               0u, h, sh, s3, sh64, mom[0], nullptr, m, lt, le);
-                        if (threadIdx.x == 0) sub_result(c, depth, A, q, m, lt, le);
+                        if (threadIdx.x == 0) sub_result(c, depth, T.max_depth, A, q, m, lt, le);
                     }
                     for (uint32_t q = w; q < nq; q += NW) {
                         const uint32_t s0 = A.start[q], nk = A.end[q] - s0;
                         if (nk > WAVE_CELL_MAX) continue;
                         uint32_t m, lt, le;
                         wave_candidate<RULE>(c, keys, s0, nk, h[w], mom[w], m, lt, le);
-                        if (l == 0) sub_result(c, depth, A, q, m, lt, le);
+                        if (l == 0) sub_result(c, depth, T.max_depth, A, q, m, lt, le);
                     }
                 }
                 __syncthreads();
@@ -2500,18 +2503,101 @@ __global__ __launch_bounds__(NT) void k_emit_write(Ctx c, uint32_t level) {
     if (ci < ncells) emit_cell(c, level, ci, c.pre + uint64_t(ci) * EMIT_STRIDE);
 }
 
-// The whole emit step in one workgroup of EMIT_NT threads, for levels of at
-// most EMIT_ONE_MAX cells (each thread takes EMIT_PER consecutive cells): the
-// counts and their prefix rows in LDS, the totals, the per-tree update, then
-// the node records and next cells.
+// The whole emit step in one workgroup of EMIT_NT threads (each thread takes
+// EMIT_PER consecutive cells).  Up to EMIT_ONE_MAX cells: the counts and
+// their prefix rows in LDS, the totals, the per-tree update, then the node
+// records and next cells.  More cells (a level run in tail shape): the same
+// in chunks of EMIT_ONE_MAX cells with the prefix rows in the workspace.
 constexpr int EMIT_NT = 1024;
 constexpr int EMIT_NW = EMIT_NT / WAVE;
 constexpr uint32_t EMIT_ONE_MAX = 2048;
 constexpr uint32_t EMIT_PER = EMIT_ONE_MAX / EMIT_NT;
+
+// Exclusive scan over the workgroup of one value per thread and counter;
+// swave: per-wave scratch.  Returns the totals in tot[].
+__device__ __forceinline__ void emit_wg_scan(const uint32_t (&local)[EMIT_COUNTERS],
+                                             uint32_t (&excl)[EMIT_COUNTERS],
+                                             uint32_t (&tot)[EMIT_COUNTERS],
+                                             uint32_t (*swave)[EMIT_COUNTERS]) {
+    const int w = threadIdx.x / WAVE;
+    uint32_t incl[EMIT_COUNTERS];
+#pragma unroll
+    for (int k = 0; k < EMIT_COUNTERS; k++) {
+        incl[k] = wave_incl_scan(local[k]);
+        if (lane() == WAVE - 1) swave[w][k] = incl[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < EMIT_COUNTERS; k++) {
+        uint32_t before = 0, all = 0;
+        for (int v = 0; v < EMIT_NW; v++) {
+            const uint32_t t = swave[v][k];
+            before += v < w ? t : 0u;
+            all += t;
+        }
+        excl[k] = before + incl[k] - local[k];
+        tot[k] = all;
+    }
+    __syncthreads();
+}
+
+__device__ void emit_chunked(const Ctx &c, uint32_t level, uint32_t ncells,
+                             uint32_t (*swave)[EMIT_COUNTERS]) {
+    uint32_t base[EMIT_COUNTERS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t b0 = 0; b0 < ncells; b0 += EMIT_ONE_MAX) {
+        const uint32_t c0 = b0 + threadIdx.x * EMIT_PER;
+        uint32_t cnt[EMIT_PER][EMIT_COUNTERS], local[EMIT_COUNTERS], excl[EMIT_COUNTERS],
+            tot[EMIT_COUNTERS];
+#pragma unroll
+        for (uint32_t j = 0; j < EMIT_PER; j++) emit_counts(c, level, c0 + j, ncells, cnt[j]);
+#pragma unroll
+        for (int k = 0; k < EMIT_COUNTERS; k++) {
+            local[k] = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < EMIT_PER; j++) local[k] += cnt[j][k];
+        }
+        emit_wg_scan(local, excl, tot, swave);
+#pragma unroll
+        for (int k = 0; k < EMIT_COUNTERS; k++) {
+            uint32_t run = base[k] + excl[k];
+#pragma unroll
+            for (uint32_t j = 0; j < EMIT_PER; j++) {
+                if (c0 + j < ncells) c.pre[uint64_t(c0 + j) * EMIT_STRIDE + k] = run;
+                run += cnt[j][k];
+            }
+            base[k] += tot[k];
+        }
+    }
+    if (threadIdx.x < uint32_t(EMIT_COUNTERS))
+        c.pre[uint64_t(ncells) * EMIT_STRIDE + threadIdx.x] = base[threadIdx.x];
+    if (threadIdx.x == 0) {
+        LevelInfo in{};
+        in.num_cells = base[1];
+        in.num_tiles = base[2];
+        in.points = base[3];
+        in.big_points = base[4];
+        in.num_big = base[5];
+        in.resolved = base[8];
+        c.info[level + 1] = in;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < c.ntrees; t += EMIT_NT)
+        emit_tree(c, level, t, c.pre, EMIT_STRIDE);
+    __threadfence_block();
+    __syncthreads();
+    for (uint32_t ci = threadIdx.x; ci < ncells; ci += EMIT_NT)
+        emit_cell(c, level, ci, c.pre + uint64_t(ci) * EMIT_STRIDE);
+}
+
 __global__ __launch_bounds__(EMIT_NT) void k_emit_one(Ctx c, uint32_t level) {
     __shared__ uint32_t spre[(EMIT_ONE_MAX + 1) * EMIT_COUNTERS];
     __shared__ uint32_t swave[EMIT_NW][EMIT_COUNTERS];
     const uint32_t ncells = c.info[level].num_cells;
+    if (ncells > EMIT_ONE_MAX) {
+        emit_chunked(c, level, ncells, swave);
+        return;
+    }
     const uint32_t c0 = threadIdx.x * EMIT_PER;
     const int w = threadIdx.x / WAVE;
     uint32_t cnt[EMIT_PER][EMIT_COUNTERS];
@@ -2711,6 +2797,16 @@ bool shape_ok(uint64_t n, uint32_t d) { return n > 0 && n <= 0xffffff00ull && d 
 
 uint64_t default_capacity(uint64_t n, uint32_t leaf) { return 4 * ((n + leaf - 1) / leaf) + 64; }
 
+// Depth cap for max_depth = 0: ten levels beyond the depth h of a balanced
+// tree of n points with leaves of at most `leaf` points (leaf * 2^h >= n),
+// at most 64.  Cells at the cap stay leaves (counted in hdr->oversize when
+// they hold more than `leaf` points).
+uint32_t default_depth(uint64_t n, uint32_t leaf) {
+    uint32_t h = 0;
+    while (h < 40 && (uint64_t(leaf) << h) < n) h++;
+    return std::min<uint32_t>(64, h + 10);
+}
+
 uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 struct Bump {
@@ -2890,62 +2986,27 @@ struct HostTree {
     const kd_tree *out;
 };
 
-// Level totals read back by the host: a pinned slot per level and a ring of
-// events, made once per thread and device and kept until the process ends.
-// The level loop waits for the totals of the level LEVEL_LAG before the one
-// it is about to enqueue, so the device always has that many levels queued;
-// launch shapes come from bounds derived from the last totals read.
-constexpr uint32_t LEVEL_LAG = 2;
-constexpr uint32_t READBACK_RING = 4;
-static_assert(LEVEL_LAG < READBACK_RING, "an event is waited on before it is recorded again");
-constexpr int READBACK_DEVICES = 64;
-
-struct LevelReadback {
-    LevelInfo *host = nullptr;  // MAX_LEVELS + 1 pinned slots
-    hipEvent_t ev[READBACK_RING] = {};
-};
-
-LevelReadback *level_readback() {
-    thread_local LevelReadback per_device[READBACK_DEVICES];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= READBACK_DEVICES) return nullptr;
-    LevelReadback &r = per_device[dev];
-    if (!r.host) {
-        void *h = nullptr;
-        if (hipHostMalloc(&h, sizeof(LevelInfo) * (MAX_LEVELS + 1), hipHostMallocDefault) !=
-            hipSuccess)
-            return nullptr;
-        for (uint32_t k = 0; k < READBACK_RING; k++)
-            if (hipEventCreateWithFlags(&r.ev[k], hipEventDisableTiming) != hipSuccess) {
-                for (uint32_t j = 0; j < k; j++) (void)hipEventDestroy(r.ev[j]);
-                (void)hipHostFree(h);
-                return nullptr;
-            }
-        r.host = static_cast<LevelInfo *>(h);
-    }
-    return &r;
-}
-
-// Upper bounds of a level's totals from the totals `K` of a level `gap`
-// levels earlier (gap 0: K itself).  Cells hold more than leaf_size points
-// and at most double per level; large cells hold more than SMALL_MAX points;
-// a cell of s points spans at most s / TILE + 1 tiles.
+// Upper bounds of a level's totals that hold whatever the data: from the
+// level-0 totals `K` (known on the host) and the level number.  Cells hold
+// more than leaf_size points and at most double per level; large cells (more
+// than SMALL_MAX points) only descend from large cells; a cell of s points
+// spans at most s / TILE + 1 tiles.
 struct LevelBound {
     uint64_t cells, tiles, big, big_points, small_points;
 };
 
-LevelBound level_bound(const LevelInfo &K, uint32_t gap, uint32_t leaf_size, const Layout &L) {
+uint64_t shl_sat(uint64_t x, uint32_t s) { return s >= 40 || x >= (uint64_t(1) << (63 - s)) ? ~uint64_t(0) >> 1 : x << s; }
+
+LevelBound level_bound(const LevelInfo &K, uint32_t level, uint32_t leaf_size, const Layout &L) {
     LevelBound b;
-    if (gap == 0) {
+    if (level == 0) {
         b = LevelBound{K.num_cells, K.num_tiles, K.num_big, K.big_points,
-                       uint64_t(K.points) - K.big_points - K.resolved};
+                       uint64_t(K.points) - K.big_points};
     } else {
-        b.cells = std::min<uint64_t>(uint64_t(K.num_cells) << gap, K.points / (uint64_t(leaf_size) + 1));
-        b.big = std::min<uint64_t>(uint64_t(K.num_big) << gap, K.big_points / (SMALL_MAX + 1));
+        b.cells = std::min<uint64_t>(shl_sat(K.num_cells, level), K.points / (uint64_t(leaf_size) + 1));
+        b.big = std::min<uint64_t>(shl_sat(K.num_big, level), K.big_points / (SMALL_MAX + 1));
         b.big_points = b.big ? K.big_points : 0;
         b.tiles = b.big ? b.big_points / TILE + b.big : 0;
-        // children of resolved cells can be handed back unresolved (a
-        // subtree that stops early), so every point counts here
         b.small_points = K.points;
     }
     b.cells = std::min(b.cells, L.max_cells);
@@ -2953,6 +3014,24 @@ LevelBound level_bound(const LevelInfo &K, uint32_t gap, uint32_t leaf_size, con
     b.tiles = std::min(b.tiles, L.max_tiles);
     return b;
 }
+
+// Tree descriptors reach the workspace as kernel arguments, so a build keeps
+// no host buffer past the call and a captured graph holds its own copy.
+constexpr uint32_t DESC_CHUNK = 8;
+struct DescChunk {
+    TreeDesc d[DESC_CHUNK];
+    uint32_t first, count;
+};
+__global__ void k_set_desc(TreeDesc *dst, DescChunk ch) {
+    for (uint32_t i = threadIdx.x; i < ch.count; i += blockDim.x) dst[ch.first + i] = ch.d[i];
+}
+
+// Levels past the depth a balanced tree of the largest input would reach
+// (plus TAIL_SLACK) run in "tail" shape: every kernel on a few workgroups
+// (they loop over whatever work the level holds) and the emit step in one
+// workgroup, so the empty levels at the end cost a few microseconds each.
+constexpr uint32_t TAIL_SLACK = 4;
+constexpr uint32_t TAIL_GRID = 64;
 
 // The level loop over every tree of the build.
 // Process-wide launch shapes (set by kd_set_tuning / kd_autotune).
@@ -3012,10 +3091,17 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         D.pbase = pbase;
         pbase += n[t];
         D.d = d[t];
+        D.max_depth = p->max_depth ? p->max_depth : default_depth(n[t], p->leaf_size);
     }
-    if (hipMemcpyAsync(ws + L.trees, desc.data(), sizeof(TreeDesc) * ntrees,
-                       hipMemcpyHostToDevice, st) != hipSuccess)
-        return KD_EDEVICE;
+    for (uint32_t t0 = 0; t0 < ntrees; t0 += DESC_CHUNK) {
+        DescChunk ch{};
+        ch.first = t0;
+        ch.count = std::min<uint32_t>(DESC_CHUNK, ntrees - t0);
+        for (uint32_t i = 0; i < ch.count; i++) ch.d[i] = desc[t0 + i];
+        hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, st,
+                           reinterpret_cast<TreeDesc *>(ws + L.trees), ch);
+    }
+    KD_LAUNCH_CHECK();
 
     Ctx c{};
     c.trees = reinterpret_cast<TreeDesc *>(ws + L.trees);
@@ -3058,7 +3144,6 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     c.pool_entries = p->pool_entries;
     c.seed = p->seed;
     c.leaf_size = p->leaf_size;
-    c.max_depth = p->max_depth ? p->max_depth : 64;
     c.key_rule = p->key_rule;
     c.split_rule = p->split_rule;
     c.J = p->fourier_J;
@@ -3114,22 +3199,15 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
             : 0;
     static_assert(sizeof(uint32_t) * (2 * MAX_SUBSETS + 1) + 64 * 1024 <= 160 * 1024,
                   "small-cell kernel LDS");
-    LevelReadback *rb = level_readback();
-    if (!rb) return KD_EDEVICE;
-    auto read_back = [&](uint32_t k) {  // enqueue the copy of level k's totals
-        return hipMemcpyAsync(&rb->host[k], c.info + k, sizeof(LevelInfo), hipMemcpyDeviceToHost,
-                              st) == hipSuccess &&
-               hipEventRecord(rb->ev[k % READBACK_RING], st) == hipSuccess;
-    };
     auto fail = [&]() {
         (void)hipStreamSynchronize(st);
         return KD_EDEVICE;
     };
-    if (!read_back(0)) return fail();
     // level 0 on the host: one root cell per tree with more than leaf_size points
     LevelInfo K{};
+    uint32_t likely = 0;  // levels a balanced tree of the largest input would have, + slack
     for (uint32_t t = 0; t < ntrees; t++) {
-        if (n[t] <= p->leaf_size || c.max_depth == 0) continue;
+        if (n[t] <= p->leaf_size || desc[t].max_depth == 0) continue;
         K.num_cells++;
         K.points += uint32_t(n[t]);
         if (n[t] > uint64_t(SMALL_MAX)) {
@@ -3137,48 +3215,68 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
             K.big_points += uint32_t(n[t]);
             K.num_big++;
         }
+        uint32_t h = 0;
+        while (h < 64 && (uint64_t(p->leaf_size) << h) < n[t]) h++;  // ceil(log2(n / leaf))
+        likely = std::max<uint32_t>(likely, h + 1 + TAIL_SLACK);
     }
-    uint32_t known = 0, next_read = 0;
-    // profiled builds wait for every level's totals: exact shapes and byte counts
-    const uint32_t lag = prof ? 0u : LEVEL_LAG;
-    const uint32_t level_cap = std::min<uint32_t>(MAX_LEVELS, c.max_depth);
+    // Profiled builds (measurement only) read every level's totals back and
+    // stop at the first empty level, so their launch shapes and byte counts
+    // are exact; every other build enqueues all levels at once and returns.
+    const bool paced = prof != nullptr;
+    uint32_t level_cap = 0;  // the deepest cap of any tree with a root cell
+    for (uint32_t t = 0; t < ntrees; t++)
+        if (n[t] > p->leaf_size) level_cap = std::max(level_cap, desc[t].max_depth);
+    level_cap = std::min<uint32_t>(level_cap, MAX_LEVELS);
     uint32_t levels_run = 0;
     for (uint32_t level = 0; level < level_cap; level++) {
-        while (next_read + lag <= level) {
-            if (hipEventSynchronize(rb->ev[next_read % READBACK_RING]) != hipSuccess) return fail();
-            K = rb->host[next_read];
-            known = next_read++;
+        LevelBound B;
+        bool tail = false;
+        if (paced) {
+            LevelInfo I{};
+            if (hipMemcpyAsync(&I, c.info + level, sizeof(LevelInfo), hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return fail();
+            if (I.num_cells == 0) break;
+            B = LevelBound{I.num_cells, I.num_tiles, I.num_big, I.big_points,
+                           uint64_t(I.points) - I.big_points - I.resolved};
+        } else {
+            B = level_bound(K, level, p->leaf_size, L);
+            tail = level >= likely;
         }
-        if (K.num_cells == 0) break;  // no cells at `known`, none after it
         levels_run++;
-        const LevelBound B = level_bound(K, level - known, p->leaf_size, L);
+        // launch shape: the bound's workgroups, or a few in tail shape
+        auto G = [&](uint64_t work, uint32_t cap) {
+            const uint32_t g = grid_for(work, cap);
+            return dim3(tail ? std::min<uint32_t>(g, TAIL_GRID) : g);
+        };
         const uint64_t nc = B.cells, ntl = B.tiles, nbig = B.big;
         const uint64_t bigp = B.big_points, smallp = B.small_points;
         P.run(KD_PROF_OTHER, 0, 0, [&] {
-            hipLaunchKernelGGL(k_level_init, dim3(grid_for(std::max(nc, ntl) / NT + 1, 4096)),
+            hipLaunchKernelGGL(k_level_init, G(std::max(nc, ntl) / NT + 1, 4096),
                                dim3(NT), 0, st, c, level, nbig > 0 ? 1u : 0u);
         });
         if (nbig > 0) {
             if (p->split_rule == KD_SPLIT_EXACT) {
                 for (uint32_t pass = 0; pass < uint32_t(BIG_PASSES); pass++) {
                     P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
-                        hipLaunchKernelGGL(k_big_hist, dim3(grid_for(ntl, hist_grid)), dim3(NT), 0,
+                        hipLaunchKernelGGL(k_big_hist, G(ntl, hist_grid), dim3(NT), 0,
                                            st, c, level, pass);
                     });
                     P.run(KD_PROF_PICK, 0, 0, [&] {
-                        hipLaunchKernelGGL(k_big_pick, dim3(grid_for((nbig + NW - 1) / NW, 65535)),
+                        hipLaunchKernelGGL(k_big_pick, G((nbig + NW - 1) / NW, 65535),
                                            dim3(NT), 0, st, c, level, pass);
                     });
                 }
             } else if (p->split_rule == KD_SPLIT_FOURIER) {
                 P.run(KD_PROF_SELECT, bigp, 8 * bigp, [&] {
-                    hipLaunchKernelGGL(k_big_minmax, dim3(grid_for(ntl, hist_grid)), dim3(NT), 0,
+                    hipLaunchKernelGGL(k_big_minmax, G(ntl, hist_grid), dim3(NT), 0,
                                        st, c, level);
-                    hipLaunchKernelGGL(k_big_moments, dim3(grid_for(ntl, hist_grid)), dim3(NT), 0,
+                    hipLaunchKernelGGL(k_big_moments, G(ntl, hist_grid), dim3(NT), 0,
                                        st, c, level);
                 });
                 P.run(KD_PROF_PICK, 0, 0, [&] {
-                    hipLaunchKernelGGL(k_big_fsolve, dim3(grid_for((nbig + NW - 1) / NW, 65535)),
+                    hipLaunchKernelGGL(k_big_fsolve, G((nbig + NW - 1) / NW, 65535),
                                        dim3(NT), 0, st, c, level);
                 });
             } else {
@@ -3188,43 +3286,43 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                 // workgroup or wave each, in LDS
                 const uint64_t nseg = std::min<uint64_t>(bigp / (SMALL_MAX + 1), nbig * c.S);
                 P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
-                    hipLaunchKernelGGL(k_big_bounds, dim3(grid_for(nbig / NT + 1, 4096)), dim3(NT),
+                    hipLaunchKernelGGL(k_big_bounds, G(nbig / NT + 1, 4096), dim3(NT),
                                        0, st, c, level);
                     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(NT), 0, st, c.seg_count, 1ull, 0u);
-                    hipLaunchKernelGGL(k_seg_list, dim3(grid_for(nbig * c.S / NT + 1, 4096)),
+                    hipLaunchKernelGGL(k_seg_list, G(nbig * c.S / NT + 1, 4096),
                                        dim3(NT), 0, st, c, level);
                     for (uint32_t pass = 0; nseg > 0 && pass < uint32_t(RPASSES); pass++) {
-                        hipLaunchKernelGGL(k_seg_hist, dim3(grid_for(nseg * SEG_FAN, 65535)),
+                        hipLaunchKernelGGL(k_seg_hist, G(nseg * SEG_FAN, 65535),
                                            dim3(NT), 0, st, c, level, pass);
-                        hipLaunchKernelGGL(k_seg_pick, dim3(grid_for(nseg, 65535)), dim3(NT), 0, st,
+                        hipLaunchKernelGGL(k_seg_pick, G(nseg, 65535), dim3(NT), 0, st,
                                            c, pass);
                     }
-                    hipLaunchKernelGGL(k_subset_select, dim3(grid_for(nbig * c.S / NW + 1, 65535)),
+                    hipLaunchKernelGGL(k_subset_select, G(nbig * c.S / NW + 1, 65535),
                                        dim3(NT), 0, st, c, level);
                 });
                 P.run(KD_PROF_PICK, 0, 0, [&] {
-                    hipLaunchKernelGGL(k_subset_mean, dim3(grid_for(nbig / NT + 1, 4096)),
+                    hipLaunchKernelGGL(k_subset_mean, G(nbig / NT + 1, 4096),
                                        dim3(NT), 0, st, c, level);
                 });
             }
             P.run(KD_PROF_COUNT, bigp, 4 * bigp, [&] {
-                hipLaunchKernelGGL(k_big_count, dim3(grid_for(ntl, tile_grid)), dim3(NT), 0, st, c,
+                hipLaunchKernelGGL(k_big_count, G(ntl, tile_grid), dim3(NT), 0, st, c,
                                    level);
-                hipLaunchKernelGGL(k_big_decide, dim3(grid_for(nbig, 65535)), dim3(NT), 0, st, c,
+                hipLaunchKernelGGL(k_big_decide, G(nbig, 65535), dim3(NT), 0, st, c,
                                    level);
             });
             P.run(KD_PROF_BIG_SCATTER, bigp, scatter_avg_bpp * bigp, [&] {
                 if (maxvar)
-                    hipLaunchKernelGGL(k_big_scatter<true>, dim3(grid_for(ntl, tile_grid)), dim3(NT), 0,
+                    hipLaunchKernelGGL(k_big_scatter<true>, G(ntl, tile_grid), dim3(NT), 0,
                                        st, c, level);
                 else
-                    hipLaunchKernelGGL(k_big_scatter<false>, dim3(grid_for(ntl, tile_grid)), dim3(NT),
+                    hipLaunchKernelGGL(k_big_scatter<false>, G(ntl, tile_grid), dim3(NT),
                                        0, st, c, level);
             });
         }
         if (smallp > 0) {
             P.run(KD_PROF_SMALL, smallp, scatter_avg_bpp * smallp, [&] {
-                const dim3 g(grid_for((smallp + TILE - 1) / TILE, small_grid));
+                const dim3 g = G((smallp + TILE - 1) / TILE, small_grid);
 #define KD_SUB(R, M) hipLaunchKernelGGL((k_subtree<R, M>), g, dim3(NT), small_dyn, st, c, level)
 #define KD_SMALL(R, M) hipLaunchKernelGGL((k_small<R, M>), g, dim3(NT), small_dyn, st, c, level)
                 // EXACT, FOURIER and SUBSET with equal subsets finish small
@@ -3249,18 +3347,18 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         }
         const uint32_t nb = uint32_t((nc + NT - 1) / NT);
         P.run(KD_PROF_EMIT, 0, 0, [&] {
-            if (nc <= EMIT_ONE_MAX) {
+            if (nc <= EMIT_ONE_MAX || tail) {
                 hipLaunchKernelGGL(k_emit_one, dim3(1), dim3(EMIT_NT), 0, st, c, level);
                 return;
             }
             hipLaunchKernelGGL(k_emit_sum, dim3(nb), dim3(NT), 0, st, c, level);
             hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(NT), 0, st, c, level, nb);
             hipLaunchKernelGGL(k_emit_prefix, dim3(nb), dim3(NT), 0, st, c, level);
-            hipLaunchKernelGGL(k_emit_trees, dim3(grid_for(ntrees / NT + 1, 1024)), dim3(NT), 0,
+            hipLaunchKernelGGL(k_emit_trees, G(ntrees / NT + 1, 1024), dim3(NT), 0,
                                st, c, level);
             hipLaunchKernelGGL(k_emit_write, dim3(nb), dim3(NT), 0, st, c, level);
         });
-        if (hipGetLastError() != hipSuccess || !read_back(level + 1)) return fail();
+        if (hipGetLastError() != hipSuccess) return fail();
     }
     P.run(KD_PROF_OTHER, 0, 0, [&] {
         hipLaunchKernelGGL(k_leaf_mark, per_tree_nodes, dim3(NT), 0, st, c);
@@ -3272,8 +3370,6 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     });
     KD_LAUNCH_CHECK();
     if (!P.finish(levels_run)) return KD_EDEVICE;
-    // the tree descriptors were copied from `desc`: wait before it goes away
-    if (hipStreamSynchronize(st) != hipSuccess) return KD_EDEVICE;
     return KD_OK;
 }
 

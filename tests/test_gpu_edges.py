@@ -4,6 +4,7 @@ sizes at or above the point count."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2201_08288_amd import synth
 from tests.gpu_common import KEYS, RULES, assert_same_tree, gpu_tree, oracle_tree
 
@@ -66,3 +67,17 @@ def test_leaf_size_at_or_above_n(leaf):
     o = oracle_tree(x, **kw)
     assert_same_tree(g, o, x)
     assert g["num_leaves"] == (1 if leaf >= 5000 else 2)
+
+
+@pytest.mark.parametrize("rule", [0, 1, 2])
+def test_default_depth_cap(rule):
+    """Exponentially spaced values: FOURIER peels about one point per level and
+    meets the default depth cap (the levels past the likely depth run in the
+    small tail launch shape); the tree equals the oracle's for every rule."""
+    print(f"case depth cap rule={rule}", flush=True)
+    x = np.stack([(2.0 ** np.arange(0, 120)).astype(np.float32),
+                  np.linspace(-1, 1, 120, dtype=np.float32)])
+    kw = dict(leaf_size=1, num_subsets=4, split_rule=rule)
+    g = gpu_tree(x, **kw)[1]
+    o = oracle.build_tree(x, **kw)
+    assert_same_tree(g, o, x)

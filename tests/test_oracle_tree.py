@@ -276,3 +276,17 @@ def test_batched_oracle_equals_single_builds():
         a = oracle.build_tree(x, **kw)
         for k, v in a.items():
             assert np.array_equal(np.asarray(v), np.asarray(b[k])), k
+
+
+def test_default_depth_cap():
+    """max_depth = 0 caps the depth at h + 10 (h: depth of a balanced tree,
+    leaf_size * 2^h >= n); cells at the cap stay leaves and are counted as
+    oversize.  FOURIER on exponentially spaced values peels about one point
+    per level, so it meets the cap; EXACT on the same values does not."""
+    x = (2.0 ** np.arange(0, 120)).astype(np.float32)[None, :]
+    t = oracle.build_tree(x, leaf_size=1, split_rule=oracle.SPLIT_FOURIER)
+    assert t["depth"] == 7 + 10 and t["oversize"] > 0
+    deep = oracle.build_tree(x, leaf_size=1, split_rule=oracle.SPLIT_FOURIER, max_depth=64)
+    assert deep["depth"] > 17 and deep["oversize"] == 0
+    t = oracle.build_tree(x, leaf_size=1, split_rule=oracle.SPLIT_EXACT)
+    assert t["depth"] == 7 and t["oversize"] == 0
