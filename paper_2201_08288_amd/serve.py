@@ -22,10 +22,12 @@ import torch
 from . import kdtree
 
 
-def footprint_bytes(n, d, leaf_size, num_queries=0):
+def footprint_bytes(n, d, params, num_queries=0):
     """Device bytes one request holds while in flight: input, output tree,
-    permuted points and the build workspace (as sized by the library)."""
-    prm = kdtree.make_params(leaf_size=leaf_size)
+    permuted points and the build workspace, as the library sizes them for
+    these build parameters (split rule, subsets, key rule, leaf size,
+    node capacity)."""
+    prm = kdtree.make_params(**params)
     cap, ws = kdtree.tree_bounds(n, d, prm)
     tree = 4 * n + cap * 4 * 9 + 4 * (cap + 1) + 32 + 4 * d * n
     return 4 * d * n + tree + ws + 8 * num_queries * d
@@ -33,7 +35,7 @@ def footprint_bytes(n, d, leaf_size, num_queries=0):
 
 class Request:
     __slots__ = ("rid", "points", "queries", "t_arrive", "t_admit", "t_done", "tree", "leaves",
-                 "status", "bytes", "event", "ready")
+                 "status", "bytes", "event", "ready", "state", "cancel_asked", "retries", "error")
 
     def __init__(self, rid, points, queries, t_arrive):
         self.rid, self.points, self.queries, self.t_arrive = rid, points, queries, t_arrive
@@ -43,6 +45,10 @@ class Request:
         self.bytes = 0
         self.event = threading.Event()
         self.ready = None  # device event: the inputs are complete on the submitting stream
+        self.state = "new"  # new -> pending -> waiting -> building -> done
+        self.cancel_asked = False
+        self.retries = 0    # rebuilds with larger node arrays after KD_ECAPACITY
+        self.error = None   # text of an unexpected failure of its batch
 
 
 class ServeEngine:
@@ -73,17 +79,45 @@ class ServeEngine:
             req.ready.record(torch.cuda.current_stream(req.points.device))
         d, n = req.points.shape
         nq = 0 if req.queries is None else req.queries.shape[1]
-        req.bytes = footprint_bytes(n, d, self.params.get("leaf_size", 32), nq)
+        req.bytes = footprint_bytes(n, d, self.params, nq)
         with self.lock:
             if req.bytes > self.cap_bytes:
-                req.status = kdtree.KD_ENOMEM
-                req.t_done = time.perf_counter()
-                req.event.set()
+                self._finish_locked(req, kdtree.KD_ENOMEM)
                 return False
+            req.state = "pending"
             self.pending.append(req)
             self._admit_locked()
             self.lock.notify_all()
         return True
+
+    def cancel(self, req):
+        """Withdraw a request.  Not yet building: it leaves the queues at once
+        and its reserved bytes are freed.  Building: its batch runs to the end
+        (the other requests' results do not depend on it), then its result is
+        dropped and its bytes freed with the batch.  Either way it ends with
+        status KD_ECANCELLED.  Returns False if it had already finished."""
+        with self.lock:
+            if req.state == "done":
+                return False
+            req.cancel_asked = True
+            if req.state == "pending":
+                self.pending.remove(req)
+                self._finish_locked(req, kdtree.KD_ECANCELLED)
+            elif req.state == "waiting":
+                self.waiting.remove(req)
+                self.used -= req.bytes
+                self._finish_locked(req, kdtree.KD_ECANCELLED)
+                self._admit_locked()
+            self.lock.notify_all()
+        return True
+
+    def _finish_locked(self, req, status):
+        req.status = status
+        req.state = "done"
+        req.t_done = time.perf_counter()
+        if status != kdtree.KD_OK:
+            req.tree = req.leaves = None
+        req.event.set()
 
     def _admit_locked(self):
         # first come, first served: a large request at the head waits for memory
@@ -91,12 +125,14 @@ class ServeEngine:
             r = self.pending.popleft()
             self.used += r.bytes
             r.t_admit = time.perf_counter()
+            r.state = "waiting"
             self.waiting.append(r)
 
-    def _release(self, reqs):
+    def _release(self, reqs, statuses):
         with self.lock:
-            for r in reqs:
+            for r, st in zip(reqs, statuses):
                 self.used -= r.bytes
+                self._finish_locked(r, kdtree.KD_ECANCELLED if r.cancel_asked else st)
             self._admit_locked()
             self.lock.notify_all()
 
@@ -107,7 +143,10 @@ class ServeEngine:
 
     def _run_batch(self, batch, stream):
         """One batched build of every request of the batch, then each
-        request's lookups, all on this worker's stream."""
+        request's lookups, all on this worker's stream.  Returns each
+        request's status: a tree whose node arrays were too small (header
+        status KD_ECAPACITY) is rebuilt alone with twice the node capacity,
+        up to the most nodes a tree of its size can have (2n - 1)."""
         with torch.cuda.stream(stream):
             for r in batch:
                 if r.ready is not None:
@@ -115,9 +154,24 @@ class ServeEngine:
             trees = kdtree.build_batched([r.points for r in batch], stream=stream, **self.params)
             for r, t in zip(batch, trees):
                 r.tree = t
-                if r.queries is not None:
-                    r.leaves = kdtree.query_leaf(t, r.queries, stream=stream)
         stream.synchronize()
+        statuses = []
+        for r in batch:
+            h = r.tree.header()
+            while h["status"] == kdtree.KD_ECAPACITY and r.tree.cap < 2 * r.points.shape[1] + 64:
+                r.retries += 1
+                prm = dict(self.params, node_capacity=2 * r.tree.cap)
+                with torch.cuda.stream(stream):
+                    r.tree = kdtree.build(r.points, stream=stream, **prm)
+                stream.synchronize()
+                h = r.tree.header()
+            statuses.append(h["status"])
+        with torch.cuda.stream(stream):
+            for r, st in zip(batch, statuses):
+                if st == kdtree.KD_OK and r.queries is not None:
+                    r.leaves = kdtree.query_leaf(r.tree, r.queries, stream=stream)
+        stream.synchronize()
+        return statuses
 
     def _work(self):
         stream = self._make_stream()
@@ -129,22 +183,23 @@ class ServeEngine:
                     return
                 batch = []
                 while self.waiting and len(batch) < self.max_batch:
-                    batch.append(self.waiting.popleft())
+                    r = self.waiting.popleft()
+                    r.state = "building"
+                    batch.append(r)
                 self.batches += 1
                 self.batch_sizes.append(len(batch))
+            statuses = [kdtree.KD_EDEVICE] * len(batch)
             try:
-                self._run_batch(batch, stream)
-                for r in batch:
-                    r.status = kdtree.KD_OK
+                statuses = self._run_batch(batch, stream)
             except kdtree.KDError as e:
+                statuses = [e.status] * len(batch)
+            except Exception as e:  # noqa: BLE001 -- every request must end
                 for r in batch:
-                    r.status = e.status
-            now = time.perf_counter()
-            for r in batch:
-                r.t_done = now
-            self._release(batch)
-            for r in batch:
-                r.event.set()
+                    r.error = f"{type(e).__name__}: {e}"
+            finally:
+                # whatever happened, the batch's bytes are released and every
+                # waiter is woken
+                self._release(batch, statuses)
 
     def close(self):
         with self.lock:

@@ -76,7 +76,7 @@ def test_oversize_request_rejected_others_complete():
     from paper_2201_08288_amd import kdtree, serve
     params = dict(leaf_size=64, num_subsets=64)
     reqs = make_requests(6, seed=77, lo_log2=12, hi_log2=14)
-    cap = 4 * max(serve.footprint_bytes(x.shape[1], x.shape[0], 64, 1024) for x, _, _ in reqs)
+    cap = 4 * max(serve.footprint_bytes(x.shape[1], x.shape[0], params, 1024) for x, _, _ in reqs)
     log(f"case serving admission: cap {cap} bytes")
     eng = serve.ServeEngine(params, cap_bytes=cap, workers=2)
     try:
@@ -123,6 +123,75 @@ def test_inputs_still_being_written_when_submitted():
         eng.close()
     for r, x in zip(reqs, data):
         assert r.status == kdtree.KD_OK
+        alone = kdtree.build(x, **params)
+        torch.cuda.synchronize()
+        a, b = alone.to_numpy(), r.tree.to_numpy()
+        for f in FIELDS:
+            assert np.array_equal(a[f], b[f]), (r.rid, f)
+
+
+def test_cancelled_request_leaves_others_unchanged():
+    """One request of a mix is cancelled while queued and one while its
+    batch builds; both end KD_ECANCELLED with their bytes freed, and every
+    other request's tree equals its alone build."""
+    import torch
+
+    from paper_2201_08288_amd import kdtree, serve
+    print("case serving cancellation", flush=True)
+    params = dict(leaf_size=64, num_subsets=64)
+    reqs = make_requests(24, seed=41, lo_log2=12, hi_log2=16)
+    eng = serve.ServeEngine(params, cap_bytes=8 << 30, workers=1)
+    done = []
+    try:
+        for k, (x, q, _) in enumerate(reqs):
+            r = serve.Request(k, x, q, time.perf_counter())
+            eng.submit(r)
+            done.append(r)
+            if k == 0:
+                while done[0].state != "building":  # the first batch holds request 0 alone
+                    time.sleep(0.0005)
+                eng.cancel(done[0])
+        eng.cancel(done[-1])  # still queued behind the first batch (one worker)
+        for r in done:
+            assert r.event.wait(60), r.rid
+        assert eng.used == 0
+    finally:
+        eng.close()
+    assert done[0].status == kdtree.KD_ECANCELLED and done[0].tree is None
+    assert done[-1].status == kdtree.KD_ECANCELLED
+    for r, (x, q, _) in list(zip(done, reqs))[1:-1]:
+        assert r.status == kdtree.KD_OK, (r.rid, r.status)
+        alone = kdtree.build(x, **params)
+        torch.cuda.synchronize()
+        a, b = alone.to_numpy(), r.tree.to_numpy()
+        for f in FIELDS:
+            assert np.array_equal(a[f], b[f]), (r.rid, f)
+
+
+def test_capacity_overflow_is_retried():
+    """Node arrays far too small for the trees (node_capacity 16): every
+    request comes back KD_ECAPACITY from the batch, is rebuilt alone with
+    doubled capacity until it fits, and then equals the build with the
+    default capacity."""
+    import torch
+
+    from paper_2201_08288_amd import kdtree, serve
+    print("case serving capacity retry", flush=True)
+    params = dict(leaf_size=64, num_subsets=64)
+    reqs = make_requests(6, seed=43, lo_log2=12, hi_log2=14)
+    eng = serve.ServeEngine(dict(params, node_capacity=16), cap_bytes=8 << 30, workers=2)
+    done = []
+    try:
+        for k, (x, q, _) in enumerate(reqs):
+            r = serve.Request(k, x, q, time.perf_counter())
+            eng.submit(r)
+            done.append(r)
+        for r in done:
+            assert r.event.wait(60), r.rid
+    finally:
+        eng.close()
+    for r, (x, q, idx) in zip(done, reqs):
+        assert r.status == kdtree.KD_OK and r.retries > 0, (r.rid, r.status, r.retries, r.error)
         alone = kdtree.build(x, **params)
         torch.cuda.synchronize()
         a, b = alone.to_numpy(), r.tree.to_numpy()
