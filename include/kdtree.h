@@ -28,8 +28,9 @@
  *     Data-dependent errors (non-finite input, node capacity) are written to
  *     hdr->status on the device.
  *   - Calls on distinct streams with distinct workspaces may run
- *     concurrently.  The library's only mutable global state is the
- *     process-wide launch-shape setting (kd_set_tuning, kd_autotune).
+ *     concurrently.  The library's mutable global state is the process-wide
+ *     launch-shape setting (kd_set_tuning, kd_autotune) and the fixed
+ *     workspace of kd_build_noalloc (one per device).
  */
 #ifndef KDTREE_H
 #define KDTREE_H
@@ -136,6 +137,19 @@ kd_status kd_tree_bounds(uint64_t n, uint32_t d, const kd_params *params,
 kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
                    const kd_params *params, kd_tree *out, void *workspace,
                    uint64_t ws_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): kd_build with the
+ * library's own fixed workspace instead of a caller's.  The workspace is one
+ * array of KD_NOALLOC_SCRATCH_BYTES per device, held by the library until
+ * the process ends; the call allocates nothing.  Builds whose workspace
+ * (kd_tree_bounds with out->node_capacity) is larger return KD_ENOMEM and
+ * enqueue nothing.  Every call on a device uses the same array: calls whose
+ * work overlaps on one device (other streams or threads) race and must be
+ * ordered by the caller.  Otherwise as kd_build (stream-ordered).          */
+#define KD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+kd_status kd_build_noalloc(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
+                           const kd_params *params, kd_tree *out, void *stream);
 
 /* Optional instrumentation of one build: HIP events recorded on the build's
  * stream around every launch, summed per kernel class.  bytes are the

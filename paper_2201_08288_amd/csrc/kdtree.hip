@@ -3381,6 +3381,34 @@ bool tree_ok(const kd_tree *o) {
 
 }  // namespace
 
+// ------------------------------------------------------------ fixed scratch
+
+// Workspace of kd_build_noalloc: one array per device, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host the name is a stand-in, not the device address): the address is
+// taken once per device with hipGetSymbolAddress and kept in g_scratch.
+static_assert(KD_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+__device__ __align__(256) uint8_t scratch[KD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[SCRATCH_DEVICES] = {};
+
+// Device address of the current device's scratch (nullptr on failure).
+void *device_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch[dev] = ptr;
+    }
+    return g_scratch[dev];
+}
+}  // namespace
+
 // ------------------------------------------------------------ C ABI
 
 extern "C" {
@@ -3427,6 +3455,17 @@ kd_status kd_build_profiled(const float *pts, uint64_t n, uint32_t d, uint64_t l
 kd_status kd_build(const float *pts, uint64_t n, uint32_t d, uint64_t ld, const kd_params *p,
                    kd_tree *out, void *workspace, uint64_t ws_bytes, void *stream) {
     return kd_build_profiled(pts, n, d, ld, p, out, workspace, ws_bytes, stream, nullptr);
+}
+
+kd_status kd_build_noalloc(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
+                           const kd_params *p, kd_tree *out, void *stream) {
+    if (!params_ok(p) || !shape_ok(n, d) || !pts || ld < n || !tree_ok(out)) return KD_EINVAL;
+    const uint64_t cap = out->node_capacity;
+    const Layout L = plan(1, &n, &d, &cap, p);
+    if (L.total > KD_NOALLOC_SCRATCH_BYTES) return KD_ENOMEM;
+    void *ws = device_scratch();
+    if (!ws) return KD_EDEVICE;
+    return kd_build(pts, n, d, ld, p, out, ws, KD_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 kd_status kd_query_leaf(const kd_tree *tree, const float *q, uint64_t nq, uint32_t d,

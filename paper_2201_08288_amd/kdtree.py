@@ -85,6 +85,9 @@ def lib():
         L.kd_build.restype = st
         L.kd_build.argtypes = [_vp, _u64, _u32, _u64, ctypes.POINTER(Params),
                                ctypes.POINTER(TreeStruct), _vp, _u64, _vp]
+        L.kd_build_noalloc.restype = st
+        L.kd_build_noalloc.argtypes = [_vp, _u64, _u32, _u64, ctypes.POINTER(Params),
+                                       ctypes.POINTER(TreeStruct), _vp]
         L.kd_build_profiled.restype = st
         L.kd_build_profiled.argtypes = [_vp, _u64, _u32, _u64, ctypes.POINTER(Params),
                                         ctypes.POINTER(TreeStruct), _vp, _u64, _vp,
@@ -253,6 +256,27 @@ def build(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
     _check(st, "kd_build")
     tree.params = prm
     tree.workspace = workspace
+    return tree
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def build_noalloc(points, tree, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
+                  split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0, stream=None):
+    """kd_build_noalloc into an existing KDTree (the library's fixed per-device
+    workspace; nothing is allocated)."""
+    assert points.is_cuda and points.dtype == torch.float32 and points.dim() == 2
+    assert points.stride(1) == 1
+    d, n = points.shape
+    assert tree.n == n and tree.d == d
+    ld = points.stride(0) if d > 1 else n
+    prm = make_params(leaf_size, max_depth, num_subsets, key_rule, split_rule, fourier_J,
+                      subset_pool, seed, tree.cap)
+    _check(lib().kd_build_noalloc(points.data_ptr(), n, d, ld, ctypes.byref(prm),
+                                  ctypes.byref(tree.struct), _stream_ptr(stream)),
+           "kd_build_noalloc")
+    tree.params = prm
     return tree
 
 
