@@ -67,6 +67,13 @@ enum { KD_KEY_CYCLIC = 0, KD_KEY_MAXVAR = 1 };
  *           lower medians of the cell's subsets.                          */
 enum { KD_SPLIT_EXACT = 0, KD_SPLIT_FOURIER = 1, KD_SPLIT_SUBSET = 2 };
 
+/* kd_params.flags.  KD_FLAG_LEVEL_BY_LEVEL: small cells (at most 4096
+ * points) are also split one level per pass, so every level of the build
+ * streams through device memory, instead of each small cell's remaining
+ * levels being finished on chip in one pass.  The tree is the same either
+ * way; the flag exists to measure the plain per-level build.               */
+enum { KD_FLAG_LEVEL_BY_LEVEL = 1 };
+
 typedef struct kd_params {
     uint32_t leaf_size;        /* cells with > leaf_size points are split (>= 1)   */
     uint32_t max_depth;        /* cells at this depth stay leaves; 0 -> h + 10, at
@@ -81,7 +88,7 @@ typedef struct kd_params {
                                   * weights in units of 2^-32 (entry 0 unused);
                                   * NULL -> equal subsets floor(r*n_c/S)          */
     uint32_t pool_entries;
-    uint32_t reserved;
+    uint32_t flags;            /* KD_FLAG_* (0: none)                               */
     uint64_t seed;             /* picks the pool row of each cell                   */
     uint64_t node_capacity;    /* 0 -> 4*ceil(n/leaf_size)+64                       */
 } kd_params;

@@ -2790,6 +2790,7 @@ bool params_ok(const kd_params *p) {
         return false;
     if (p->subset_pool && p->pool_entries == 0) return false;
     if (p->max_depth > MAX_LEVELS) return false;
+    if (p->flags & ~uint32_t(KD_FLAG_LEVEL_BY_LEVEL)) return false;
     return true;
 }
 
@@ -2850,8 +2851,9 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     for (uint32_t t = 0; t < T; t++) caps += cap[t];
     // records of splits found ahead: the subtree path (every rule but SUBSET
     // with a subset pool or the largest-variance key)
-    const bool per_level = p->split_rule == KD_SPLIT_SUBSET &&
-                           (p->subset_pool != nullptr || p->key_rule == KD_KEY_MAXVAR);
+    const bool per_level = (p->flags & KD_FLAG_LEVEL_BY_LEVEL) ||
+                           (p->split_rule == KD_SPLIT_SUBSET &&
+                            (p->subset_pool != nullptr || p->key_rule == KD_KEY_MAXVAR));
     L.rec_cap = per_level ? 0 : std::min<uint64_t>(caps, REC_INDEX - 1);
     L.subrec = B.take(L.rec_cap * sizeof(SubRec));
     L.rec_count = B.take(4);
@@ -3328,6 +3330,17 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                 // EXACT, FOURIER and SUBSET with equal subsets finish small
                 // cells' subtrees in one pass; a subset pool's rows depend on a
                 // cell's rank within its level, known only level by level
+                if (p->flags & KD_FLAG_LEVEL_BY_LEVEL) {
+                    switch (p->split_rule * 2 + (maxvar ? 1 : 0)) {
+                        case 0: KD_SMALL(KD_SPLIT_EXACT, false); break;
+                        case 1: KD_SMALL(KD_SPLIT_EXACT, true); break;
+                        case 2: KD_SMALL(KD_SPLIT_FOURIER, false); break;
+                        case 3: KD_SMALL(KD_SPLIT_FOURIER, true); break;
+                        case 4: KD_SMALL(KD_SPLIT_SUBSET, false); break;
+                        default: KD_SMALL(KD_SPLIT_SUBSET, true); break;
+                    }
+                    return;
+                }
                 switch (p->split_rule * 2 + (maxvar ? 1 : 0)) {
                     case 0: KD_SUB(KD_SPLIT_EXACT, false); break;
                     case 1: KD_SUB(KD_SPLIT_EXACT, true); break;

@@ -15,6 +15,7 @@ from . import _build
 KEY_CYCLIC, KEY_MAXVAR = 0, 1
 SPLIT_EXACT, SPLIT_FOURIER, SPLIT_SUBSET = 0, 1, 2
 KD_OK, KD_EINVAL, KD_ENOMEM, KD_ENAN, KD_ECAPACITY, KD_EDEVICE, KD_ECANCELLED = range(7)
+FLAG_LEVEL_BY_LEVEL = 1
 NO_LEAF = 0xFFFFFFFF
 
 _u32, _u64, _vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
@@ -23,7 +24,7 @@ _u32, _u64, _vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
 class Params(ctypes.Structure):
     _fields_ = [("leaf_size", _u32), ("max_depth", _u32), ("num_subsets", _u32),
                 ("key_rule", _u32), ("split_rule", _u32), ("fourier_J", _u32),
-                ("subset_pool", _vp), ("pool_entries", _u32), ("reserved", _u32),
+                ("subset_pool", _vp), ("pool_entries", _u32), ("flags", _u32),
                 ("seed", _u64), ("node_capacity", _u64)]
 
 
@@ -141,8 +142,9 @@ def _check(status, what):
 
 def make_params(leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
                 split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0,
-                node_capacity=0):
+                node_capacity=0, flags=0):
     p = Params()
+    p.flags = flags
     p.leaf_size = leaf_size
     p.max_depth = max_depth
     p.num_subsets = num_subsets
@@ -224,7 +226,7 @@ def _stream_ptr(stream):
 
 def build(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
           split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0, node_capacity=0,
-          points_out=True, workspace=None, stream=None, tree=None, profile=None):
+          points_out=True, workspace=None, stream=None, tree=None, profile=None, flags=0):
     """kd_build on a (d, ld)-strided float32 CUDA tensor of shape (d, n).
 
     tree: reuse the output arrays of an earlier KDTree of the same shape.
@@ -235,7 +237,7 @@ def build(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
     d, n = points.shape
     ld = points.stride(0) if d > 1 else n
     prm = make_params(leaf_size, max_depth, num_subsets, key_rule, split_rule, fourier_J,
-                      subset_pool, seed, node_capacity)
+                      subset_pool, seed, node_capacity, flags)
     cap, _ = tree_bounds(n, d, prm)
     if tree is None or tree.cap < cap or tree.n != n or tree.d != d:
         tree = KDTree(n, d, cap, points.device, points_out)
@@ -263,7 +265,8 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def build_noalloc(points, tree, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
-                  split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0, stream=None):
+                  split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0, stream=None,
+                  flags=0):
     """kd_build_noalloc into an existing KDTree (the library's fixed per-device
     workspace; nothing is allocated)."""
     assert points.is_cuda and points.dtype == torch.float32 and points.dim() == 2
@@ -272,7 +275,7 @@ def build_noalloc(points, tree, leaf_size=32, max_depth=0, num_subsets=1, key_ru
     assert tree.n == n and tree.d == d
     ld = points.stride(0) if d > 1 else n
     prm = make_params(leaf_size, max_depth, num_subsets, key_rule, split_rule, fourier_J,
-                      subset_pool, seed, tree.cap)
+                      subset_pool, seed, tree.cap, flags)
     _check(lib().kd_build_noalloc(points.data_ptr(), n, d, ld, ctypes.byref(prm),
                                   ctypes.byref(tree.struct), _stream_ptr(stream)),
            "kd_build_noalloc")
@@ -282,11 +285,11 @@ def build_noalloc(points, tree, leaf_size=32, max_depth=0, num_subsets=1, key_ru
 
 def build_batched(points_list, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
                   split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0,
-                  node_capacity=0, points_out=True, workspace=None, stream=None):
+                  node_capacity=0, points_out=True, workspace=None, stream=None, flags=0):
     """kd_build_batched over a list of (d_t, n_t) float32 CUDA tensors
     (node_capacity: node-array entries of every tree, 0 = the default)."""
     prm = make_params(leaf_size, max_depth, num_subsets, key_rule, split_rule, fourier_J,
-                      subset_pool, seed, node_capacity)
+                      subset_pool, seed, node_capacity, flags)
     T = len(points_list)
     items = (BatchItem * T)()
     trees = []
@@ -410,13 +413,14 @@ def get_tuning():
 
 
 def autotune(points, leaf_size=32, max_depth=0, num_subsets=1, key_rule=KEY_CYCLIC,
-             split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0, stream=None):
+             split_rule=SPLIT_EXACT, fourier_J=15, subset_pool=None, seed=0, stream=None,
+             flags=0):
     """kd_autotune on this input; returns the chosen launch shapes (now in use)."""
     assert points.is_cuda and points.dtype == torch.float32 and points.stride(1) == 1
     d, n = points.shape
     ld = points.stride(0) if d > 1 else n
     prm = make_params(leaf_size, max_depth, num_subsets, key_rule, split_rule, fourier_J,
-                      subset_pool, seed, 0)
+                      subset_pool, seed, 0, flags)
     cap, ws = tree_bounds(n, d, prm)
     prm.node_capacity = cap
     workspace = torch.empty(ws, dtype=torch.uint8, device=points.device)

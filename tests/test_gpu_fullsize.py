@@ -56,6 +56,7 @@ def _compare(x, kw, pool=None):
         f"{[(k, g[k]) for k in ('status', 'num_nodes', 'num_leaves', 'depth', 'unsplittable')]}")
     assert g["status"] == 0
     t0 = time.perf_counter()
+    kw = {k: v for k, v in kw.items() if k != "flags"}
     o = oracle.build_tree(x, pool=pool, **kw)
     log(f"oracle whole build {time.perf_counter() - t0:.1f} s")
     assert_same_tree(g, o, x)
@@ -75,6 +76,18 @@ def test_hard_whole_tree(hard_input, rule):
     log(f"case hard n=2^26 d=16 rule={RULE_NAMES[rule]} (largest-variance key, subset pool)")
     _compare(x, dict(leaf_size=w["leaf_size"], num_subsets=w["num_subsets"], split_rule=rule,
                      key_rule=oracle.KEY_MAXVAR, fourier_J=15, seed=w.get("seed", 0)), pool=pool)
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_hard_whole_tree_level_by_level(hard_input, rule):
+    """The plain per-level build (every level through device memory, no
+    on-chip completion of small cells) at n = 2^26 gives the same tree."""
+    from paper_2201_08288_amd import kdtree
+    w, x, pool = hard_input
+    log(f"case hard n=2^26 d=16 rule={RULE_NAMES[rule]}, level by level")
+    _compare(x, dict(leaf_size=w["leaf_size"], num_subsets=w["num_subsets"], split_rule=rule,
+                     key_rule=oracle.KEY_MAXVAR, fourier_J=15, seed=w.get("seed", 0),
+                     flags=kdtree.FLAG_LEVEL_BY_LEVEL), pool=pool)
 
 
 def batched_inputs():
