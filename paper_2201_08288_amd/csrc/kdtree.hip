@@ -80,6 +80,10 @@ struct Ctx {
     SubRec *subrec;
     uint32_t *rec_count;
     uint32_t rec_cap;
+    // largest-variance key: each record's per-coordinate sums (S1, hi, lo),
+    // stride recstats_stride * 3 words
+    unsigned long long *recstats;
+    uint32_t recstats_stride;
     const uint32_t *pool;
     uint32_t pool_entries;
     unsigned long long seed;
@@ -1923,10 +1927,6 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
     __shared__ ChunkLds<SC> C;
     __shared__ SubTable<SC, CH> Q[2];
     __shared__ uint32_t sh[2 * NW + 1], s3[4];
-    // MAXVAR: chunk prefix sums (S1, hi, lo) at the first slot of every child
-    // and per-wave totals of the scan, double-buffered over the columns
-    __shared__ unsigned long long pat[2][MAXVAR ? CH : 1][3];
-    __shared__ unsigned long long wtot[2][MAXVAR ? NW : 1][3];
     static_assert(CH < int(SEG_LEAF), "child numbers fit a byte below SEG_LEAF");
     // SUBSET: subset bounds and medians (dynamic LDS of max(4096, 2S + 1) words)
     extern __shared__ uint32_t dyn_lds[];
@@ -2146,113 +2146,100 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                 }
                 if (MAXVAR && recs) {
                     // key coordinate of every child: the largest fixed-point
-                    // variance over the columns, ties to the lowest.  Thread t
-                    // holds slots 16t .. 16t+15 and takes a record of its
-                    // running sums at each child's first slot; slots outside
-                    // the children add nothing, so a child's sums are the
-                    // difference of its record and the next one.
+                    // variance over the columns, ties to the lowest.  Every
+                    // child is a contiguous run of slots.  One wave takes a
+                    // sub-cell q: its lanes stride over the slots of one
+                    // child and the exact sums of each column are wave
+                    // reductions (no workgroup barrier between columns).
+                    // When both children go on, only the smaller is summed
+                    // from its points; the other's sums are q's minus it,
+                    // exact integers either way.  Every child's sums are
+                    // kept by record for the next sub-depth.  The place of
+                    // each slot's point is staged in the key buffer (free
+                    // until the next sub-depth's keys).
                     const int shift = maxvar_shift(c.ts[tr].maxabs);
-                    const uint32_t e0 = threadIdx.x * PER_THREAD;
-                    uint32_t amask = 0, rmask = 0, rid[4] = {0, 0, 0, 0}, pe[PER_THREAD];
-                    {
-                        const uint4 sq = *reinterpret_cast<const uint4 *>(seg + e0);
-                        const uint32_t sw[4] = {sq.x, sq.y, sq.z, sq.w};
-#pragma unroll
-                        for (int j = 0; j < PER_THREAD; j++) {
-                            const uint32_t e = e0 + j, k = (sw[j >> 2] >> (8 * (j & 3))) & 0xffu;
-                            pe[j] = 0;
-                            if (e < tot && k != SEG_LEAF) {
-                                amask |= 1u << j;
-                                const uint32_t o = lp[e];
-                                pe[j] = C.off[seg0[o]] + o;
-                                if (e == N.start[k]) {
-                                    rmask |= 1u << j;
-                                    rid[j >> 2] |= k << (8 * (j & 3));
-                                }
-                            }
-                        }
+                    const uint64_t rstride = uint64_t(c.recstats_stride) * 3;
+                    for (uint32_t e = threadIdx.x; e < tot; e += NT) {
+                        const uint32_t o = lp[e];
+                        keys[e] = C.off[seg0[o]] + o;
                     }
-                    const uint32_t mine = threadIdx.x;  // child whose coordinate this thread picks
-                    __int128 best = -1;
-                    uint32_t bd = 0;
-                    // the next column's values are loaded while this one is
-                    // summed; the records alternate between two buffers, so one
-                    // barrier per column separates their writes and reads
-                    uint32_t xn[PER_THREAD];
-                    {
-                        const KD_GLOBAL uint32_t *src = gp(T.cols[cur]);
-#pragma unroll
-                        for (int j = 0; j < PER_THREAD; j++) xn[j] = (amask >> j) & 1u ? src[pe[j]] : 0u;
-                    }
-                    for (uint32_t col = 0; col < d; col++) {
-                        const int pb = col & 1;
-                        uint32_t xv[PER_THREAD];
-#pragma unroll
-                        for (int j = 0; j < PER_THREAD; j++) xv[j] = xn[j];
-                        if (col + 1 < d) {
-                            const KD_GLOBAL uint32_t *src = gp(T.cols[cur] + uint64_t(col + 1) * n);
-#pragma unroll
-                            for (int j = 0; j < PER_THREAD; j++)
-                                xn[j] = (amask >> j) & 1u ? src[pe[j]] : 0u;
+                    __syncthreads();
+                    // (sub-cell, column) items over the waves: even one
+                    // sub-cell keeps every wave busy
+                    for (uint32_t it = w; it < nq * d; it += NW) {
+                        const uint32_t q = it / d, col = it - q * d;
+                        const uint32_t k0 = A.kid[q][0], k1 = A.kid[q][1];
+                        if (k0 == NONE && k1 == NONE) continue;
+                        uint32_t ka = k0 != NONE ? k0 : k1, kb = NONE;
+                        if (k0 != NONE && k1 != NONE) {
+                            const bool first = N.end[k0] - N.start[k0] <= N.end[k1] - N.start[k1];
+                            ka = first ? k0 : k1;
+                            kb = first ? k1 : k0;
                         }
+                        const uint32_t s0 = N.start[ka], s1 = N.end[ka];
+                        const KD_GLOBAL uint32_t *src = gp(T.cols[cur] + uint64_t(col) * n);
                         VarSums a;
+                        uint32_t e = s0 + l;
+                        // eight values per lane between folds (no wrap)
+                        for (; e + 7 * WAVE < s1; e += 8 * WAVE) {
+                            uint32_t xv[8];
 #pragma unroll
-                        for (int j = 0; j < PER_THREAD; j++) {
-                            if ((rmask >> j) & 1u) {
-                                a.fold();
-                                const uint32_t r = (rid[j >> 2] >> (8 * (j & 3))) & 0xffu;
-                                pat[pb][r][0] = a.s1;
-                                pat[pb][r][1] = a.hi;
-                                pat[pb][r][2] = a.lo;
-                            }
-                            if ((amask >> j) & 1u) a.add(maxvar_q32(xv[j], shift));
-                            if (j == 7) a.fold();
+                            for (int j = 0; j < 8; j++) xv[j] = src[keys[e + j * WAVE]];
+#pragma unroll
+                            for (int j = 0; j < 8; j++) a.add(maxvar_q32(xv[j], shift));
+                            a.fold();
+                        }
+                        for (; e < s1; e += WAVE) {
+                            a.add(maxvar_q32(src[keys[e]], shift));
+                            a.fold();
                         }
                         a.fold();
-                        unsigned long long x[3] = {a.s1, a.hi, a.lo};
+                        const unsigned long long v[3] = {wave_sum64(a.s1), wave_sum64(a.hi),
+                                                         wave_sum64(a.lo)};
+                        if (l == 0) {
+                            unsigned long long *sa = c.recstats + uint64_t(N.rec[ka] - 1) * rstride;
 #pragma unroll
-                        for (int i = 0; i < 3; i++) x[i] = wave_scan64(x[i]);
-                        if (rmask) {
-                            const unsigned long long ex[3] = {x[0] - a.s1, x[1] - a.hi, x[2] - a.lo};
-                            for (uint32_t mm = rmask; mm; mm &= mm - 1) {
-                                const int j = __builtin_ctz(mm);
-                                const uint32_t r = (rid[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                            for (int i = 0; i < 3; i++) sa[col * 3 + i] = v[i];
+                            if (kb != NONE) {
+                                // q's own sums minus ka's
+                                const unsigned long long *ps;
+                                if (depth == level) {
+                                    const uint32_t ci = C.ci[q], link = c.cell_rec[cur][ci];
+                                    ps = link ? c.recstats + uint64_t((link & REC_INDEX) - 1) * rstride
+                                              : T.stats[cur] + uint64_t(c.cells[cur][ci].slot) * d * 3;
+                                } else {
+                                    ps = c.recstats + uint64_t(A.rec[q] - 1) * rstride;
+                                }
+                                unsigned long long *sb =
+                                    c.recstats + uint64_t(N.rec[kb] - 1) * rstride;
 #pragma unroll
-                                for (int i = 0; i < 3; i++) pat[pb][r][i] += ex[i];
+                                for (int i = 0; i < 3; i++) sb[col * 3 + i] = ps[col * 3 + i] - v[i];
                             }
                         }
-                        if (l == WAVE - 1)
-#pragma unroll
-                            for (int i = 0; i < 3; i++) wtot[pb][w][i] = x[i];
-                        __syncthreads();
-                        if (mine < nact) {
-                            // chunk prefix at child r's first slot (r = nact: the end)
-                            auto prefix = [&](uint32_t r, int i) {
-                                unsigned long long v = r < nact ? pat[pb][r][i] : 0ull;
-                                const uint32_t wr =
-                                    r < nact ? N.start[r] / (WAVE * PER_THREAD) : uint32_t(NW);
-                                for (uint32_t ww = 0; ww < wr; ww++) v += wtot[pb][ww][i];
-                                return v;
-                            };
-                            const long long s1 =
-                                (long long)(prefix(mine + 1, 0) - prefix(mine, 0));
-                            const __int128 s2 =
-                                (__int128)(long long)(prefix(mine + 1, 1) - prefix(mine, 1)) *
-                                    ((__int128)1 << 32) +
-                                (__int128)(long long)(prefix(mine + 1, 2) - prefix(mine, 2));
-                            const __int128 nc = N.end[mine] - N.start[mine];
-                            const __int128 V = nc * s2 - (__int128)s1 * (__int128)s1;
+                    }
+                    __syncthreads();
+                    // each child's coordinate from its sums
+                    for (uint32_t k = threadIdx.x; k < nact; k += NT) {
+                        const unsigned long long *sk = c.recstats + uint64_t(N.rec[k] - 1) * rstride;
+                        const __int128 nc = N.end[k] - N.start[k];
+                        __int128 best = -1;
+                        uint32_t bd = 0;
+                        for (uint32_t col = 0; col < d; col++) {
+                            const __int128 S1 = (long long)sk[col * 3];
+                            const __int128 S2 =
+                                (__int128)(long long)sk[col * 3 + 1] * ((__int128)1 << 32) +
+                                (__int128)(long long)sk[col * 3 + 2];
+                            const __int128 V = nc * S2 - S1 * S1;
                             if (V > best) {
                                 best = V;
                                 bd = col;
                             }
                         }
-                    }
-                    if (mine < nact) {
-                        N.dim[mine] = bd;
+                        N.dim[k] = bd;
                         // children that stop here take their coordinate along
-                        if (!go_on) c.subrec[rbase + mine] = SubRec{bd, 0u, 0u, 0u, {0u, 0u}};
+                        if (!go_on) c.subrec[rbase + k] = SubRec{bd, 0u, 0u, 0u, {0u, 0u}};
                     }
+                    __syncthreads();
                 }
                 if (!go_on) break;
                 // the children become the next sub-depth
@@ -2825,7 +2812,7 @@ struct TreeLayout {
 };
 
 struct Layout {
-    uint64_t cell_rec[2], subrec, rec_count, rec_cap;
+    uint64_t cell_rec[2], subrec, rec_count, rec_cap, recstats, recstats_stride;
     uint64_t trees, ts, cells[2], res, big_list, tile_lt, tile_le, tile_off, tile_cell, tiles, hist, mm, mom,
         bounds, med, pre, scan, buckets, segs, info, leafbits, leafpre, leafblk, total;
     uint64_t max_cells, max_tiles, max_big, scan_blocks, all_points, leaf_words, leaf_blocks;
@@ -2856,6 +2843,13 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
                             (p->subset_pool != nullptr || p->key_rule == KD_KEY_MAXVAR));
     L.rec_cap = per_level ? 0 : std::min<uint64_t>(caps, REC_INDEX - 1);
     L.subrec = B.take(L.rec_cap * sizeof(SubRec));
+    // largest-variance key on the subtree path: every record's per-coordinate
+    // sums (the widest tree's dimension as the stride)
+    L.recstats_stride = 0;
+    if (p->key_rule == KD_KEY_MAXVAR && L.rec_cap)
+        for (uint32_t t = 0; t < T; t++)
+            L.recstats_stride = std::max<uint64_t>(L.recstats_stride, d[t]);
+    L.recstats = B.take(L.rec_cap * L.recstats_stride * 3 * 8);
     L.rec_count = B.take(4);
     L.res = B.take(L.max_cells * sizeof(CellRes));
     L.big_list = B.take(L.max_big * 4);
@@ -3142,6 +3136,8 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     c.subrec = reinterpret_cast<SubRec *>(ws + L.subrec);
     c.rec_count = reinterpret_cast<uint32_t *>(ws + L.rec_count);
     c.rec_cap = uint32_t(L.rec_cap);
+    c.recstats = reinterpret_cast<unsigned long long *>(ws + L.recstats);
+    c.recstats_stride = uint32_t(L.recstats_stride);
     c.pool = p->subset_pool;
     c.pool_entries = p->pool_entries;
     c.seed = p->seed;
