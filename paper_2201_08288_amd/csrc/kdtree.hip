@@ -2180,20 +2180,18 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                         const KD_GLOBAL uint32_t *src = gp(T.cols[cur] + uint64_t(col) * n);
                         VarSums a;
                         uint32_t e = s0 + l;
-                        // eight values per lane between folds (no wrap)
-                        for (; e + 7 * WAVE < s1; e += 8 * WAVE) {
+                        // up to eight loads in flight per lane, eight values
+                        // between folds (no wrap)
+                        for (; e < s1; e += 8 * WAVE) {
                             uint32_t xv[8];
 #pragma unroll
-                            for (int j = 0; j < 8; j++) xv[j] = src[keys[e + j * WAVE]];
+                            for (int j = 0; j < 8; j++)
+                                xv[j] = e + j * WAVE < s1 ? src[keys[e + j * WAVE]] : 0u;
 #pragma unroll
-                            for (int j = 0; j < 8; j++) a.add(maxvar_q32(xv[j], shift));
+                            for (int j = 0; j < 8; j++)
+                                if (e + j * WAVE < s1) a.add(maxvar_q32(xv[j], shift));
                             a.fold();
                         }
-                        for (; e < s1; e += WAVE) {
-                            a.add(maxvar_q32(src[keys[e]], shift));
-                            a.fold();
-                        }
-                        a.fold();
                         const unsigned long long v[3] = {wave_sum64(a.s1), wave_sum64(a.hi),
                                                          wave_sum64(a.lo)};
                         if (l == 0) {
