@@ -426,6 +426,8 @@ def main():
     ap.add_argument("--tuning", default=None, metavar="HIST,SCATTER,SMALL",
                     help="use these launch shapes (workgroup counts, 0 = default) instead of "
                          "kd_autotune's choice")
+    ap.add_argument("--no-other-path", action="store_true",
+                    help="skip timing the build's other path (per-level / on-chip small cells)")
     ap.add_argument("--level-by-level", action="store_true",
                     help="time the plain per-level build (KD_FLAG_LEVEL_BY_LEVEL) in the main "
                          "steps, e.g. for a profiler run")
@@ -514,18 +516,19 @@ def main():
     wb = {mode: whole_build(ms, pl, d, args.workload, args.rule, mode)}
     other = "with_subtree" if args.level_by_level else "per_level"
     other_flags = 0 if args.level_by_level else kdtree.FLAG_LEVEL_BY_LEVEL
-    log(f"[bench] whole build, {other}")
-    t2 = kdtree.build(xt, subset_pool=pool_t, flags=other_flags, **kw)
-    torch.cuda.synchronize()
-    assert t2.header() == hdr
-    ms2 = time_builds(kdtree, xt, pool_t, kw, t2.workspace, t2, args.steps, args.warmup,
-                      other_flags)
-    wb[other] = whole_build(ms2, pl, d, args.workload, args.rule, other)
-    agg2 = event_pass(kdtree, xt, pool_t, kw, t2.workspace, t2, max(2, args.steps // 3),
-                      other_flags)
-    wb[other]["kernels"] = kernel_table(agg2, max(2, args.steps // 3))
-    del t2
-    torch.cuda.empty_cache()
+    if not args.no_other_path:
+        log(f"[bench] whole build, {other}")
+        t2 = kdtree.build(xt, subset_pool=pool_t, flags=other_flags, **kw)
+        torch.cuda.synchronize()
+        assert t2.header() == hdr
+        ms2 = time_builds(kdtree, xt, pool_t, kw, t2.workspace, t2, args.steps, args.warmup,
+                          other_flags)
+        wb[other] = whole_build(ms2, pl, d, args.workload, args.rule, other)
+        agg2 = event_pass(kdtree, xt, pool_t, kw, t2.workspace, t2, max(2, args.steps // 3),
+                          other_flags)
+        wb[other]["kernels"] = kernel_table(agg2, max(2, args.steps // 3))
+        del t2
+        torch.cuda.empty_cache()
 
     rules = None
     if not args.no_rules:

@@ -2164,10 +2164,11 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                         keys[e] = C.off[seg0[o]] + o;
                     }
                     __syncthreads();
-                    // (sub-cell, column) items over the waves: even one
-                    // sub-cell keeps every wave busy
+                    // (sub-cell, column) items over the waves, column by
+                    // column: the waves share a column's lines in the caches,
+                    // and even one sub-cell keeps every wave busy
                     for (uint32_t it = w; it < nq * d; it += NW) {
-                        const uint32_t q = it / d, col = it - q * d;
+                        const uint32_t col = it / nq, q = it - col * nq;
                         const uint32_t k0 = A.kid[q][0], k1 = A.kid[q][1];
                         if (k0 == NONE && k1 == NONE) continue;
                         uint32_t ka = k0 != NONE ? k0 : k1, kb = NONE;
@@ -2178,6 +2179,21 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                         }
                         const uint32_t s0 = N.start[ka], s1 = N.end[ka];
                         const KD_GLOBAL uint32_t *src = gp(T.cols[cur] + uint64_t(col) * n);
+                        // q's own sums of this column (needed when kb is
+                        // derived), requested before the gathers
+                        unsigned long long pq[3] = {0ull, 0ull, 0ull};
+                        if (kb != NONE) {
+                            const unsigned long long *ps;
+                            if (depth == level) {
+                                const uint32_t ci = C.ci[q], link = c.cell_rec[cur][ci];
+                                ps = link ? c.recstats + uint64_t((link & REC_INDEX) - 1) * rstride
+                                          : T.stats[cur] + uint64_t(c.cells[cur][ci].slot) * d * 3;
+                            } else {
+                                ps = c.recstats + uint64_t(A.rec[q] - 1) * rstride;
+                            }
+#pragma unroll
+                            for (int i = 0; i < 3; i++) pq[i] = ps[col * 3 + i];
+                        }
                         VarSums a;
                         uint32_t e = s0 + l;
                         // up to eight loads in flight per lane, eight values
@@ -2200,18 +2216,10 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                             for (int i = 0; i < 3; i++) sa[col * 3 + i] = v[i];
                             if (kb != NONE) {
                                 // q's own sums minus ka's
-                                const unsigned long long *ps;
-                                if (depth == level) {
-                                    const uint32_t ci = C.ci[q], link = c.cell_rec[cur][ci];
-                                    ps = link ? c.recstats + uint64_t((link & REC_INDEX) - 1) * rstride
-                                              : T.stats[cur] + uint64_t(c.cells[cur][ci].slot) * d * 3;
-                                } else {
-                                    ps = c.recstats + uint64_t(A.rec[q] - 1) * rstride;
-                                }
                                 unsigned long long *sb =
                                     c.recstats + uint64_t(N.rec[kb] - 1) * rstride;
 #pragma unroll
-                                for (int i = 0; i < 3; i++) sb[col * 3 + i] = ps[col * 3 + i] - v[i];
+                                for (int i = 0; i < 3; i++) sb[col * 3 + i] = pq[i] - v[i];
                             }
                         }
                     }
@@ -2222,15 +2230,26 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                         const __int128 nc = N.end[k] - N.start[k];
                         __int128 best = -1;
                         uint32_t bd = 0;
-                        for (uint32_t col = 0; col < d; col++) {
-                            const __int128 S1 = (long long)sk[col * 3];
-                            const __int128 S2 =
-                                (__int128)(long long)sk[col * 3 + 1] * ((__int128)1 << 32) +
-                                (__int128)(long long)sk[col * 3 + 2];
-                            const __int128 V = nc * S2 - S1 * S1;
-                            if (V > best) {
-                                best = V;
-                                bd = col;
+                        for (uint32_t c0 = 0; c0 < d; c0 += 8) {
+                            // eight columns' sums requested at once
+                            unsigned long long x[8][3];
+#pragma unroll
+                            for (int j = 0; j < 8; j++)
+#pragma unroll
+                                for (int i = 0; i < 3; i++)
+                                    x[j][i] = c0 + j < d ? sk[(c0 + j) * 3 + i] : 0ull;
+#pragma unroll
+                            for (int j = 0; j < 8; j++) {
+                                if (c0 + j >= d) break;
+                                const __int128 S1 = (long long)x[j][0];
+                                const __int128 S2 =
+                                    (__int128)(long long)x[j][1] * ((__int128)1 << 32) +
+                                    (__int128)(long long)x[j][2];
+                                const __int128 V = nc * S2 - S1 * S1;
+                                if (V > best) {
+                                    best = V;
+                                    bd = c0 + j;
+                                }
                             }
                         }
                         N.dim[k] = bd;
