@@ -87,7 +87,7 @@ __global__ __launch_bounds__(NT) void k_gmom(const float *pts, uint64_t n, uint6
         if (active) {
             for (uint32_t i = 0; i < m; i++) {
                 const double qa = P >= 3 ? q[0][i][a] : 1.0;
-                const double qb = P >= 2 ? q[P - 2][i][b] : 1.0;
+                const double qb = P >= 2 ? q[P >= 2 ? P - 2 : 0][i][b] : 1.0;
                 const double qab = qa * qb;
                 const double2 *row = reinterpret_cast<const double2 *>(q[P - 1][i]);
 #pragma unroll

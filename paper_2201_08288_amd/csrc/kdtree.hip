@@ -22,7 +22,9 @@
 // Children that stop being split are written straight to their final place
 // in the output permutation (and the optional permuted points).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -2940,6 +2942,17 @@ uint32_t grid_for(uint64_t work, uint32_t cap = 65535u) {
     return uint32_t(work < cap ? work : cap);
 }
 
+// roctx ranges on the host timeline (a profiler shows what each enqueue
+// belongs to: the build, each level, each kernel class).
+struct Range {
+    explicit Range(const char *m) { roctxRangePushA(m); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
+const char *const PROF_NAMES[KD_PROF_KINDS] = {"ingest", "select", "pick",  "count",
+                                               "big_scatter", "small", "emit", "other"};
+
 // Per-kernel-class timing with HIP events on the build's stream (only when
 // the caller asks for a profile).
 struct Prof {
@@ -2956,6 +2969,7 @@ struct Prof {
     }
     template <class F>
     void run(int kind, uint64_t points, uint64_t bytes, F &&launch) {
+        const Range phase(PROF_NAMES[kind]);
         if (!p) {
             launch();
             return;
@@ -3058,6 +3072,7 @@ kd_tuning current_tuning() {
 
 kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, void *workspace,
                     uint64_t ws_bytes, hipStream_t st, kd_profile *prof, const kd_tuning &tune) {
+    const Range whole(ntrees == 1 ? "kd_build" : "kd_build_batched");
     std::vector<uint64_t> n(ntrees), cap(ntrees);
     std::vector<uint32_t> d(ntrees);
     uint64_t total_points = 0, sum_d = 0;
@@ -3260,6 +3275,9 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
             tail = level >= likely;
         }
         levels_run++;
+        char level_name[32];
+        snprintf(level_name, sizeof(level_name), "level %u%s", level, tail ? " (tail)" : "");
+        const Range level_range(level_name);
         // launch shape: the bound's workgroups, or a few in tail shape
         auto G = [&](uint64_t work, uint32_t cap) {
             const uint32_t g = grid_for(work, cap);
