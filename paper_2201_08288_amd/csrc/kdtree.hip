@@ -331,8 +331,11 @@ __global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level, uint32
             __int128 best = -1;
             uint32_t bd = 0;
             for (uint32_t k = 0; k < T.d; k++) {
+                // S2 = hi * 2^32 + lo; a child's parts may be its parent's
+                // minus its sibling's, so each part is read as signed
                 const long long s1 = (long long)st[3 * k];
-                const __int128 s2 = ((__int128)st[3 * k + 1] << 32) + (__int128)st[3 * k + 2];
+                const __int128 s2 = (__int128)(long long)st[3 * k + 1] * ((__int128)1 << 32) +
+                                    (__int128)(long long)st[3 * k + 2];
                 const __int128 V = n_c * s2 - (__int128)s1 * (__int128)s1;
                 if (V > best) {
                     best = V;
@@ -384,6 +387,19 @@ __device__ __forceinline__ void finish_cell(const Ctx &c, uint32_t level, uint32
         r.nl = n_c;
         r.flags = RES_LEFT_LEAF | RES_RIGHT_LEAF;
     }
+}
+
+// Largest-variance key, large cells: the child whose per-coordinate sums the
+// scatter adds up (0 left, 1 right, -1 none).  When both children go on it
+// is the smaller; the emit step then writes the other's sums as the parent's
+// minus it (exact integers).
+__device__ __forceinline__ int vsum_side(uint32_t flags, uint32_t nl, uint32_t n_c) {
+    if (!(flags & RES_SPLIT)) return -1;
+    const bool ll = flags & RES_LEFT_LEAF, rl = flags & RES_RIGHT_LEAF;
+    if (ll && rl) return -1;
+    if (ll) return 1;
+    if (rl) return 0;
+    return nl <= n_c - nl ? 0 : 1;
 }
 
 // LDS index of staged element i: one pad word per 32 keeps a thread's run of
@@ -992,7 +1008,8 @@ __global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level) {
                 D.dim = r.dim;
                 D.tree = cl.tree;
                 D.li = li;
-                D.pad[0] = D.pad[1] = D.pad[2] = 0;
+                D.pad[0] = uint32_t(vsum_side(r.flags, r.nl, n_c));  // 0xffffffff: none
+                D.pad[1] = D.pad[2] = 0;
                 c.tiles[cl.tile0 + k] = D;
             }
             base += tot;
@@ -1006,11 +1023,11 @@ __global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level) {
 // staged key column; each column (and the permutation) is then permuted in
 // LDS and written as two contiguous runs, the left and right children's.
 template <bool MAXVAR>
-__global__ __launch_bounds__(NT, MAXVAR ? 3 : 4) void k_big_scatter(Ctx c, uint32_t level) {
+__global__ __launch_bounds__(NT, 4) void k_big_scatter(Ctx c, uint32_t level) {
     __shared__ uint32_t stage0[PADDED];  // staged keys / ranks, then a column buffer
     __shared__ uint32_t stage1[TILE];
     __shared__ uint32_t sh[NW + 1];
-    __shared__ unsigned long long vacc[MAXVAR ? 16 : 1][6];  // a group of 16 columns
+    __shared__ unsigned long long vacc[MAXVAR ? 16 : 1][3];  // a group of 16 columns
     const uint32_t cur = level & 1, nxt = cur ^ 1;
     const uint32_t ntiles = c.info[level].num_tiles;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -1063,9 +1080,11 @@ __global__ __launch_bounds__(NT, MAXVAR ? 3 : 4) void k_big_scatter(Ctx c, uint3
             nleft_tile = cnt;
         }
         const int shift = MAXVAR ? maxvar_shift(c.ts[D.tree].maxabs) : 0;
-        const bool stats = MAXVAR && (D.flags & RES_SPLIT) && !(lleaf && rleaf);
+        // the one child whose sums this tile adds up (see vsum_side)
+        const int vside = MAXVAR ? int(D.pad[0]) : -1;
+        const bool stats = MAXVAR && vside >= 0;
         if (stats)
-            for (uint32_t i = threadIdx.x; i < 16 * 6; i += NT) (&vacc[0][0])[i] = 0;
+            for (uint32_t i = threadIdx.x; i < 16 * 3; i += NT) (&vacc[0][0])[i] = 0;
         __syncthreads();
         // column k is staged while column k + 1 is on its way
         uint32_t vn[PER_THREAD];
@@ -1103,7 +1122,7 @@ __global__ __launch_bounds__(NT, MAXVAR ? 3 : 4) void k_big_scatter(Ctx c, uint3
             KD_GLOBAL uint32_t *lout =
                 gp(is_perm ? T.out_perm : (T.pts_out ? T.pts_out + uint64_t(k) * n : nullptr));
             const bool kstats = stats && !is_perm;
-            VarSums L, R;
+            VarSums V;
             // left run: staged [0, nleft_tile) -> D.lpos; right run -> D.rpos
             KD_GLOBAL uint32_t *ldst = lleaf ? lout : lnext;
             if (ldst) ldst += D.lpos;
@@ -1114,10 +1133,10 @@ __global__ __launch_bounds__(NT, MAXVAR ? 3 : 4) void k_big_scatter(Ctx c, uint3
                     if (i < nleft_tile) {
                         const uint32_t val = sg[i];
                         if (ldst) ldst[i] = val;
-                        if (kstats && !lleaf) L.add(maxvar_q32(val, shift));
+                        if (kstats && vside == 0) V.add(maxvar_q32(val, shift));
                     }
                 }
-                L.fold();
+                V.fold();
             }
             KD_GLOBAL uint32_t *rdst = rleaf ? lout : lnext;
             if (rdst) rdst += D.rpos;
@@ -1128,26 +1147,26 @@ __global__ __launch_bounds__(NT, MAXVAR ? 3 : 4) void k_big_scatter(Ctx c, uint3
                     if (i < cnt) {
                         const uint32_t val = sg[i];
                         if (rdst) rdst[i - nleft_tile] = val;
-                        if (kstats && !rleaf) R.add(maxvar_q32(val, shift));
+                        if (kstats && vside == 1) V.add(maxvar_q32(val, shift));
                     }
                 }
-                R.fold();
+                V.fold();
             }
             if (kstats) {
                 // wave sums into the workgroup's accumulators of this column
-                unsigned long long x[6] = {L.s1, L.hi, L.lo, R.s1, R.hi, R.lo};
+                unsigned long long x[3] = {V.s1, V.hi, V.lo};
 #pragma unroll
-                for (int q = 0; q < 6; q++) x[q] = wave_scan64(x[q]);
+                for (int q = 0; q < 3; q++) x[q] = wave_scan64(x[q]);
                 if (lane() == WAVE - 1)
 #pragma unroll
-                    for (int q = 0; q < 6; q++) atomicAdd(&vacc[k & 15][q], x[q]);
+                    for (int q = 0; q < 3; q++) atomicAdd(&vacc[k & 15][q], x[q]);
                 if ((k & 15) == 15 || k + 1 == d) {
                     __syncthreads();
                     const uint32_t k0 = k & ~15u;
-                    for (uint32_t i = threadIdx.x; i < 16 * 6; i += NT) {
-                        const uint32_t kk = k0 + i / 6, q = i % 6, side = q / 3;
-                        if (kk < d && !(side ? rleaf : lleaf))
-                            atomicAdd(T.stats[nxt] + (uint64_t(2 * D.li + side) * d + kk) * 3 + q % 3,
+                    for (uint32_t i = threadIdx.x; i < 16 * 3; i += NT) {
+                        const uint32_t kk = k0 + i / 3, q = i % 3;
+                        if (kk < d)
+                            atomicAdd(T.stats[nxt] + (uint64_t(2 * D.li + vside) * d + kk) * 3 + q,
                                       (&vacc[0][0])[i]);
                         (&vacc[0][0])[i] = 0;
                     }
@@ -2479,6 +2498,16 @@ __device__ __forceinline__ void emit_cell(const Ctx &c, uint32_t level, uint32_t
         T.node_end[left] = mid;
         T.node_begin[left + 1] = mid;
         T.node_end[left + 1] = cl.end;
+    }
+    if (c.key_rule == KD_KEY_MAXVAR && cl.big != NONE &&
+        !(r.flags & (RES_LEFT_LEAF | RES_RIGHT_LEAF))) {
+        // the large cell's scatter summed one child; the other is the
+        // parent's sums minus it (both children go on)
+        const int side = vsum_side(r.flags, r.nl, cl.end - cl.begin);
+        const unsigned long long *ps = T.stats[cur] + uint64_t(cl.slot) * T.d * 3;
+        const unsigned long long *sc = T.stats[nxt] + uint64_t(2 * li + side) * T.d * 3;
+        unsigned long long *so = T.stats[nxt] + uint64_t(2 * li + (side ^ 1)) * T.d * 3;
+        for (uint32_t k = 0; k < 3 * T.d; k++) so[k] = ps[k] - sc[k];
     }
     // small cells resolved ahead stay out of the small-point numbering
     uint32_t slot = pre[1], tile = pre[2], big = pre[5], voff = pre[3] - pre[4] - pre[8];
