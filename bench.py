@@ -177,9 +177,10 @@ def gpu_gmm(n, d, gen, components=10, box=5.0, sigma=0.5):
     return (means[comp] + sigma * z).to(torch.float32).t().contiguous()
 
 
-def bench_other_workload(name, rules, steps=5, warmup=1):
+def bench_other_workload(name, rules, steps=5, warmup=1, queries=False):
     """Build time and whole-build fraction of another workload under each rule
-    (kd_build, default launch shapes)."""
+    (kd_build, default launch shapes); with queries, the kNN and box queries
+    on its EXACT tree."""
     import numpy as np
     import torch
 
@@ -200,6 +201,8 @@ def bench_other_workload(name, rules, steps=5, warmup=1):
         res.update({"depth": hdr["depth"], "point_levels": hdr["point_levels"],
                     "point_levels_per_s": hdr["point_levels"] / (ms * 1e-3)})
         out[rule] = res
+        if queries and rule == "exact":
+            out["queries"] = bench_queries(tree, xt)
         del tree
         torch.cuda.empty_cache()
     return out
@@ -548,7 +551,7 @@ def main():
             torch.cuda.empty_cache()
 
     queries = None
-    if not args.no_queries:
+    if not args.no_queries and (args.no_scale or args.workload == "scale_n2^24_d8"):
         log("[bench] queries (kNN, boxes)")
         queries = bench_queries(tree, xt)
 
@@ -564,8 +567,9 @@ def main():
     kdtree.set_tuning()  # everything below runs the default launch shapes
     scale = None
     if not args.no_scale and args.workload != "scale_n2^24_d8":
-        log("[bench] scale workload n=2^24 d=8, every rule")
-        scale = bench_other_workload("scale_n2^24_d8", list(RULES))
+        log("[bench] scale workload n=2^24 d=8, every rule (and queries on its tree)")
+        scale = bench_other_workload("scale_n2^24_d8", list(RULES), queries=not args.no_queries)
+        queries = scale.pop("queries", None)
 
     glob = None
     if not args.no_global:
