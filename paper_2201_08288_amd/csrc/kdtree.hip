@@ -458,7 +458,10 @@ __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
             const uint32_t i = v.tb + j * NT + threadIdx.x;
-            u[j] = i < v.te ? key_of_bits(col[i]) : 0u;
+            // the index is clamped rather than the load made conditional: a
+            // load under a condition was waited for before the next was
+            // issued, one load in flight instead of sixteen
+            u[j] = key_of_bits(col[min(i, v.te - 1)]);  // used only where i < v.te
         }
         // a thread's keys often share a digit (the leading digits of a cell):
         // one atomic per run of equal digits
@@ -582,7 +585,7 @@ __global__ __launch_bounds__(NT) void k_big_minmax(Ctx c, uint32_t level) {
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
             const uint32_t i = v.tb + j * NT + threadIdx.x;
-            u[j] = i < v.te ? key_of_bits(col[i]) : NONE;
+            u[j] = key_of_bits(col[min(i, v.te - 1)]);  // used only where i < v.te
         }
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
@@ -658,7 +661,7 @@ __global__ __launch_bounds__(NT) void k_big_moments(Ctx c, uint32_t level) {
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
                 const uint32_t i = v.tb + j * NT + threadIdx.x;
-                u[j] = i < v.te ? key_of_bits(col[i]) : 0u;
+                u[j] = key_of_bits(col[min(i, v.te - 1)]);  // used only where i < v.te
             }
             // a tile's sums per thread fit 32 bits (16 terms of at most 2^24)
             static_assert(PER_THREAD * (1ll << 24) < (1ll << 31), "per-tile sums fit int32");
@@ -866,7 +869,7 @@ __global__ __launch_bounds__(NT) void k_seg_hist(Ctx c, uint32_t level, uint32_t
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
                 const uint32_t x = i0 + j * NT + threadIdx.x;
-                u[j] = x < e ? key_of_bits(g[x]) : 0u;
+                u[j] = key_of_bits(g[min(x, e - 1)]);  // used only where x < e
             }
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
@@ -932,7 +935,7 @@ __global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level) {
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
             const uint32_t i = v.tb + j * NT + threadIdx.x;
-            u[j] = i < v.te ? key_of_bits(col[i]) : 0u;
+            u[j] = key_of_bits(col[min(i, v.te - 1)]);  // used only where i < v.te
         }
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
@@ -1043,7 +1046,7 @@ __global__ __launch_bounds__(NT, 4) void k_big_scatter(Ctx c, uint32_t level) {
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
                 const uint32_t i = j * NT + threadIdx.x;
-                u[j] = i < cnt ? key_of_bits(col[i]) : 0u;
+                u[j] = key_of_bits(col[min(i, cnt - 1)]);  // used only where i < cnt
             }
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
@@ -1093,7 +1096,7 @@ __global__ __launch_bounds__(NT, 4) void k_big_scatter(Ctx c, uint32_t level) {
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
                 const uint32_t i = j * NT + threadIdx.x;
-                vn[j] = i < cnt ? src[i] : 0u;
+                vn[j] = src[min(i, cnt - 1)];  // used only where i < cnt
             }
         }
         for (uint32_t k = 0; k <= d; k++) {
@@ -1108,7 +1111,7 @@ __global__ __launch_bounds__(NT, 4) void k_big_scatter(Ctx c, uint32_t level) {
 #pragma unroll
                 for (int j = 0; j < PER_THREAD; j++) {
                     const uint32_t i = j * NT + threadIdx.x;
-                    if (i < cnt) vn[j] = src[i];
+                    vn[j] = src[min(i, cnt - 1)];
                 }
             }
 #pragma unroll
