@@ -1999,21 +1999,24 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                 SubTable<SC, CH> &A = Q[qa];
                 SubTable<SC, CH> &N = Q[qa ^ 1];
                 const uint32_t nq = A.count;
-                // keys of the active slots, read through the numbers they hold
+                // keys of the active slots, read through the numbers they hold;
+                // every load is issued (no branch), idle slots all reading
+                // the chunk's first place
                 {
+                    const KD_GLOBAL uint32_t *cols = gp(T.cols[cur]);
+                    const uint64_t idle = C.off[seg0[0]];
                     uint32_t u[PER_THREAD];
+                    bool live[PER_THREAD];
 #pragma unroll
                     for (int jj = 0; jj < PER_THREAD; jj++) {
-                        const uint32_t e = jj * NT + threadIdx.x;
-                        u[jj] = 0;
-                        if (e < tot) {
-                            const uint32_t q = seg[e];
-                            if (q != SEG_LEAF) {
-                                const uint32_t o = lp[e];
-                                u[jj] = gp(T.cols[cur] + uint64_t(A.dim[q]) * n)[C.off[seg0[o]] + o];
-                            }
-                        }
+                        const uint32_t e = jj * NT + threadIdx.x, ec = min(e, tot - 1);
+                        const uint32_t q = seg[ec], o = lp[ec];
+                        live[jj] = e < tot && q != SEG_LEAF;
+                        const uint64_t at = uint64_t(A.dim[live[jj] ? q : 0u]) * n + C.off[seg0[o]] + o;
+                        u[jj] = cols[live[jj] ? at : idle];
                     }
+#pragma unroll
+                    for (int jj = 0; jj < PER_THREAD; jj++) u[jj] = live[jj] ? u[jj] : 0u;
 #pragma unroll
                     for (int jj = 0; jj < PER_THREAD; jj++) {
                         const uint32_t e = jj * NT + threadIdx.x;
@@ -2219,17 +2222,23 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                             for (int i = 0; i < 3; i++) pq[i] = ps[col * 3 + i];
                         }
                         VarSums a;
-                        uint32_t e = s0 + l;
-                        // up to eight loads in flight per lane, eight values
-                        // between folds (no wrap)
-                        for (; e < s1; e += 8 * WAVE) {
-                            uint32_t xv[8];
+                        // eight loads in flight per lane, eight values between
+                        // folds (no wrap): each batch of 8 * WAVE slots reads
+                        // its places first and then issues every load, the
+                        // slots past the child's end reading its last place
+                        // again and adding zero (no branch: a load under a
+                        // condition is issued only after the others complete)
+                        for (uint32_t eb = s0; eb < s1; eb += 8 * WAVE) {
+                            uint32_t kx[8], xv[8];
 #pragma unroll
-                            for (int j = 0; j < 8; j++)
-                                xv[j] = e + j * WAVE < s1 ? src[keys[e + j * WAVE]] : 0u;
+                            for (int j = 0; j < 8; j++) kx[j] = keys[min(eb + j * WAVE + l, s1 - 1)];
 #pragma unroll
-                            for (int j = 0; j < 8; j++)
-                                if (e + j * WAVE < s1) a.add(maxvar_q32(xv[j], shift));
+                            for (int j = 0; j < 8; j++) xv[j] = src[kx[j]];
+#pragma unroll
+                            for (int j = 0; j < 8; j++) {
+                                const int q = maxvar_q32(xv[j], shift);
+                                a.add(eb + j * WAVE + l < s1 ? q : 0);
+                            }
                             a.fold();
                         }
                         const unsigned long long v[3] = {wave_sum64(a.s1), wave_sum64(a.hi),
@@ -2324,7 +2333,7 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                 const KD_GLOBAL uint32_t *src = gp(T.cols[cur]);
 #pragma unroll
                 for (int jj = 0; jj < PER_THREAD; jj++)
-                    vn[jj] = jj * NT + threadIdx.x < tot ? src[ps[jj]] : 0u;
+                    vn[jj] = src[ps[jj]];  // place 0 where the slot is unused
             }
             for (uint32_t col = 0; col <= d; col++) {
                 uint32_t v[PER_THREAD];
@@ -2335,7 +2344,7 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                         gp(col + 1 == d ? T.perm[cur] : T.cols[cur] + uint64_t(col + 1) * n);
 #pragma unroll
                     for (int jj = 0; jj < PER_THREAD; jj++)
-                        if (jj * NT + threadIdx.x < tot) vn[jj] = src[ps[jj]];
+                        vn[jj] = src[ps[jj]];
                 }
 #pragma unroll
                 for (int jj = 0; jj < PER_THREAD; jj++) {
