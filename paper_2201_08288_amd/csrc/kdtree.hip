@@ -86,6 +86,7 @@ struct Ctx {
     // stride recstats_stride * 3 words
     unsigned long long *recstats;
     uint32_t recstats_stride;
+    uint32_t max_d;  // the largest dimension over the build's trees
     const uint32_t *pool;
     uint32_t pool_entries;
     unsigned long long seed;
@@ -330,16 +331,26 @@ __global__ __launch_bounds__(NT) void k_level_init(Ctx c, uint32_t level, uint32
             const __int128 n_c = cl.end - cl.begin;
             __int128 best = -1;
             uint32_t bd = 0;
-            for (uint32_t k = 0; k < T.d; k++) {
-                // S2 = hi * 2^32 + lo; a child's parts may be its parent's
-                // minus its sibling's, so each part is read as signed
-                const long long s1 = (long long)st[3 * k];
-                const __int128 s2 = (__int128)(long long)st[3 * k + 1] * ((__int128)1 << 32) +
-                                    (__int128)(long long)st[3 * k + 2];
-                const __int128 V = n_c * s2 - (__int128)s1 * (__int128)s1;
-                if (V > best) {
-                    best = V;
-                    bd = k;
+            for (uint32_t k0 = 0; k0 < T.d; k0 += 8) {
+                // eight columns' sums requested at once
+                unsigned long long x[8][3];
+#pragma unroll
+                for (int j = 0; j < 8; j++)
+#pragma unroll
+                    for (int i = 0; i < 3; i++) x[j][i] = st[3 * min(k0 + j, T.d - 1) + i];
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    if (k0 + j >= T.d) break;
+                    // S2 = hi * 2^32 + lo; a child's parts may be its parent's
+                    // minus its sibling's, so each part is read as signed
+                    const long long s1 = (long long)x[j][0];
+                    const __int128 s2 = (__int128)(long long)x[j][1] * ((__int128)1 << 32) +
+                                        (__int128)(long long)x[j][2];
+                    const __int128 V = n_c * s2 - (__int128)s1 * (__int128)s1;
+                    if (V > best) {
+                        best = V;
+                        bd = k0 + j;
+                    }
                 }
             }
             r.dim = bd;
@@ -391,7 +402,7 @@ __device__ __forceinline__ void finish_cell(const Ctx &c, uint32_t level, uint32
 
 // Largest-variance key, large cells: the child whose per-coordinate sums the
 // scatter adds up (0 left, 1 right, -1 none).  When both children go on it
-// is the smaller; the emit step then writes the other's sums as the parent's
+// is the smaller; k_big_derive then writes the other's sums as the parent's
 // minus it (exact integers).
 __device__ __forceinline__ int vsum_side(uint32_t flags, uint32_t nl, uint32_t n_c) {
     if (!(flags & RES_SPLIT)) return -1;
@@ -1177,6 +1188,31 @@ __global__ __launch_bounds__(NT, 4) void k_big_scatter(Ctx c, uint32_t level) {
             }
         }
         __syncthreads();
+    }
+}
+
+// Largest-variance key, large cells whose children both go on: the child
+// the scatter did not sum gets the cell's sums minus the summed child's
+// (exact integers), one thread per (cell, word) so that every load of the
+// level is in flight at once.
+__global__ __launch_bounds__(NT) void k_big_derive(Ctx c, uint32_t level) {
+    const uint32_t cur = level & 1, nxt = cur ^ 1;
+    const uint32_t nbig = c.info[level].num_big;
+    const uint32_t wmax = 3 * c.max_d;
+    for (uint64_t i = uint64_t(blockIdx.x) * NT + threadIdx.x; i < uint64_t(nbig) * wmax;
+         i += uint64_t(gridDim.x) * NT) {
+        const uint32_t b = uint32_t(i / wmax), k = uint32_t(i - uint64_t(b) * wmax);
+        const uint32_t ci = c.big_list[b];
+        const Cell cl = c.cells[cur][ci];
+        const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
+        if (k >= 3 * T.d) continue;
+        const CellRes r = c.res[ci];
+        if (!(r.flags & RES_SPLIT) || (r.flags & (RES_LEFT_LEAF | RES_RIGHT_LEAF))) continue;
+        const int side = vsum_side(r.flags, r.nl, cl.end - cl.begin);
+        const uint32_t li = ci - c.ts[cl.tree].first[cur];
+        const uint64_t w3 = 3 * T.d;
+        T.stats[nxt][(2 * li + (side ^ 1)) * w3 + k] =
+            T.stats[cur][uint64_t(cl.slot) * w3 + k] - T.stats[nxt][(2 * li + side) * w3 + k];
     }
 }
 
@@ -2270,7 +2306,7 @@ __global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void
                             for (int j = 0; j < 8; j++)
 #pragma unroll
                                 for (int i = 0; i < 3; i++)
-                                    x[j][i] = c0 + j < d ? sk[(c0 + j) * 3 + i] : 0ull;
+                                    x[j][i] = sk[min(c0 + j, d - 1) * 3 + i];
 #pragma unroll
                             for (int j = 0; j < 8; j++) {
                                 if (c0 + j >= d) break;
@@ -2510,16 +2546,6 @@ __device__ __forceinline__ void emit_cell(const Ctx &c, uint32_t level, uint32_t
         T.node_end[left] = mid;
         T.node_begin[left + 1] = mid;
         T.node_end[left + 1] = cl.end;
-    }
-    if (c.key_rule == KD_KEY_MAXVAR && cl.big != NONE &&
-        !(r.flags & (RES_LEFT_LEAF | RES_RIGHT_LEAF))) {
-        // the large cell's scatter summed one child; the other is the
-        // parent's sums minus it (both children go on)
-        const int side = vsum_side(r.flags, r.nl, cl.end - cl.begin);
-        const unsigned long long *ps = T.stats[cur] + uint64_t(cl.slot) * T.d * 3;
-        const unsigned long long *sc = T.stats[nxt] + uint64_t(2 * li + side) * T.d * 3;
-        unsigned long long *so = T.stats[nxt] + uint64_t(2 * li + (side ^ 1)) * T.d * 3;
-        for (uint32_t k = 0; k < 3 * T.d; k++) so[k] = ps[k] - sc[k];
     }
     // small cells resolved ahead stay out of the small-point numbering
     uint32_t slot = pre[1], tile = pre[2], big = pre[5], voff = pre[3] - pre[4] - pre[8];
@@ -3211,6 +3237,8 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     c.rec_cap = uint32_t(L.rec_cap);
     c.recstats = reinterpret_cast<unsigned long long *>(ws + L.recstats);
     c.recstats_stride = uint32_t(L.recstats_stride);
+    c.max_d = 0;
+    for (uint32_t t = 0; t < ntrees; t++) c.max_d = std::max(c.max_d, ht[t].d);
     c.pool = p->subset_pool;
     c.pool_entries = p->pool_entries;
     c.seed = p->seed;
@@ -3386,10 +3414,13 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                                    level);
             });
             P.run(KD_PROF_BIG_SCATTER, bigp, scatter_avg_bpp * bigp, [&] {
-                if (maxvar)
+                if (maxvar) {
                     hipLaunchKernelGGL(k_big_scatter<true>, G(ntl, tile_grid), dim3(NT), 0,
                                        st, c, level);
-                else
+                    const uint64_t words = uint64_t(nbig) * 3 * c.max_d;
+                    hipLaunchKernelGGL(k_big_derive, G(uint32_t((words + NT - 1) / NT), 4096),
+                                       dim3(NT), 0, st, c, level);
+                } else
                     hipLaunchKernelGGL(k_big_scatter<false>, G(ntl, tile_grid), dim3(NT),
                                        0, st, c, level);
             });
