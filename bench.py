@@ -426,9 +426,9 @@ def main():
     ap.add_argument("--no-global", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch shapes instead of kd_autotune's choice")
-    ap.add_argument("--tuning", default=None, metavar="HIST,SCATTER,SMALL",
-                    help="use these launch shapes (workgroup counts, 0 = default) instead of "
-                         "kd_autotune's choice")
+    ap.add_argument("--tuning", default=None, metavar="HIST,SCATTER,SMALL[,DIGIT]",
+                    help="use these launch shapes (workgroup counts, 0 = default) and digit "
+                         "width (11 or 8, 0 = 11) instead of kd_autotune's choice")
     ap.add_argument("--no-other-path", action="store_true",
                     help="skip timing the build's other path (per-level / on-chip small cells)")
     ap.add_argument("--level-by-level", action="store_true",
@@ -477,8 +477,7 @@ def main():
     main_flags = kdtree.FLAG_LEVEL_BY_LEVEL if args.level_by_level else 0
     tuning = kdtree.get_tuning()
     if args.tuning is not None:
-        h, sc, sm = (int(v) for v in args.tuning.split(","))
-        kdtree.set_tuning(h, sc, sm)
+        kdtree.set_tuning(*(int(v) for v in args.tuning.split(",")))
         tuning = kdtree.get_tuning()
     elif not args.no_autotune:
         log("[bench] autotune")

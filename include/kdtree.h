@@ -292,17 +292,21 @@ typedef struct kd_tuning {
     uint32_t hist_blocks;      /* workgroups of a large-cell digit pass            */
     uint32_t scatter_blocks;   /* workgroups of the large-cell count and scatter   */
     uint32_t small_blocks;     /* workgroups of the small-cell kernel              */
-    uint32_t reserved;
+    uint32_t digit_bits;       /* EXACT large-cell digit width: 11 (three passes)
+                                  or 8 (four); 0 = 11; anything else: KD_EINVAL  */
 } kd_tuning;
 
-/* Process-wide launch shapes used by kd_build and kd_build_batched (host
- * only; the library's only global state).  Set them between builds, not
- * while builds run on other threads.                                        */
+/* Process-wide launch shapes and digit width used by kd_build and
+ * kd_build_batched (host only).  Set them between builds, not while builds
+ * run on other threads.  None of them changes the tree.  KD_EINVAL for a
+ * digit width other than 0, 8 or 11.                                        */
 kd_status kd_set_tuning(const kd_tuning *t);
 kd_status kd_get_tuning(kd_tuning *t);
 
-/* Time the build of the given input under a small set of launch shapes
- * (one field at a time, 3 timed builds each, on `stream`), check that every
+/* Time the build of the given input under a small set of launch shapes and
+ * digit widths (one field at a time: digit-pass, scatter and small-cell
+ * workgroup counts, then 11- or 8-bit digits; 3 timed builds each, on
+ * `stream`), check that every
  * shape yields the same tree as the current one, keep the fastest with
  * kd_set_tuning and return it in *best.  Arguments as for kd_build; `out`
  * and `workspace` are overwritten.  Returns KD_EDEVICE if a shape gave a

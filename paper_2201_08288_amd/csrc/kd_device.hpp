@@ -18,18 +18,22 @@ constexpr int SMALL_MAX = 4096;      // cells up to this size are done by one wo
 constexpr int RBITS = 8;             // radix-select digit width inside one workgroup
 constexpr int NBINS = 1 << RBITS;
 constexpr int RPASSES = 32 / RBITS;
-// large cells: device-wide passes of BIG_DIGIT-bit digits, most significant
-// first (the last may be narrower)
-#ifndef KD_BIG_DIGIT
-#define KD_BIG_DIGIT 11
-#endif
-constexpr int BIG_DIGIT = KD_BIG_DIGIT;
-constexpr int BIG_PASSES = (32 + BIG_DIGIT - 1) / BIG_DIGIT;
-constexpr int BIG_BINS = 1 << BIG_DIGIT;
-__host__ __device__ constexpr int big_shift(int pass) {
-    return 32 - BIG_DIGIT * (pass + 1) > 0 ? 32 - BIG_DIGIT * (pass + 1) : 0;
-}
-__host__ __device__ constexpr int big_bits(int pass) { return 32 - BIG_DIGIT * pass - big_shift(pass); }
+// large cells: device-wide passes of D-bit digits, most significant first
+// (the last may be narrower).  D is a launch choice (kd_tuning.digit_bits):
+// 11 (three passes) by default, or 8 (four passes, smaller histograms).
+// Every cell's histogram has BIG_BINS_MAX bins of room.
+constexpr int BIG_DIGIT_DEFAULT = 11;
+constexpr int BIG_BINS_MAX = 1 << 11;
+template <int D>
+struct BigDigits {
+    static_assert(D >= 8 && D <= 11, "histogram rows of 256 bins, at most BIG_BINS_MAX");
+    static constexpr int PASSES = (32 + D - 1) / D;
+    static constexpr int BINS = 1 << D;
+    __host__ __device__ static constexpr int shift(int pass) {
+        return 32 - D * (pass + 1) > 0 ? 32 - D * (pass + 1) : 0;
+    }
+    __host__ __device__ static constexpr int bits(int pass) { return 32 - D * pass - shift(pass); }
+};
 constexpr int MAX_SUBSETS = 4096;
 constexpr int MAX_LEVELS = 128;
 constexpr uint32_t NONE = 0xffffffffu;

@@ -437,24 +437,26 @@ __device__ __forceinline__ TileView tile_view(const Ctx &c, uint32_t cur, uint32
 
 // EXACT, large cells: digit histograms of a run of consecutive tiles in LDS,
 // added into the cell's histogram whenever the run moves to another cell.
+template <int D>
 __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t pass) {
-    __shared__ uint32_t h[BIG_BINS];
+    using DG = BigDigits<D>;
+    __shared__ uint32_t h[DG::BINS];
     __shared__ uint32_t s_cell;
     const uint32_t cur = level & 1;
     const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
-    const int shift = big_shift(pass);
-    const uint32_t dmask = (1u << big_bits(pass)) - 1u;
-    const uint32_t pmask = pass == 0 ? 0u : (~0u << (shift + big_bits(pass)));
+    const int shift = DG::shift(pass);
+    const uint32_t dmask = (1u << DG::bits(pass)) - 1u;
+    const uint32_t pmask = pass == 0 ? 0u : (~0u << (shift + DG::bits(pass)));
     const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
     const uint32_t t0 = blockIdx.x * per, t1 = min(t0 + per, ntiles);
-    for (int b = threadIdx.x; b < BIG_BINS; b += NT) h[b] = 0;
+    for (int b = threadIdx.x; b < DG::BINS; b += NT) h[b] = 0;
     uint32_t big = NONE;
     for (uint32_t t = t0; t < t1; t++) {
         const TileView v = tile_view(c, cur, ncells, t, &s_cell);
         if (v.cl.big != big) {
             if (big != NONE) {
-                uint32_t *gh = c.hist + uint64_t(big) * BIG_BINS;
-                for (int b = threadIdx.x; b < BIG_BINS; b += NT) {
+                uint32_t *gh = c.hist + uint64_t(big) * BIG_BINS_MAX;
+                for (int b = threadIdx.x; b < DG::BINS; b += NT) {
                     if (h[b]) atomicAdd(&gh[b], h[b]);
                     h[b] = 0;
                 }
@@ -494,8 +496,8 @@ __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t
         __syncthreads();
     }
     if (big != NONE) {
-        uint32_t *gh = c.hist + uint64_t(big) * BIG_BINS;
-        for (int b = threadIdx.x; b < BIG_BINS; b += NT)
+        uint32_t *gh = c.hist + uint64_t(big) * BIG_BINS_MAX;
+        for (int b = threadIdx.x; b < DG::BINS; b += NT)
             if (h[b]) atomicAdd(&gh[b], h[b]);
     }
 }
@@ -505,16 +507,18 @@ __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t
 // 256 bins, lane l holding bins 4l .. 4l+3 of each row, so that every load and
 // store of the wave covers 1 KB; the rank is found row by row.  After the
 // last pass the candidate is the lower median and lt / le are exact.
+template <int D>
 __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t pass) {
-    constexpr int ROWS = BIG_BINS / (4 * WAVE);
-    static_assert(ROWS * 4 * WAVE == BIG_BINS, "whole rows of bins");
-    const int shift = big_shift(pass);
+    using DG = BigDigits<D>;
+    constexpr int ROWS = DG::BINS / (4 * WAVE);
+    static_assert(ROWS * 4 * WAVE == DG::BINS, "whole rows of bins");
+    const int shift = DG::shift(pass);
     const uint32_t nbig = c.info[level].num_big;
     const int l = lane();
     for (uint32_t b = blockIdx.x * NW + wave(); b < nbig; b += gridDim.x * NW) {
         const uint32_t ci = c.big_list[b];
         CellRes r = c.res[ci];
-        uint4 *gh = reinterpret_cast<uint4 *>(c.hist + uint64_t(b) * BIG_BINS);
+        uint4 *gh = reinterpret_cast<uint4 *>(c.hist + uint64_t(b) * BIG_BINS_MAX);
         uint4 hv[ROWS];
 #pragma unroll
         for (int q = 0; q < ROWS; q++) hv[q] = gh[q * WAVE + l];
@@ -553,7 +557,7 @@ __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t
             r.prefix |= bin << shift;
             r.rank -= below;
             r.lt += below;  // keys below the selected digit
-            if (pass == BIG_PASSES - 1) {
+            if (pass == DG::PASSES - 1) {
                 r.cand = r.prefix;
                 r.le = r.lt + cnt;
             }
@@ -2944,7 +2948,7 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     L.tile_off = B.take(L.max_tiles * 4);
     L.tile_cell = B.take(L.max_tiles * 4);
     L.tiles = B.take(L.max_tiles * sizeof(TileDesc));
-    L.hist = B.take(L.max_big * BIG_BINS * 4);
+    L.hist = B.take(L.max_big * BIG_BINS_MAX * 4);
     const bool fourier = p->split_rule == KD_SPLIT_FOURIER;
     const bool subset = p->split_rule == KD_SPLIT_SUBSET;
     L.mm = B.take(fourier ? L.max_big * 8 : 0);
@@ -3259,8 +3263,8 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     const dim3 per_tree_nodes(grid_for(maxcap / NT + 1, 1024), ntrees);
     const dim3 per_tree_points(grid_for(maxn / NT + 1, 1024), ntrees);
     P.run(KD_PROF_OTHER, 0, 0, [&] {
-        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.max_big * BIG_BINS / NT + 1, 4096)),
-                           dim3(NT), 0, st, c.hist, L.max_big * BIG_BINS, 0u);
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.max_big * BIG_BINS_MAX / NT + 1, 4096)),
+                           dim3(NT), 0, st, c.hist, L.max_big * BIG_BINS_MAX, 0u);
         hipLaunchKernelGGL(k_init, per_tree_nodes, dim3(NT), 0, st, c);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(NT), 0, st, c.rec_count, 1ull, 0u);
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L.leaf_words / NT + 1, 4096)), dim3(NT), 0,
@@ -3291,6 +3295,7 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     const uint32_t hist_grid = tune.hist_blocks ? tune.hist_blocks : 2048u;
     const uint32_t tile_grid = tune.scatter_blocks ? tune.scatter_blocks : 65535u;
     const uint32_t small_grid = tune.small_blocks ? tune.small_blocks : (1u << 20);
+    const int digit = tune.digit_bits ? int(tune.digit_bits) : BIG_DIGIT_DEFAULT;
     // dynamic LDS of the small-cell kernel (SUBSET: subset bounds and medians)
     const size_t small_dyn =
         p->split_rule == KD_SPLIT_SUBSET
@@ -3360,14 +3365,23 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         });
         if (nbig > 0) {
             if (p->split_rule == KD_SPLIT_EXACT) {
-                for (uint32_t pass = 0; pass < uint32_t(BIG_PASSES); pass++) {
+                const uint32_t passes =
+                    digit == 8 ? BigDigits<8>::PASSES : BigDigits<11>::PASSES;
+                for (uint32_t pass = 0; pass < passes; pass++) {
                     P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
-                        hipLaunchKernelGGL(k_big_hist, G(ntl, hist_grid), dim3(NT), 0,
-                                           st, c, level, pass);
+                        if (digit == 8)
+                            hipLaunchKernelGGL(k_big_hist<8>, G(ntl, hist_grid), dim3(NT), 0,
+                                               st, c, level, pass);
+                        else
+                            hipLaunchKernelGGL(k_big_hist<11>, G(ntl, hist_grid), dim3(NT), 0,
+                                               st, c, level, pass);
                     });
                     P.run(KD_PROF_PICK, 0, 0, [&] {
-                        hipLaunchKernelGGL(k_big_pick, G((nbig + NW - 1) / NW, 65535),
-                                           dim3(NT), 0, st, c, level, pass);
+                        const dim3 g = G((nbig + NW - 1) / NW, 65535);
+                        if (digit == 8)
+                            hipLaunchKernelGGL(k_big_pick<8>, g, dim3(NT), 0, st, c, level, pass);
+                        else
+                            hipLaunchKernelGGL(k_big_pick<11>, g, dim3(NT), 0, st, c, level, pass);
                     });
                 }
             } else if (p->split_rule == KD_SPLIT_FOURIER) {
@@ -3734,8 +3748,8 @@ kd_status kd_build_batched(uint32_t count, const kd_batch_item *items, const kd_
 kd_status kd_set_tuning(const kd_tuning *t) {
     if (!t) return KD_EINVAL;
     std::lock_guard<std::mutex> lk(g_tuning_mu);
+    if (t->digit_bits != 0 && t->digit_bits != 8 && t->digit_bits != 11) return KD_EINVAL;
     g_tuning = *t;
-    g_tuning.reserved = 0;
     return KD_OK;
 }
 
@@ -3818,12 +3832,16 @@ kd_status kd_autotune(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
     static const uint32_t kHist[] = {0, 65535, 4096, 1024, 512};
     static const uint32_t kTile[] = {0, 4096, 2048, 1024};
     static const uint32_t kSmall[] = {0, 8192, 4096, 2048};
-    for (int field = 0; field < 3 && s == KD_OK; field++) {
-        const uint32_t *vals = field == 0 ? kHist : field == 1 ? kTile : kSmall;
-        const int nv = field == 0 ? 5 : 4;
+    static const uint32_t kDigit[] = {0, 8};  // 0: 11-bit digits
+    for (int field = 0; field < 4 && s == KD_OK; field++) {
+        const uint32_t *vals = field == 0 ? kHist : field == 1 ? kTile : field == 2 ? kSmall : kDigit;
+        const int nv = field == 0 ? 5 : field == 3 ? 2 : 4;
         for (int i = 0; i < nv && s == KD_OK; i++) {
             kd_tuning t = cur;
-            uint32_t &f = field == 0 ? t.hist_blocks : field == 1 ? t.scatter_blocks : t.small_blocks;
+            uint32_t &f = field == 0   ? t.hist_blocks
+                          : field == 1 ? t.scatter_blocks
+                          : field == 2 ? t.small_blocks
+                                       : t.digit_bits;
             if (f == vals[i]) continue;
             f = vals[i];
             float ms = 0.0f;

@@ -56,11 +56,11 @@ class Profile(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("hist_blocks", _u32), ("scatter_blocks", _u32), ("small_blocks", _u32),
-                ("reserved", _u32)]
+                ("digit_bits", _u32)]
 
     def to_dict(self):
         return {"hist_blocks": self.hist_blocks, "scatter_blocks": self.scatter_blocks,
-                "small_blocks": self.small_blocks}
+                "small_blocks": self.small_blocks, "digit_bits": self.digit_bits}
 
 
 class BatchItem(ctypes.Structure):
@@ -400,9 +400,9 @@ def global_counts(points, medians, depth, stream=None):
     return cnt
 
 
-def set_tuning(hist_blocks=0, scatter_blocks=0, small_blocks=0):
-    """kd_set_tuning: process-wide launch shapes (0 = default)."""
-    t = Tuning(hist_blocks, scatter_blocks, small_blocks, 0)
+def set_tuning(hist_blocks=0, scatter_blocks=0, small_blocks=0, digit_bits=0):
+    """kd_set_tuning: process-wide launch shapes and digit width (0 = default)."""
+    t = Tuning(hist_blocks, scatter_blocks, small_blocks, digit_bits)
     _check(lib().kd_set_tuning(ctypes.byref(t)), "kd_set_tuning")
 
 

@@ -79,9 +79,14 @@ def test_tuning_round_trip(lib):
     from paper_2201_08288_amd import kdtree
     before = kdtree.get_tuning()
     try:
-        kdtree.set_tuning(hist_blocks=1024, scatter_blocks=2048, small_blocks=4096)
+        kdtree.set_tuning(hist_blocks=1024, scatter_blocks=2048, small_blocks=4096, digit_bits=8)
         assert kdtree.get_tuning() == {"hist_blocks": 1024, "scatter_blocks": 2048,
-                                       "small_blocks": 4096}
+                                       "small_blocks": 4096, "digit_bits": 8}
+        # only 11- and 8-bit digits exist; a rejected setting leaves the old one
+        for bad in (1, 9, 10, 12, 16):
+            t = kdtree.Tuning(0, 0, 0, bad)
+            assert kdtree.lib().kd_set_tuning(ctypes.byref(t)) == kdtree.KD_EINVAL
+        assert kdtree.get_tuning()["digit_bits"] == 8
     finally:
         kdtree.set_tuning(**before)
     assert kdtree.get_tuning() == before

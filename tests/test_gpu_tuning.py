@@ -1,6 +1,6 @@
-"""Launch shapes never change the tree: builds under every shape the tuner
-tries are bit-identical to each other and to the oracle, and kd_autotune
-keeps one of them."""
+"""Launch shapes and digit widths never change the tree: builds under every
+setting the tuner tries are bit-identical to each other and to the oracle,
+and kd_autotune keeps one of them."""
 import numpy as np
 import pytest
 
@@ -11,7 +11,8 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [dict(), dict(hist_blocks=512), dict(hist_blocks=1), dict(scatter_blocks=1024),
           dict(scatter_blocks=1), dict(small_blocks=2048), dict(small_blocks=1),
-          dict(hist_blocks=3, scatter_blocks=7, small_blocks=5)]
+          dict(hist_blocks=3, scatter_blocks=7, small_blocks=5), dict(digit_bits=8),
+          dict(digit_bits=8, hist_blocks=5, scatter_blocks=3)]
 
 
 @pytest.mark.parametrize("rule,key", [(0, 0), (1, 0), (2, 1)])
