@@ -1869,7 +1869,7 @@ struct SubTable {
 };
 constexpr uint32_t SEG_LEAF = 0xffu;
 template <bool MAXVAR>
-constexpr int subtree_cells() { return MAXVAR ? 120 : 64; }
+constexpr int subtree_cells() { return MAXVAR ? 80 : 64; }
 
 template <int SC, int CH>
 __device__ __forceinline__ void sub_result(const Ctx &c, uint32_t depth, uint32_t max_depth,
@@ -1970,7 +1970,11 @@ __device__ void subtree_subset(const Ctx &c, uint32_t depth, uint32_t max_depth,
 }
 
 template <int RULE, bool MAXVAR>
-__global__ __launch_bounds__(NT, MAXVAR || RULE == KD_SPLIT_SUBSET ? 2 : 3) void k_subtree(
+// Workgroups per CU: three (LDS about 53 KB with the largest-variance key and
+// 80 chunk cells; a few spilled registers), two for the FOURIER moments with
+// that key and for SUBSET.
+__global__ __launch_bounds__(NT, MAXVAR ? (RULE == KD_SPLIT_EXACT ? 3 : 2)
+                                        : (RULE == KD_SPLIT_SUBSET ? 2 : 3)) void k_subtree(
     Ctx c, uint32_t level) {
     constexpr int SC = subtree_cells<MAXVAR>();
     constexpr int CH = MAXVAR ? 2 * SC : SC;
