@@ -191,6 +191,20 @@ __device__ __forceinline__ unsigned long long wave_scan64(unsigned long long x) 
     return x;
 }
 
+// Reduction of 32-bit values over a wave64 with DPP moves, for an operation
+// with identity `id` (lanes a move does not reach take the identity), in the
+// pattern of wave_scan64; the result is lane 63's, returned to every lane.
+template <class Op>
+__device__ __forceinline__ uint32_t wave_reduce32(uint32_t x, uint32_t id, Op op) {
+    x = op(x, uint32_t(__builtin_amdgcn_update_dpp(int(id), int(x), 0x111, 0xf, 0xf, false)));
+    x = op(x, uint32_t(__builtin_amdgcn_update_dpp(int(id), int(x), 0x112, 0xf, 0xf, false)));
+    x = op(x, uint32_t(__builtin_amdgcn_update_dpp(int(id), int(x), 0x114, 0xf, 0xf, false)));
+    x = op(x, uint32_t(__builtin_amdgcn_update_dpp(int(id), int(x), 0x118, 0xf, 0xf, false)));
+    x = op(x, uint32_t(__builtin_amdgcn_update_dpp(int(id), int(x), 0x142, 0xa, 0xf, false)));
+    x = op(x, uint32_t(__builtin_amdgcn_update_dpp(int(id), int(x), 0x143, 0xc, 0xf, false)));
+    return uint32_t(__builtin_amdgcn_readlane(int(x), WAVE - 1));
+}
+
 // Sum over a wave64, valid in every lane (DPP scan, then lane 63's total).
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
     x = wave_scan64(x);

@@ -59,7 +59,8 @@ struct Ctx {
     Cell *cells[2];
     CellRes *res;
     uint32_t *big_list;
-    uint32_t *tile_lt, *tile_le, *tile_off;
+    uint32_t *tile_lt, *tile_le;
+    uint32_t *tile_mm;  // EXACT: smallest and largest last digit of a tile's keys on the prefix
     uint32_t *tile_cell;
     TileDesc *tiles;
     uint32_t *hist;
@@ -438,11 +439,13 @@ __device__ __forceinline__ TileView tile_view(const Ctx &c, uint32_t cur, uint32
 // EXACT, large cells: digit histograms of a run of consecutive tiles in LDS,
 // added into the cell's histogram whenever the run moves to another cell.
 template <int D>
-__global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t pass) {
+__global__ __launch_bounds__(NT, 8) void k_big_hist(Ctx c, uint32_t level, uint32_t pass) {
     using DG = BigDigits<D>;
     __shared__ uint32_t h[DG::BINS];
     __shared__ uint32_t s_cell;
+    __shared__ uint32_t tsum[2][NW][3];  // last pass: per-wave tile summary, by tile parity
     const uint32_t cur = level & 1;
+    const bool last = pass == DG::PASSES - 1;
     const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
     const int shift = DG::shift(pass);
     const uint32_t dmask = (1u << DG::bits(pass)) - 1u;
@@ -477,12 +480,18 @@ __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t
             u[j] = key_of_bits(col[min(i, v.te - 1)]);  // used only where i < v.te
         }
         // a thread's keys often share a digit (the leading digits of a cell):
-        // one atomic per run of equal digits
+        // one atomic per run of equal digits.  In the last pass the same loop
+        // counts the tile's keys below the prefix and on it, and the
+        // smallest and largest last digit of those on it: once the
+        // candidate is known, the tile's counts around it follow without
+        // rereading the keys unless its last digit falls strictly inside
         uint32_t run_bin = NONE, run_cnt = 0;
+        uint32_t below = 0, on = 0, dmn = 0xffffu, dmx = 0;
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
             const uint32_t i = v.tb + j * NT + threadIdx.x;
-            if (i < v.te && (u[j] & pmask) == r.prefix) {
+            const uint32_t up = u[j] & pmask;
+            if (i < v.te && up == r.prefix) {
                 const uint32_t bin = (u[j] >> shift) & dmask;
                 if (bin != run_bin) {
                     if (run_cnt) atomicAdd(&h[run_bin], run_cnt);
@@ -490,10 +499,39 @@ __global__ __launch_bounds__(NT) void k_big_hist(Ctx c, uint32_t level, uint32_t
                     run_cnt = 0;
                 }
                 run_cnt++;
+                on++;
+                dmn = min(dmn, bin);
+                dmx = max(dmx, bin);
             }
+            below += i < v.te && up < r.prefix;
         }
         if (run_cnt) atomicAdd(&h[run_bin], run_cnt);
+        const uint32_t par = (t - t0) & 1u;
+        if (last) {
+            // both counts of a wave fit 16 bits: one sum of the pair
+            const uint32_t pair = wave_reduce32(below | (on << 16), 0u,
+                                                [](uint32_t a, uint32_t b) { return a + b; });
+            dmn = wave_reduce32(dmn, 0xffffffffu, [](uint32_t a, uint32_t b) { return min(a, b); });
+            dmx = wave_reduce32(dmx, 0u, [](uint32_t a, uint32_t b) { return max(a, b); });
+            if (lane() == 0) {
+                tsum[par][wave()][0] = pair & 0xffffu;
+                tsum[par][wave()][1] = pair >> 16;
+                tsum[par][wave()][2] = dmn | (dmx << 16);
+            }
+        }
         __syncthreads();
+        if (last && threadIdx.x == 0) {
+            uint32_t below = 0, on = 0, dmn = 0xffffu, dmx = 0;
+            for (int w = 0; w < NW; w++) {
+                below += tsum[par][w][0];
+                on += tsum[par][w][1];
+                dmn = min(dmn, tsum[par][w][2] & 0xffffu);
+                dmx = max(dmx, tsum[par][w][2] >> 16);
+            }
+            c.tile_lt[t] = below;
+            c.tile_le[t] = on;
+            c.tile_mm[t] = dmn | (dmx << 16);
+        }
     }
     if (big != NONE) {
         uint32_t *gh = c.hist + uint64_t(big) * BIG_BINS_MAX;
@@ -936,7 +974,12 @@ __global__ __launch_bounds__(NT) void k_subset_mean(Ctx c, uint32_t level) {
 }
 
 // a6, large cells: per tile, keys below and at the candidate.
-__global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level) {
+// summ (EXACT): the last digit pass left each tile's keys below the prefix,
+// on it, and their smallest and largest last digit (lshift, lmask); a tile
+// is reread only when the candidate's last digit lies strictly between two
+// different digits of its keys on the prefix.
+__global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level, uint32_t summ,
+                                                  uint32_t lshift, uint32_t lmask) {
     __shared__ uint32_t s_cell;
     __shared__ uint32_t sh[NW + 1];
     const uint32_t cur = level & 1;
@@ -944,6 +987,30 @@ __global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level) {
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileView v = tile_view(c, cur, ncells, t, &s_cell);
         const CellRes r = c.res[v.ci];
+        if (summ) {
+            // the decision depends only on the tile's digits, the same in
+            // every wave (the counts below are rewritten by thread 0 only)
+            const uint32_t below = c.tile_lt[t], on = c.tile_le[t], mm = c.tile_mm[t];
+            const uint32_t dsel = (r.cand >> lshift) & lmask, dmn = mm & 0xffffu, dmx = mm >> 16;
+            uint32_t lt = below, le = below;
+            bool known = true;
+            if (on == 0 || dsel < dmn) {
+                // every key on the prefix is above the candidate
+            } else if (dsel > dmx) {
+                lt = le = below + on;  // every key on the prefix is below
+            } else if (dmn == dmx) {
+                le = below + on;  // every key on the prefix is the candidate
+            } else {
+                known = false;
+            }
+            if (known) {
+                if (threadIdx.x == 0) {
+                    c.tile_lt[t] = lt;
+                    c.tile_le[t] = le;
+                }
+                continue;
+            }
+        }
         const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
         const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
         uint32_t lt = 0, le = 0, u[PER_THREAD];
@@ -2907,7 +2974,7 @@ struct TreeLayout {
 
 struct Layout {
     uint64_t cell_rec[2], subrec, rec_count, rec_cap, recstats, recstats_stride;
-    uint64_t trees, ts, cells[2], res, big_list, tile_lt, tile_le, tile_off, tile_cell, tiles, hist, mm, mom,
+    uint64_t trees, ts, cells[2], res, big_list, tile_lt, tile_le, tile_mm, tile_cell, tiles, hist, mm, mom,
         bounds, med, pre, scan, buckets, segs, info, leafbits, leafpre, leafblk, total;
     uint64_t max_cells, max_tiles, max_big, scan_blocks, all_points, leaf_words, leaf_blocks;
     std::vector<TreeLayout> per_tree;
@@ -2949,7 +3016,7 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     L.big_list = B.take(L.max_big * 4);
     L.tile_lt = B.take(L.max_tiles * 4);
     L.tile_le = B.take(L.max_tiles * 4);
-    L.tile_off = B.take(L.max_tiles * 4);
+    L.tile_mm = B.take(L.max_tiles * 4);
     L.tile_cell = B.take(L.max_tiles * 4);
     L.tiles = B.take(L.max_tiles * sizeof(TileDesc));
     L.hist = B.take(L.max_big * BIG_BINS_MAX * 4);
@@ -3215,7 +3282,7 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
     c.big_list = reinterpret_cast<uint32_t *>(ws + L.big_list);
     c.tile_lt = reinterpret_cast<uint32_t *>(ws + L.tile_lt);
     c.tile_le = reinterpret_cast<uint32_t *>(ws + L.tile_le);
-    c.tile_off = reinterpret_cast<uint32_t *>(ws + L.tile_off);
+    c.tile_mm = reinterpret_cast<uint32_t *>(ws + L.tile_mm);
     c.tile_cell = reinterpret_cast<uint32_t *>(ws + L.tile_cell);
     c.tiles = reinterpret_cast<TileDesc *>(ws + L.tiles);
     c.hist = reinterpret_cast<uint32_t *>(ws + L.hist);
@@ -3425,9 +3492,17 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                                        dim3(NT), 0, st, c, level);
                 });
             }
-            P.run(KD_PROF_COUNT, bigp, 4 * bigp, [&] {
-                hipLaunchKernelGGL(k_big_count, G(ntl, tile_grid), dim3(NT), 0, st, c,
-                                   level);
+            // EXACT counts come from the last digit pass's tile summaries
+            const uint64_t count_bytes = p->split_rule == KD_SPLIT_EXACT ? 0 : 4 * bigp;
+            P.run(KD_PROF_COUNT, bigp, count_bytes, [&] {
+                const bool summ = p->split_rule == KD_SPLIT_EXACT;
+                const int lpass = (digit == 8 ? BigDigits<8>::PASSES : BigDigits<11>::PASSES) - 1;
+                const uint32_t lshift = uint32_t(digit == 8 ? BigDigits<8>::shift(lpass)
+                                                            : BigDigits<11>::shift(lpass));
+                const uint32_t lbits = uint32_t(digit == 8 ? BigDigits<8>::bits(lpass)
+                                                           : BigDigits<11>::bits(lpass));
+                hipLaunchKernelGGL(k_big_count, G(ntl, tile_grid), dim3(NT), 0, st, c, level,
+                                   summ ? 1u : 0u, lshift, (1u << lbits) - 1u);
                 hipLaunchKernelGGL(k_big_decide, G(nbig, 65535), dim3(NT), 0, st, c,
                                    level);
             });
