@@ -106,8 +106,17 @@ struct TreeDesc {
     uint64_t cap;
     uint32_t n, d;
     uint32_t max_depth;   // cells at this depth stay leaves
-    uint32_t pad;
+    uint32_t direct;      // the root is a large cell: level 0 reads pts, not cols[0]
 };
+
+// Column `dim` of the points a level reads: the caller's points ([d][ld])
+// at level 0 of a tree whose root is a large cell, else the level's working
+// copy ([d][n]).  Only large-cell kernels run at level 0 of such a tree.
+template <class Desc>  // TreeDesc in any address space
+__device__ __forceinline__ const uint32_t *level_col(const Desc &T, uint32_t level, uint32_t dim) {
+    return level == 0 && T.direct ? T.pts + uint64_t(dim) * T.ld
+                                  : T.cols[level & 1] + uint64_t(dim) * T.n;
+}
 
 // Mutable per-tree counters of the level loop (device memory).
 struct TreeState {

@@ -139,8 +139,10 @@ __global__ __launch_bounds__(NT) void k_init(Ctx c) {
     }
 }
 
-// a1: copy the caller's points into working buffer 0 (float bits), identity
-// permutation, reject NaN / Inf; max |x| for the largest-variance grid.
+// a1: reject NaN / Inf, identity permutation, max |x| for the
+// largest-variance grid; copy the caller's points into working buffer 0
+// (float bits) unless the root is a large cell, whose level 0 reads them in
+// place.
 __global__ __launch_bounds__(NT) void k_ingest(Ctx c) {
     const uint32_t t = blockIdx.z, col = blockIdx.y;
     const KD_CONST TreeDesc &T = cref(&c.trees[t]);
@@ -149,6 +151,7 @@ __global__ __launch_bounds__(NT) void k_ingest(Ctx c) {
     KD_GLOBAL uint32_t *dst = gp(T.cols[0] + uint64_t(col) * T.n);
     KD_GLOBAL uint32_t *perm = gp(T.perm[0]);
     const uint32_t n = T.n;
+    const bool copy = !T.direct;  // a large root's level 0 reads the caller's points
     bool bad = false;
     uint32_t mx = 0;
     for (uint32_t i0 = blockIdx.x * NT * 4 + threadIdx.x; i0 < n; i0 += gridDim.x * NT * 4) {
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(NT) void k_ingest(Ctx c) {
                 const bool nf = (b[j] & 0x7f800000u) == 0x7f800000u;
                 bad |= nf;
                 if (!nf) mx = max(mx, b[j] & 0x7fffffffu);
-                dst[i] = b[j];
+                if (copy) dst[i] = b[j];
                 if (col == 0) perm[i] = i;
             }
         }
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(NT) void k_root_stats(Ctx c) {
     const KD_CONST TreeDesc &T = cref(&c.trees[t]);
     if (S.count[0] == 0 || col >= T.d) return;
     const int shift = maxvar_shift(S.maxabs);
-    const KD_GLOBAL uint32_t *src = gp(T.cols[0] + uint64_t(col) * T.n);
+    const KD_GLOBAL uint32_t *src = gp(level_col(T, 0, col));
     const uint32_t n = T.n;
     VarSums a;
     for (uint32_t i0 = blockIdx.x * NT * 8 + threadIdx.x; i0 < n; i0 += gridDim.x * NT * 8) {
@@ -469,7 +472,7 @@ __global__ __launch_bounds__(NT, 8) void k_big_hist(Ctx c, uint32_t level, uint3
         }
         const CellRes r = c.res[v.ci];
         const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
-        const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
+        const KD_GLOBAL uint32_t *col = gp(level_col(T, level, r.dim));
         uint32_t u[PER_THREAD];
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
@@ -633,7 +636,7 @@ __global__ __launch_bounds__(NT) void k_big_minmax(Ctx c, uint32_t level) {
         }
         const CellRes r = c.res[v.ci];
         const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
-        const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
+        const KD_GLOBAL uint32_t *col = gp(level_col(T, level, r.dim));
         uint32_t u[PER_THREAD];
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
@@ -707,7 +710,7 @@ __global__ __launch_bounds__(NT) void k_big_moments(Ctx c, uint32_t level) {
             if (lo == hi) continue;  // all keys equal: no moments needed
             const CellRes r = c.res[v.ci];
             const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
-            const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
+            const KD_GLOBAL uint32_t *col = gp(level_col(T, level, r.dim));
             const int e = fourier_exponent(lo, hi);
             const double xmin = value_of_key(lo), scale = fourier_scale(e);
             uint32_t u[PER_THREAD];
@@ -816,7 +819,7 @@ __global__ __launch_bounds__(NT) void k_subset_select(Ctx c, uint32_t level) {
         const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
         const uint32_t *B = c.bounds + uint64_t(b) * (c.S + 1);
         ns = B[s + 1] - B[s];
-        col = T.cols[cur] + uint64_t(c.res[ci].dim) * T.n + cl.begin + B[s];
+        col = level_col(T, level, c.res[ci].dim) + cl.begin + B[s];
     };
     for (uint64_t j0 = uint64_t(blockIdx.x) * NW; j0 < jobs; j0 += uint64_t(gridDim.x) * NW) {
         // one wave per small subset
@@ -889,7 +892,8 @@ struct SegView {
     const uint32_t *col;
     uint32_t b, s, ns;
 };
-__device__ __forceinline__ SegView seg_view(const Ctx &c, uint32_t cur, uint32_t i) {
+__device__ __forceinline__ SegView seg_view(const Ctx &c, uint32_t level, uint32_t i) {
+    const uint32_t cur = level & 1;
     SegView v;
     const uint32_t job = c.seg_job[i];
     v.b = job / c.S;
@@ -899,18 +903,18 @@ __device__ __forceinline__ SegView seg_view(const Ctx &c, uint32_t cur, uint32_t
     const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
     const uint32_t *B = c.bounds + uint64_t(v.b) * (c.S + 1);
     v.ns = B[v.s + 1] - B[v.s];
-    v.col = T.cols[cur] + uint64_t(c.res[ci].dim) * T.n + cl.begin + B[v.s];
+    v.col = level_col(T, level, c.res[ci].dim) + cl.begin + B[v.s];
     return v;
 }
 
 __global__ __launch_bounds__(NT) void k_seg_hist(Ctx c, uint32_t level, uint32_t pass) {
     __shared__ uint32_t h[NBINS];
-    const uint32_t cur = level & 1, nseg = *c.seg_count;
+    const uint32_t nseg = *c.seg_count;
     const int shift = 32 - RBITS * (pass + 1);
     const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
     for (uint32_t blk = blockIdx.x; blk < nseg * SEG_FAN; blk += gridDim.x) {
         const uint32_t i = blk / SEG_FAN, f = blk % SEG_FAN;
-        const SegView v = seg_view(c, cur, i);
+        const SegView v = seg_view(c, level, i);
         const uint32_t prefix = c.seg_prefix[i];
         const uint32_t per = (v.ns + SEG_FAN - 1) / SEG_FAN;
         const uint32_t a = min(f * per, v.ns), e = min(a + per, v.ns);
@@ -1012,7 +1016,7 @@ __global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level, uint32_
             }
         }
         const KD_CONST TreeDesc &T = cref(&c.trees[v.cl.tree]);
-        const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(r.dim) * T.n);
+        const KD_GLOBAL uint32_t *col = gp(level_col(T, level, r.dim));
         uint32_t lt = 0, le = 0, u[PER_THREAD];
 #pragma unroll
         for (int j = 0; j < PER_THREAD; j++) {
@@ -1123,7 +1127,7 @@ __global__ __launch_bounds__(NT, 4) void k_big_scatter(Ctx c, uint32_t level) {
         uint32_t dr[PER_THREAD];
         uint32_t nleft_tile = 0;
         if (D.flags & RES_SPLIT) {
-            const KD_GLOBAL uint32_t *col = gp(T.cols[cur] + uint64_t(D.dim) * n + D.tb);
+            const KD_GLOBAL uint32_t *col = gp(level_col(T, level, D.dim) + D.tb);
             uint32_t u[PER_THREAD];
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
@@ -1174,7 +1178,7 @@ __global__ __launch_bounds__(NT, 4) void k_big_scatter(Ctx c, uint32_t level) {
         // column k is staged while column k + 1 is on its way
         uint32_t vn[PER_THREAD];
         {
-            const KD_GLOBAL uint32_t *src = gp(T.cols[cur] + D.tb);
+            const KD_GLOBAL uint32_t *src = gp(level_col(T, level, 0) + D.tb);
 #pragma unroll
             for (int j = 0; j < PER_THREAD; j++) {
                 const uint32_t i = j * NT + threadIdx.x;
@@ -1189,7 +1193,7 @@ __global__ __launch_bounds__(NT, 4) void k_big_scatter(Ctx c, uint32_t level) {
             for (int j = 0; j < PER_THREAD; j++) v[j] = vn[j];
             if (k < d) {
                 const KD_GLOBAL uint32_t *src =
-                    gp(k + 1 == d ? T.perm[cur] + D.tb : T.cols[cur] + uint64_t(k + 1) * n + D.tb);
+                    gp(k + 1 == d ? T.perm[cur] + D.tb : level_col(T, level, k + 1) + D.tb);
 #pragma unroll
                 for (int j = 0; j < PER_THREAD; j++) {
                     const uint32_t i = j * NT + threadIdx.x;
@@ -3262,6 +3266,9 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         pbase += n[t];
         D.d = d[t];
         D.max_depth = p->max_depth ? p->max_depth : default_depth(n[t], p->leaf_size);
+        // a root that is a large cell is split at level 0 by the large-cell
+        // kernels only, which read the caller's points in place
+        D.direct = n[t] > uint64_t(SMALL_MAX) && n[t] > p->leaf_size && D.max_depth > 0 ? 1u : 0u;
     }
     for (uint32_t t0 = 0; t0 < ntrees; t0 += DESC_CHUNK) {
         DescChunk ch{};

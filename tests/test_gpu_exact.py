@@ -119,6 +119,33 @@ def test_strided_input_and_no_points_out():
     assert_same_tree(g, oracle_tree(x, leaf_size=8))
 
 
+@pytest.mark.parametrize("rule,key", [(0, 0), (0, 1), (1, 1), (2, 0), (2, 1)])
+def test_strided_large_root_every_rule(rule, key):
+    """A root of more than 4096 points is split at level 0 straight from the
+    caller's [d][ld] points (no working copy): ld > n, -0.0 and subnormal
+    coordinates among them, every rule and key, with and without points_out."""
+    import torch
+
+    from paper_2201_08288_amd import kdtree
+    print(f"case strided large root rule={rule} key={key}", flush=True)
+    n, d, ld = 70001, 4, 70001 + 333
+    x = synth.gmm(n, d, seed=40 + rule)
+    x[1, ::13] = -0.0
+    x[2, ::29] = np.float32(1e-40)
+    big = torch.full((d, ld), 7.0, dtype=torch.float32)
+    big[:, :n] = torch.from_numpy(x)
+    kw = dict(leaf_size=24, num_subsets=8, split_rule=rule, key_rule=key)
+    o = oracle_tree(x, **kw)
+    for pts_out in (True, False):
+        t = kdtree.build(big.cuda()[:, :n], points_out=pts_out, **kw)
+        torch.cuda.synchronize()
+        g = t.to_numpy()
+        if pts_out:
+            assert_same_tree(g, o, x)
+        else:
+            assert_same_tree(g, o)
+
+
 def test_workspace_too_small_rejected_before_any_work():
     import ctypes
 
