@@ -154,22 +154,27 @@ __global__ __launch_bounds__(NT) void k_ingest(Ctx c) {
     const bool copy = !T.direct;  // a large root's level 0 reads the caller's points
     bool bad = false;
     uint32_t mx = 0;
-    for (uint32_t i0 = blockIdx.x * NT * 4 + threadIdx.x; i0 < n; i0 += gridDim.x * NT * 4) {
-        uint32_t b[4];
+    // sixteen loads per thread in flight (clamped indices, no branch)
+    for (uint32_t i0 = blockIdx.x * NT * 16 + threadIdx.x; i0 < n; i0 += gridDim.x * NT * 16) {
+        uint32_t b[16];
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < 16; j++) b[j] = src[min(i0 + j * NT, n - 1)];
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
             const uint32_t i = i0 + j * NT;
-            b[j] = i < n ? src[i] : 0u;
+            const bool in = i < n;
+            const bool nf = (b[j] & 0x7f800000u) == 0x7f800000u;
+            bad |= in && nf;
+            mx = in && !nf ? max(mx, b[j] & 0x7fffffffu) : mx;
         }
+        if (copy || col == 0) {
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const uint32_t i = i0 + j * NT;
-            if (i < n) {
-                const bool nf = (b[j] & 0x7f800000u) == 0x7f800000u;
-                bad |= nf;
-                if (!nf) mx = max(mx, b[j] & 0x7fffffffu);
-                if (copy) dst[i] = b[j];
-                if (col == 0) perm[i] = i;
+            for (int j = 0; j < 16; j++) {
+                const uint32_t i = i0 + j * NT;
+                if (i < n) {
+                    if (copy) dst[i] = b[j];
+                    if (col == 0) perm[i] = i;
+                }
             }
         }
     }
@@ -3353,8 +3358,12 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                                c.seg_count, words, 0u);
         }
     });
-    P.run(KD_PROF_INGEST, total_points, 8 * sum_d + 4 * total_points, [&] {
-        hipLaunchKernelGGL(k_ingest, dim3(grid_for(maxn / (NT * 4) + 1, 1024), maxd, ntrees),
+    // bytes: the points read (and copied unless read in place at level 0),
+    // the identity permutation written
+    uint64_t ingest_bytes = 4 * total_points;
+    for (uint32_t t = 0; t < ntrees; t++) ingest_bytes += (desc[t].direct ? 4 : 8) * uint64_t(d[t]) * n[t];
+    P.run(KD_PROF_INGEST, total_points, ingest_bytes, [&] {
+        hipLaunchKernelGGL(k_ingest, dim3(grid_for(maxn / (NT * 16) + 1, 1024), maxd, ntrees),
                            dim3(NT), 0, st, c);
     });
     P.run(KD_PROF_OTHER, 0, 0, [&] {
