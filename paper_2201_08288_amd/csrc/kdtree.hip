@@ -993,7 +993,11 @@ __global__ __launch_bounds__(NT) void k_big_count(Ctx c, uint32_t level, uint32_
     __shared__ uint32_t sh[NW + 1];
     const uint32_t cur = level & 1;
     const uint32_t ncells = c.info[level].num_cells, ntiles = c.info[level].num_tiles;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // a run of consecutive tiles per workgroup (mostly of one cell, whose
+    // records then stay in the scalar cache)
+    const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = blockIdx.x * per, t1 = min(t0 + per, ntiles);
+    for (uint32_t t = t0; t < t1; t++) {
         const TileView v = tile_view(c, cur, ncells, t, &s_cell);
         const CellRes r = c.res[v.ci];
         if (summ) {
@@ -3517,8 +3521,11 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                                                             : BigDigits<11>::shift(lpass));
                 const uint32_t lbits = uint32_t(digit == 8 ? BigDigits<8>::bits(lpass)
                                                            : BigDigits<11>::bits(lpass));
-                hipLaunchKernelGGL(k_big_count, G(ntl, tile_grid), dim3(NT), 0, st, c, level,
-                                   summ ? 1u : 0u, lshift, (1u << lbits) - 1u);
+                // EXACT: runs of eight tiles, most of them settled from the
+                // summaries alone
+                hipLaunchKernelGGL(k_big_count, summ ? G((ntl + 7) / 8, 65535) : G(ntl, tile_grid),
+                                   dim3(NT), 0, st, c, level, summ ? 1u : 0u, lshift,
+                                   (1u << lbits) - 1u);
                 hipLaunchKernelGGL(k_big_decide, G(nbig, 65535), dim3(NT), 0, st, c,
                                    level);
             });
