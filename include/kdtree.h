@@ -9,9 +9,8 @@
  *
  * Problem statement (§2, §4): a data set X of n points in d dimensions; a
  * tree of cells obtained by recursive splits along one coordinate (the key)
- * at an (approximate) median.  The split values are "all the information
- * needed to build the tree" (§2); the leaves are cells of about equal count
- * (§4).
+ * at an (approximate) median.  The split values alone determine the tree
+ * (§2); the leaves are cells of about equal count (§4).
  *
  * Conventions for every entry point
  *   - Points are fp32, structure of arrays: coordinate c of point i is at
@@ -128,8 +127,13 @@ typedef struct kd_tree {
 } kd_tree;
 
 /* Sizes to allocate for a build of n points in d dimensions (host only, no
- * device work).  node_capacity: entries of each node array; workspace_bytes:
- * device workspace for kd_build.  Returns KD_EINVAL on bad parameters.     */
+ * device work).  The tree of §2 splits cells until they hold at most
+ * leaf_size points (or reach the depth cap).  node_capacity: entries of
+ * each node array, params->node_capacity if set, else 4 * ceil(n /
+ * leaf_size) + 64, which holds any tree whose leaves average at least
+ * half of leaf_size points (a tree that needs more reports
+ * KD_ECAPACITY); workspace_bytes: device workspace for kd_build.  Returns
+ * KD_EINVAL on bad parameters.                                             */
 kd_status kd_tree_bounds(uint64_t n, uint32_t d, const kd_params *params,
                          uint64_t *node_capacity, uint64_t *workspace_bytes);
 
@@ -186,8 +190,8 @@ typedef struct kd_profile {
     uint32_t reserved;
 } kd_profile;
 
-/* kd_build with per-kernel timing written to *prof (host struct, zeroed by
- * the call).  Same results as kd_build; for measurement only: it waits for
+/* kd_build (§4) with per-kernel timing written to *prof (host struct,
+ * zeroed by the call).  Same results as kd_build; for measurement only: it waits for
  * every level's totals so launch shapes and byte counts are exact, and
  * returns when the tree is complete.                                     */
 kd_status kd_build_profiled(const float *pts, uint64_t n, uint32_t d, uint64_t ld,
@@ -204,13 +208,15 @@ typedef struct kd_batch_item {
     kd_tree out;
 } kd_batch_item;
 
-/* Workspace for kd_build_batched over the given items (host only). */
+/* Workspace for kd_build_batched over the given items (host only): the sum
+ * of what each item's tree of §2 needs, laid out for one shared level loop. */
 kd_status kd_batch_bounds(uint32_t count, const kd_batch_item *items, const kd_params *params,
                           uint64_t *workspace_bytes);
 
-/* Build `count` independent trees with one set of level launches over the
- * union of their cells.  Every tree is bit-identical to kd_build on it
- * (each tree keeps its own depth cap).  Stream-ordered like kd_build.      */
+/* Build `count` independent trees, each by the level-by-level construction
+ * of §4, with one set of level launches over the union of their cells.
+ * Every tree is bit-identical to kd_build on it (each tree keeps its own
+ * depth cap).  Stream-ordered like kd_build.                               */
 kd_status kd_build_batched(uint32_t count, const kd_batch_item *items, const kd_params *params,
                            void *workspace, uint64_t ws_bytes, void *stream);
 
