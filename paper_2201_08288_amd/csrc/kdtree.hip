@@ -3212,7 +3212,7 @@ __global__ void k_set_desc(TreeDesc *dst, DescChunk ch) {
 // (plus TAIL_SLACK) run in "tail" shape: every kernel on a few workgroups
 // (they loop over whatever work the level holds) and the emit step in one
 // workgroup, so the empty levels at the end cost a few microseconds each.
-constexpr uint32_t TAIL_SLACK = 4;
+constexpr uint32_t TAIL_SLACK = 2;
 constexpr uint32_t TAIL_GRID = 64;
 
 // The level loop over every tree of the build.
