@@ -81,3 +81,21 @@ def test_default_depth_cap(rule):
     g = gpu_tree(x, **kw)[1]
     o = oracle.build_tree(x, **kw)
     assert_same_tree(g, o, x)
+
+
+@pytest.mark.parametrize("sigma", [4.0, 8.0])
+def test_deep_tree_work_in_tail_shape(sigma):
+    """Log-normal keys with FOURIER at J = 2: splits far from the median make
+    the tree several levels deeper than a balanced one (h = 14; sigma 4:
+    depth h + 5; sigma 8: the default cap h + 10, with oversize leaves and
+    cells of more than 4096 points down to depth 15), so the levels past the
+    likely depth, launched in the small tail shape, still split cells; the
+    tree equals the oracle's."""
+    print(f"case deep tree sigma={sigma}", flush=True)
+    rng = np.random.default_rng(5)
+    x = np.exp(rng.normal(0.0, sigma, size=(1, 200_000))).astype(np.float32)
+    kw = dict(leaf_size=16, num_subsets=4, split_rule=1, fourier_J=2)
+    g = gpu_tree(x, **kw)[1]
+    o = oracle.build_tree(x, **kw)
+    assert o["depth"] >= 14 + 5
+    assert_same_tree(g, o, x)
