@@ -1120,8 +1120,10 @@ __global__ __launch_bounds__(NT) void k_big_decide(Ctx c, uint32_t level) {
 // a7, large cells: stable partition-scatter of one tile.  Ranks come from the
 // staged key column; each column (and the permutation) is then permuted in
 // LDS and written as two contiguous runs, the left and right children's.
+// Workgroups per CU: four, or three with the largest-variance sums (their
+// accumulators then fit without squeezing the rest into 128 VGPRs).
 template <bool MAXVAR>
-__global__ __launch_bounds__(NT, 4) void k_big_scatter(Ctx c, uint32_t level) {
+__global__ __launch_bounds__(NT, MAXVAR ? 3 : 4) void k_big_scatter(Ctx c, uint32_t level) {
     __shared__ uint32_t stage0[PADDED];  // staged keys / ranks, then a column buffer
     __shared__ uint32_t stage1[TILE];
     __shared__ uint32_t sh[NW + 1];
