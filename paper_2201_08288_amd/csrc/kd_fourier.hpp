@@ -122,19 +122,26 @@ __device__ __forceinline__ void fourier_terms(uint32_t key, double xmin, double 
     }
 }
 
-// F(v) from the summed statistics, held one harmonic per lane: lane j has
-// a_j = Cc[j] * 2^-24 and b_j = Cs[j] * 2^-24 (harmonic 2j+1, j < J); every
-// lane evaluates F at its own v, reading the coefficients from their lanes.
-// Call with all lanes of the wave active: an inactive lane's register may
-// hold another value.
-__device__ __forceinline__ double lane_value(double x, int j) {
-    const unsigned long long b = __double_as_longlong(x);
-    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(b), j);
-    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(b >> 32), j);
-    return __longlong_as_double((long long)((unsigned long long)hi << 32 | lo));
+// F(v) from the summed statistics: cf[2j] and cf[2j+1] hold the bits of
+// a_j = Cc[j] * 2^-24 and b_j = Cs[j] * 2^-24 (harmonic 2j+1, j < J) in LDS,
+// read by every lane at once; each lane evaluates F at its own v.  The harmonics are taken
+// four at a time so that their weights are fetched together; the sum runs
+// over j in order either way.
+__device__ __forceinline__ void fourier_F_term(const long long *cf, const TrigTables &T, int j,
+                                               double C2, double S2, double &cj, double &sj,
+                                               double &F) {
+    const double a = __longlong_as_double(cf[2 * j]), b = __longlong_as_double(cf[2 * j + 1]);
+    const double t1 = a * sj, t2 = b * cj;
+    const double t = t1 - t2;
+    const double wt = T.w[j] * t;
+    F = F + wt;
+    const double p1 = cj * C2, p2 = sj * S2;
+    const double p3 = sj * C2, p4 = cj * S2;
+    cj = p1 - p2;
+    sj = p3 + p4;
 }
 
-__device__ __forceinline__ double fourier_F(double a_lane, double b_lane, int J, double v,
+__device__ __forceinline__ double fourier_F(const long long *cf, int J, double v,
                                             const TrigTables &T) {
     double s1, c1;
     sincos64(v, T, s1, c1);
@@ -143,18 +150,12 @@ __device__ __forceinline__ double fourier_F(double a_lane, double b_lane, int J,
     const double sc = s1 * c1;
     const double S2 = 2.0 * sc;
     double cj = c1, sj = s1, F = 0.0;
-    for (int j = 0; j < J; j++) {
-        const double a = lane_value(a_lane, j);
-        const double b = lane_value(b_lane, j);
-        const double t1 = a * sj, t2 = b * cj;
-        const double t = t1 - t2;
-        const double wt = T.w[j] * t;
-        F = F + wt;
-        const double p1 = cj * C2, p2 = sj * S2;
-        const double p3 = sj * C2, p4 = cj * S2;
-        cj = p1 - p2;
-        sj = p3 + p4;
+    int j = 0;
+    for (; j + 4 <= J; j += 4) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) fourier_F_term(cf, T, j + k, C2, S2, cj, sj, F);
     }
+    for (; j < J; j++) fourier_F_term(cf, T, j, C2, S2, cj, sj, F);
     return F;
 }
 
@@ -163,20 +164,29 @@ __device__ __forceinline__ double fourier_F(double a_lane, double b_lane, int J,
 // in parallel (lane i-1 holds heap node i) and then follows the path the
 // sequential bisection would take, so the result is the sequential one.
 // Returns the key m (lo when F(v(lo)) >= 0).  Every lane gets the result.
+// cf: this wave's LDS for 2J values (16-byte aligned); it may be the LDS
+// that holds Cc and Cs (the same type, so the reads stay before the writes).
 __device__ uint32_t fourier_solve_wave(const long long *Cc, const long long *Cs, int J,
-                                       uint32_t lo, uint32_t hi, int e, const TrigTables &T) {
+                                       uint32_t lo, uint32_t hi, int e, const TrigTables &T,
+                                       long long *cf) {
     const double xmin = value_of_key(lo);
     const double scale = fourier_scale(e);
     const int l = lane();
-    // the statistics as doubles, harmonic j in lane j
+    // the statistics as doubles
     const double q = 1.0 / 16777216.0;
-    double a_lane = 0.0, b_lane = 0.0;
+    double a = 0.0, b = 0.0;
     if (l < J) {
-        a_lane = double(Cc[l]) * q;
-        b_lane = double(Cs[l]) * q;
+        a = double(Cc[l]) * q;
+        b = double(Cs[l]) * q;
     }
+    __builtin_amdgcn_wave_barrier();
+    if (l < J) {
+        cf[2 * l] = __double_as_longlong(a);
+        cf[2 * l + 1] = __double_as_longlong(b);
+    }
+    __builtin_amdgcn_wave_barrier();
     // F at v = 0 (the smallest key)
-    const double f0 = fourier_F(a_lane, b_lane, J, 0.0, T);
+    const double f0 = fourier_F(cf, J, 0.0, T);
     if (f0 >= 0.0) return lo;
     while (hi - lo > 1u) {
         // heap node of this lane and its interval
@@ -195,10 +205,9 @@ __device__ uint32_t fourier_solve_wave(const long long *Cc, const long long *Cs,
         }
         live = live && (b - a > 1u);
         const uint32_t mid = a + (b - a) / 2u;
-        // evaluated by every lane (the coefficients are read from their lanes,
-        // which must all be active); lanes without a live node use v = 0
+        // evaluated by every lane; lanes without a live node use v = 0
         const double v = live ? (value_of_key(mid) - xmin) * scale : 0.0;
-        const double f = fourier_F(a_lane, b_lane, J, v, T);
+        const double f = fourier_F(cf, J, v, T);
         const unsigned long long neg = __ballot(live && f < 0.0);
         // follow the sequential path for up to six steps
         uint32_t nd = 1;

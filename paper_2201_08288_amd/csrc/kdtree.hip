@@ -741,6 +741,7 @@ __global__ __launch_bounds__(NT) void k_big_moments(Ctx c, uint32_t level) {
 
 // FOURIER, large cells: solve Eq. (2) for the candidate (one wave per cell).
 __global__ __launch_bounds__(NT) void k_big_fsolve(Ctx c, uint32_t level) {
+    __shared__ __attribute__((aligned(16))) long long cf[NW][2 * FOURIER_JMAX];
     const uint32_t nbig = c.info[level].num_big;
     for (uint32_t b = blockIdx.x * NW + wave(); b < nbig; b += gridDim.x * NW) {
         const uint32_t ci = c.big_list[b];
@@ -749,7 +750,7 @@ __global__ __launch_bounds__(NT) void k_big_fsolve(Ctx c, uint32_t level) {
         if (lo != hi) {
             const long long *mom = c.mom + uint64_t(b) * 2 * FOURIER_JMAX;
             m = fourier_solve_wave(mom, mom + FOURIER_JMAX, int(c.J), lo, hi,
-                                   fourier_exponent(lo, hi), c.trig);
+                                   fourier_exponent(lo, hi), c.trig, cf[wave()]);
         }
         if (lane() == 0) c.res[ci].cand = m;
     }
@@ -1416,6 +1417,47 @@ __device__ __forceinline__ void store_cell(const Ctx &c, uint32_t level, ChunkLd
     C.flags[k] = r.flags;
 }
 
+// Wave sums of 2 * FCHUNK per-lane values at once: each exchange hands the
+// partner lane half of the values still held and adds the half it keeps, so
+// lane l ends with the total of value l >> 1 (lanes 2k and 2k + 1 both).  The
+// first two exchanges add at most four lanes' sums, which the caller bounds
+// below 2^31; the rest run in 64 bits.  Integer sums, exact in any order.
+__device__ __forceinline__ long long wave_sum_transposed(const int (&acc)[2 * FCHUNK]) {
+    static_assert(2 * FCHUNK == WAVE / 2, "one value per pair of lanes");
+    const int l = lane();
+    int v16[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const bool up = l & 32;
+        const int keep = up ? acc[16 + i] : acc[i], give = up ? acc[i] : acc[16 + i];
+        v16[i] = keep + __shfl_xor(give, 32, WAVE);
+    }
+    int v8[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const bool up = l & 16;
+        const int keep = up ? v16[8 + i] : v16[i], give = up ? v16[i] : v16[8 + i];
+        v8[i] = keep + __shfl_xor(give, 16, WAVE);
+    }
+    long long v4[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const bool up = l & 8;
+        const long long keep = up ? v8[4 + i] : v8[i], give = up ? v8[i] : v8[4 + i];
+        v4[i] = keep + __shfl_xor(give, 8, WAVE);
+    }
+    long long v2[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const bool up = l & 4;
+        const long long keep = up ? v4[2 + i] : v4[i], give = up ? v4[i] : v4[2 + i];
+        v2[i] = keep + __shfl_xor(give, 4, WAVE);
+    }
+    const bool up = l & 2;
+    const long long v1 = (up ? v2[1] : v2[0]) + __shfl_xor(up ? v2[0] : v2[1], 2, WAVE);
+    return v1 + __shfl_xor(v1, 1, WAVE);
+}
+
 // Candidate of a cell of at most WAVE_CELL_MAX points by one wave (EXACT,
 // FOURIER); keys at keys[px(s0 + i)], i < nk.
 template <int RULE>
@@ -1440,23 +1482,22 @@ __device__ void wave_candidate(const Ctx &c, const uint32_t *keys, uint32_t s0, 
             const int e = fourier_exponent(mn, mx);
             const double xmin = value_of_key(mn), scale = fourier_scale(e);
             for (int j0 = 0; j0 < J; j0 += FCHUNK) {
-                // a lane's sums fit 32 bits: at most WAVE_CELL_MAX / WAVE terms of 2^24
-                static_assert((WAVE_CELL_MAX / WAVE) * (1ll << 24) < (1ll << 31), "int32 sums");
+                // the sums of four lanes fit 32 bits: at most 4 * WAVE_CELL_MAX / WAVE
+                // terms, each at most 2^24 * (1 + 2^-10) (|cos|, |sin| of the
+                // fp32 recurrence stay within that of 1)
+                static_assert(4 * (WAVE_CELL_MAX / WAVE) * ((1ll << 24) + (1ll << 14)) < (1ll << 31),
+                              "int32 sums");
                 int acc[2 * FCHUNK];
 #pragma unroll
                 for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = 0;
                 for (uint32_t i = l; i < nk; i += WAVE)
                     fourier_terms(keys[px(s0 + i)], xmin, scale, J, j0, c.trig, acc);
-#pragma unroll
-                for (int k = 0; k < 2 * FCHUNK; k++) {
-                    const long long sum =
-                        (long long)wave_sum64((unsigned long long)(long long)acc[k]);
-                    const int j = j0 + (k % FCHUNK);
-                    if (l == k && j < J) mom[(k < FCHUNK ? 0 : FOURIER_JMAX) + j] = sum;
-                }
+                const long long sum = wave_sum_transposed(acc);
+                const int k = l >> 1, j = j0 + (k % FCHUNK);
+                if (!(l & 1) && j < J) mom[(k < FCHUNK ? 0 : FOURIER_JMAX) + j] = sum;
             }
             wave_sync();
-            m = fourier_solve_wave(mom, mom + FOURIER_JMAX, J, mn, mx, e, c.trig);
+            m = fourier_solve_wave(mom, mom + FOURIER_JMAX, J, mn, mx, e, c.trig, mom);
             wave_sync();
         }
     }
@@ -1498,21 +1539,32 @@ __device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *ke
             const int e = fourier_exponent(mn, mx);
             const double xmin = value_of_key(mn), scale = fourier_scale(e);
             for (int j0 = 0; j0 < J; j0 += FCHUNK) {
-                // a thread's sums fit 32 bits: at most TILE / NT terms of 2^24
-                static_assert((TILE / NT) * (1ll << 24) < (1ll << 31), "int32 sums");
+                // the sums of four threads fit 32 bits: at most 4 * TILE / NT
+                // terms of at most 2^24 * (1 + 2^-10) (see wave_candidate)
+                static_assert(4 * (TILE / NT) * ((1ll << 24) + (1ll << 14)) < (1ll << 31),
+                              "int32 sums");
                 int a32[2 * FCHUNK];
 #pragma unroll
                 for (int k = 0; k < 2 * FCHUNK; k++) a32[k] = 0;
                 for (uint32_t i = threadIdx.x; i < nk; i += NT)
                     fourier_terms(keys[px(s0 + i)], xmin, scale, J, j0, c.trig, a32);
-                long long acc[2 * FCHUNK];
-#pragma unroll
-                for (int k = 0; k < 2 * FCHUNK; k++) acc[k] = a32[k];
-                reduce_moments(acc, sh64, j0, J, mom, false);
+                // wave totals (transposed), then the workgroup's
+                const long long ws = wave_sum_transposed(a32);
+                if (!(lane() & 1)) sh64[wave() * 2 * FCHUNK + (lane() >> 1)] = ws;
+                __syncthreads();
+                if (threadIdx.x < 2 * FCHUNK) {
+                    const int k = threadIdx.x, j = j0 + (k % FCHUNK);
+                    if (j < J) {
+                        long long t = 0;
+                        for (int w = 0; w < NW; w++) t += (long long)sh64[w * 2 * FCHUNK + k];
+                        mom[(k < FCHUNK ? 0 : FOURIER_JMAX) + j] = t;
+                    }
+                }
+                __syncthreads();
             }
             if (wave() == 0) {
                 const uint32_t mm = fourier_solve_wave(mom, mom + FOURIER_JMAX, J, mn, mx, e,
-                                                       c.trig);
+                                                       c.trig, mom);
                 if (lane() == 0) s3[0] = mm;
             }
             __syncthreads();
