@@ -72,7 +72,10 @@ struct Ctx {
     uint32_t *scan_tmp;
     uint32_t *bucket_first;  // small cells: first cell of each bucket of TILE numbers
     // SUBSET: subsets of more than SMALL_MAX points of the level's large cells
-    uint32_t *seg_count, *seg_job, *seg_prefix, *seg_rank, *seg_hist;
+    // (seg_count[0] subsets, seg_count[1] histogram workgroups), each with its
+    // first key and size; seg_blk: the (subset, part) of each workgroup
+    uint32_t *seg_count, *seg_job, *seg_prefix, *seg_rank, *seg_hist, *seg_ns, *seg_blk;
+    const uint32_t **seg_col;
     LevelInfo *info;  // totals of every level (MAX_LEVELS + 1)
     // leaf numbering: a bit per position of every tree at each leaf's first
     // position, and exclusive prefix counts of set bits per word (within a
@@ -871,12 +874,21 @@ __global__ __launch_bounds__(NT) void k_subset_select(Ctx c, uint32_t level) {
 }
 
 // SUBSET, large cells: subsets of more than SMALL_MAX points are selected by
-// several workgroups each.  A list of them is made first; then per 8-bit
-// digit, SEG_FAN workgroups per subset add the digit histogram of their part
-// into the subset's histogram, and one workgroup per subset picks the digit.
+// several workgroups each, one per SEG_CHUNK points up to SEG_FAN.  A list of
+// them (and of their workgroups) is made first; then per 8-bit digit, each
+// workgroup adds the digit histogram of its part into the subset's
+// histogram, and one workgroup per subset picks the digit.
 constexpr uint32_t SEG_FAN = 64;
+constexpr uint32_t SEG_CHUNK = PER_THREAD * NT;  // one pass of a workgroup's loads
+static_assert(SEG_FAN <= 64, "(subset, part) packed in 32 bits for up to 2^26 subsets");
+static_assert(SEG_CHUNK >= uint32_t(SMALL_MAX), "at most two workgroups per SMALL_MAX + 1 points");
+
+__device__ __forceinline__ uint32_t seg_fan(uint32_t ns) {
+    return min(SEG_FAN, (ns + SEG_CHUNK - 1) / SEG_CHUNK);
+}
 
 __global__ __launch_bounds__(NT) void k_seg_list(Ctx c, uint32_t level) {
+    const uint32_t cur = level & 1;
     const uint32_t nbig = c.info[level].num_big;
     const uint64_t jobs = uint64_t(nbig) * c.S;
     for (uint64_t job = blockIdx.x * uint64_t(NT) + threadIdx.x; job < jobs;
@@ -886,47 +898,34 @@ __global__ __launch_bounds__(NT) void k_seg_list(Ctx c, uint32_t level) {
         const uint32_t ns = B[s + 1] - B[s];
         if (ns > uint32_t(SMALL_MAX)) {
             const uint32_t i = atomicAdd(c.seg_count, 1u);
+            const uint32_t fan = seg_fan(ns), k0 = atomicAdd(c.seg_count + 1, fan);
+            const uint32_t ci = c.big_list[b];
+            const Cell cl = c.cells[cur][ci];
+            const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
             c.seg_job[i] = uint32_t(job);
             c.seg_prefix[i] = 0;
             c.seg_rank[i] = (ns - 1) / 2;
+            c.seg_ns[i] = ns;
+            c.seg_col[i] = level_col(T, level, c.res[ci].dim) + cl.begin + B[s];
+            for (uint32_t f = 0; f < fan; f++) c.seg_blk[k0 + f] = i * SEG_FAN + f;
         }
     }
 }
 
-// Column, first position and size of large subset i.
-struct SegView {
-    const uint32_t *col;
-    uint32_t b, s, ns;
-};
-__device__ __forceinline__ SegView seg_view(const Ctx &c, uint32_t level, uint32_t i) {
-    const uint32_t cur = level & 1;
-    SegView v;
-    const uint32_t job = c.seg_job[i];
-    v.b = job / c.S;
-    v.s = job % c.S;
-    const uint32_t ci = c.big_list[v.b];
-    const Cell cl = c.cells[cur][ci];
-    const KD_CONST TreeDesc &T = cref(&c.trees[cl.tree]);
-    const uint32_t *B = c.bounds + uint64_t(v.b) * (c.S + 1);
-    v.ns = B[v.s + 1] - B[v.s];
-    v.col = level_col(T, level, c.res[ci].dim) + cl.begin + B[v.s];
-    return v;
-}
-
-__global__ __launch_bounds__(NT) void k_seg_hist(Ctx c, uint32_t level, uint32_t pass) {
+__global__ __launch_bounds__(NT) void k_seg_hist(Ctx c, uint32_t pass) {
     __shared__ uint32_t h[NBINS];
-    const uint32_t nseg = *c.seg_count;
+    const uint32_t nblk = c.seg_count[1];
     const int shift = 32 - RBITS * (pass + 1);
     const uint32_t mask = pass == 0 ? 0u : (~0u << (32 - RBITS * pass));
-    for (uint32_t blk = blockIdx.x; blk < nseg * SEG_FAN; blk += gridDim.x) {
-        const uint32_t i = blk / SEG_FAN, f = blk % SEG_FAN;
-        const SegView v = seg_view(c, level, i);
+    for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const uint32_t bf = c.seg_blk[blk], i = bf / SEG_FAN, f = bf % SEG_FAN;
+        const uint32_t ns = c.seg_ns[i], fan = seg_fan(ns);
         const uint32_t prefix = c.seg_prefix[i];
-        const uint32_t per = (v.ns + SEG_FAN - 1) / SEG_FAN;
-        const uint32_t a = min(f * per, v.ns), e = min(a + per, v.ns);
+        const uint32_t per = (ns + fan - 1) / fan;
+        const uint32_t a = min(f * per, ns), e = min(a + per, ns);
         h[threadIdx.x] = 0;
         __syncthreads();
-        const KD_GLOBAL uint32_t *g = gp(v.col);
+        const KD_GLOBAL uint32_t *g = gp(c.seg_col[i]);
         for (uint32_t i0 = a; i0 < e; i0 += PER_THREAD * NT) {
             uint32_t u[PER_THREAD];
 #pragma unroll
@@ -3099,8 +3098,13 @@ Layout plan(uint32_t T, const uint64_t *n, const uint32_t *d, const uint64_t *ca
     for (uint32_t t = 0; t < T; t++) all_points += n[t];
     L.all_points = all_points;
     L.buckets = B.take((all_points / TILE + 2) * 4);
-    // at most one large subset per SMALL_MAX + 1 points
-    L.segs = B.take(subset ? (all_points / (SMALL_MAX + 1) + 2) * 4 * (3 + NBINS) + 256 : 0);
+    // at most one large subset per SMALL_MAX + 1 points, and at most two
+    // histogram workgroups per SMALL_MAX + 1 points (a subset of ns >
+    // SMALL_MAX points has ceil(ns / SEG_CHUNK) <= 2 ns / (SMALL_MAX + 1)):
+    // per subset 3 + NBINS + 1 words, two for workgroups and two for the
+    // address of its first key
+    L.segs = B.take(subset ? (all_points / (SMALL_MAX + 1) + 2) * 4 * (3 + NBINS + 1 + 2 + 2) + 256
+                           : 0);
     L.info = B.take(sizeof(LevelInfo) * (MAX_LEVELS + 1));
     // one bit per position of every tree, plus the position after the last
     L.leaf_words = all_points / 32 + 1;
@@ -3371,6 +3375,11 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
         c.seg_prefix = c.seg_job + max_seg;
         c.seg_rank = c.seg_prefix + max_seg;
         c.seg_hist = c.seg_rank + max_seg;
+        c.seg_ns = c.seg_hist + max_seg * NBINS;
+        c.seg_blk = c.seg_ns + max_seg;
+        // 64 + max_seg * (3 + NBINS + 1 + 2) words before it: 8-byte aligned
+        static_assert((3 + NBINS + 1 + 2) % 2 == 0, "aligned addresses");
+        c.seg_col = reinterpret_cast<const uint32_t **>(c.seg_blk + 2 * max_seg);
     }
     c.info = reinterpret_cast<LevelInfo *>(ws + L.info);
     c.leafbits = reinterpret_cast<uint32_t *>(ws + L.leafbits);
@@ -3549,12 +3558,13 @@ kd_status run_build(uint32_t ntrees, const HostTree *ht, const kd_params *p, voi
                 P.run(KD_PROF_SELECT, bigp, 4 * bigp, [&] {
                     hipLaunchKernelGGL(k_big_bounds, G(nbig / NT + 1, 4096), dim3(NT),
                                        0, st, c, level);
-                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(NT), 0, st, c.seg_count, 1ull, 0u);
+                    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(NT), 0, st, c.seg_count, 2ull, 0u);
                     hipLaunchKernelGGL(k_seg_list, G(nbig * c.S / NT + 1, 4096),
                                        dim3(NT), 0, st, c, level);
+                    const uint64_t nblk = std::min<uint64_t>(bigp / SEG_CHUNK + nseg, nseg * SEG_FAN);
                     for (uint32_t pass = 0; nseg > 0 && pass < uint32_t(RPASSES); pass++) {
-                        hipLaunchKernelGGL(k_seg_hist, G(nseg * SEG_FAN, 65535),
-                                           dim3(NT), 0, st, c, level, pass);
+                        hipLaunchKernelGGL(k_seg_hist, G(nblk, 65535),
+                                           dim3(NT), 0, st, c, pass);
                         hipLaunchKernelGGL(k_seg_pick, G(nseg, 65535), dim3(NT), 0, st,
                                            c, pass);
                     }
