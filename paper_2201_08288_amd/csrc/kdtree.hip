@@ -1859,8 +1859,13 @@ __global__ __launch_bounds__(NT, MAXVAR ? (RULE != KD_SPLIT_FOURIER ? 3 : 1) : (
                     ps[j] = C.off[k] + e;
                     const bool right = e - C.start[k] >= C.nl[k];
                     if (C.flags[k] & (right ? RES_RIGHT_LEAF : RES_LEFT_LEAF)) leafm |= 1u << j;
-                    if (RULE != KD_SPLIT_EXACT) vn[j] = gp(T.cols[cur])[ps[j]];
                 }
+            }
+            // every load issued (no branch; slots past the chunk read place 0)
+            if (RULE != KD_SPLIT_EXACT) {
+                const KD_GLOBAL uint32_t *src = gp(T.cols[cur]);
+#pragma unroll
+                for (int j = 0; j < PER_THREAD; j++) vn[j] = src[ps[j]];
             }
             const int shift = MAXVAR ? maxvar_shift(c.ts[tr].maxabs) : 0;
             const bool chunk_stats = MAXVAR && C.goes_on;
@@ -1872,13 +1877,31 @@ __global__ __launch_bounds__(NT, MAXVAR ? (RULE != KD_SPLIT_FOURIER ? 3 : 1) : (
                     const KD_GLOBAL uint32_t *src =
                         gp(col + 1 == d ? T.perm[cur] : T.cols[cur] + uint64_t(col + 1) * n);
 #pragma unroll
-                    for (int j = 0; j < PER_THREAD; j++)
-                        if (j * NT + threadIdx.x < tot) vn[j] = src[ps[j]];
+                    for (int j = 0; j < PER_THREAD; j++) vn[j] = src[ps[j]];  // place 0 past the chunk
                 }
+                // staged at the destination, in groups of eight whose places
+                // are read together (no branch: slots past the chunk go to
+                // their own place, which no number of the chunk goes to); one
+                // at a time where registers are short
+                constexpr int SG = (RULE == KD_SPLIT_EXACT && !MAXVAR) ? 4 : 8;
+                if constexpr (RULE == KD_SPLIT_EXACT && !MAXVAR) {
 #pragma unroll
-                for (int j = 0; j < PER_THREAD; j++) {
-                    const uint32_t e = j * NT + threadIdx.x;
-                    if (e < tot) stage[keys[px(e)]] = v[j];
+                    for (int j = 0; j < PER_THREAD; j++) {
+                        const uint32_t e = j * NT + threadIdx.x;
+                        if (e < tot) stage[keys[px(e)]] = v[j];
+                    }
+                } else {
+#pragma unroll
+                    for (int j0 = 0; j0 < PER_THREAD; j0 += SG) {
+                        uint32_t dd[SG];
+#pragma unroll
+                        for (int j = 0; j < SG; j++) dd[j] = keys[px((j0 + j) * NT + threadIdx.x)];
+#pragma unroll
+                        for (int j = 0; j < SG; j++) {
+                            const uint32_t e = (j0 + j) * NT + threadIdx.x;
+                            stage[e < tot ? dd[j] : e] = v[j0 + j];
+                        }
+                    }
                 }
                 __syncthreads();
                 KD_GLOBAL uint32_t *nb =
@@ -1887,11 +1910,17 @@ __global__ __launch_bounds__(NT, MAXVAR ? (RULE != KD_SPLIT_FOURIER ? 3 : 1) : (
                     col == d ? gp(T.out_perm)
                              : (T.pts_out ? gp(T.pts_out + uint64_t(col) * n) : nullptr);
 #pragma unroll
-                for (int j = 0; j < PER_THREAD; j++) {
-                    const uint32_t e = j * NT + threadIdx.x;
-                    if (e < tot) {
-                        KD_GLOBAL uint32_t *p = (leafm >> j) & 1u ? ob : nb;
-                        if (p) p[ps[j]] = stage[e];
+                for (int j0 = 0; j0 < PER_THREAD; j0 += SG) {
+                    uint32_t sv[SG];
+#pragma unroll
+                    for (int j = 0; j < SG; j++) sv[j] = stage[(j0 + j) * NT + threadIdx.x];
+#pragma unroll
+                    for (int j = 0; j < SG; j++) {
+                        const uint32_t e = (j0 + j) * NT + threadIdx.x;
+                        if (e < tot) {
+                            KD_GLOBAL uint32_t *p = (leafm >> (j0 + j)) & 1u ? ob : nb;
+                            if (p) p[ps[j0 + j]] = sv[j];
+                        }
                     }
                 }
                 if (chunk_stats && col < d) {
@@ -2523,22 +2552,33 @@ __global__ __launch_bounds__(NT, MAXVAR ? (RULE == KD_SPLIT_EXACT ? 3 : 2)
                     for (int jj = 0; jj < PER_THREAD; jj++)
                         vn[jj] = src[ps[jj]];
                 }
+                // staged at the slot's number; slots past the chunk at their
+                // own place, which no number uses (no branch)
 #pragma unroll
-                for (int jj = 0; jj < PER_THREAD; jj++) {
-                    const uint32_t e = jj * NT + threadIdx.x;
-                    if (e < tot) keys[lds.inv[e]] = v[jj];
+                for (int j0 = 0; j0 < PER_THREAD; j0 += 8) {
+                    uint32_t dd[8];
+#pragma unroll
+                    for (int jj = 0; jj < 8; jj++) dd[jj] = lds.inv[(j0 + jj) * NT + threadIdx.x];
+#pragma unroll
+                    for (int jj = 0; jj < 8; jj++) {
+                        const uint32_t e = (j0 + jj) * NT + threadIdx.x;
+                        keys[e < tot ? dd[jj] : e] = v[j0 + jj];
+                    }
                 }
                 __syncthreads();
                 KD_GLOBAL uint32_t *nb = gp(col == d ? T.perm[op] : T.cols[op] + uint64_t(col) * n);
                 KD_GLOBAL uint32_t *ob =
                     col == d ? gp(T.out_perm)
                              : (T.pts_out ? gp(T.pts_out + uint64_t(col) * n) : nullptr);
+                uint32_t sv[PER_THREAD];
+#pragma unroll
+                for (int jj = 0; jj < PER_THREAD; jj++) sv[jj] = keys[jj * NT + threadIdx.x];
 #pragma unroll
                 for (int jj = 0; jj < PER_THREAD; jj++) {
                     const uint32_t e = jj * NT + threadIdx.x;
                     if (e < tot) {
                         KD_GLOBAL uint32_t *p = (leafm >> jj) & 1u ? ob : nb;
-                        if (p) p[ps[jj]] = keys[e];
+                        if (p) p[ps[jj]] = sv[jj];
                     }
                 }
                 __syncthreads();
