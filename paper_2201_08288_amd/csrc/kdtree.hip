@@ -786,7 +786,22 @@ __device__ __forceinline__ void subset_bounds(const Ctx &c, uint32_t n, uint32_t
 __device__ __forceinline__ uint32_t subset_mean(const uint32_t *B, const uint32_t *med,
                                                 uint32_t S, uint32_t n_c) {
     double acc = 0.0;
-    for (uint32_t r = 0; r < S; r++) {
+    uint32_t r = 0;
+    for (; r + 4 <= S; r += 4) {  // four subsets' sizes and medians read at a time
+        uint32_t ns[4], md[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            ns[t] = B[r + t + 1] - B[r + t];
+            md[t] = med[r + t];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            if (ns[t] == 0) continue;
+            const double prod = double(ns[t]) * value_of_key(md[t]);
+            acc = acc + prod;
+        }
+    }
+    for (; r < S; r++) {
         const uint32_t ns = B[r + 1] - B[r];
         if (ns == 0) continue;
         const double prod = double(ns) * value_of_key(med[r]);
@@ -1589,6 +1604,48 @@ __device__ void block_candidate(const Ctx &c, uint32_t level, const uint32_t *ke
 // position); larger subsets use a wave radix select.  The weighted mean runs
 // one thread per cell, in subset order.
 constexpr uint32_t RANK_MAX = 64;
+
+// Last r in [0, S) with B[r] <= i, for nondecreasing B with B[0] <= i: a
+// four-way search whose three probes per step are read together.
+__device__ __forceinline__ uint32_t last_at_most(const uint32_t *B, uint32_t S, uint32_t i) {
+    uint32_t lo = 0, hi = S;  // B[lo] <= i; the answer lies in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t w = hi - lo;
+        const uint32_t q1 = lo + w / 4, q2 = lo + w / 2, q3 = lo + (3 * w) / 4;
+        const uint32_t b1 = B[q1], b2 = B[q2], b3 = B[q3];
+        if (b3 <= i) {
+            lo = q3;
+        } else if (b2 <= i) {
+            lo = q2;
+            hi = q3;
+        } else if (b1 <= i) {
+            lo = q1;
+            hi = q2;
+        } else {
+            hi = q1;  // q1 > lo here: B[lo] <= i
+        }
+    }
+    return lo;
+}
+
+// Rank of key u (at slot e) among the m keys at slots s0 .. s0+m-1, ties
+// broken by slot; four keys read at a time.
+__device__ __forceinline__ uint32_t rank_in_subset(const uint32_t *keys, uint32_t s0, uint32_t m,
+                                                   uint32_t u, uint32_t e) {
+    uint32_t rank = 0, j = 0;
+    for (; j + 4 <= m; j += 4) {
+        uint32_t v[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) v[t] = keys[px(s0 + j + t)];
+#pragma unroll
+        for (int t = 0; t < 4; t++) rank += (v[t] < u) || (v[t] == u && s0 + j + t < e);
+    }
+    for (; j < m; j++) {
+        const uint32_t v = keys[px(s0 + j)];
+        rank += (v < u) || (v == u && s0 + j < e);
+    }
+    return rank;
+}
 constexpr uint32_t SUBSET_DYN_WORDS = 7680;  // dynamic LDS of the SUBSET small-cell kernels (30 KB)
 template <int SC>
 __device__ void subset_cells(const Ctx &c, uint32_t level, const uint32_t *keys,
@@ -1639,21 +1696,11 @@ __device__ void subset_cells(const Ctx &c, uint32_t level, const uint32_t *keys,
         const uint32_t g = seg[e] - k0, i = e - C.start[k0 + g];
         const uint32_t *B = dyn + g * stride;
         // subset of position i: the last r with B[r] <= i
-        uint32_t lo = 0, hi = S;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (B[mid] <= i) lo = mid;
-            else hi = mid;
-        }
+        const uint32_t lo = last_at_most(B, S, i);
         const uint32_t b = B[lo], m = B[lo + 1] - b;
         if (m > RANK_MAX) continue;
         const uint32_t s0 = C.start[k0 + g] + b, u = keys[px(e)];
-        uint32_t rank = 0;
-        for (uint32_t j = 0; j < m; j++) {
-            const uint32_t v = keys[px(s0 + j)];
-            rank += (v < u) || (v == u && s0 + j < e);
-        }
-        if (rank == (m - 1) / 2) dyn[g * stride + S + 1 + lo] = u;
+        if (rank_in_subset(keys, s0, m, u, e) == (m - 1) / 2) dyn[g * stride + S + 1 + lo] = u;
     }
     // empty subsets, and lower medians of the large ones (a wave select
     // each): a wave takes a cell and checks 64 subsets at a time
@@ -2073,21 +2120,11 @@ __device__ void subtree_subset(const Ctx &c, uint32_t depth, uint32_t max_depth,
             if (q == SEG_LEAF || q < q0 || q >= q0 + g1) continue;
             const uint32_t g = q - q0, i = e - A.start[q];
             const uint32_t *B = dyn + g * stride;
-            uint32_t lo = 0, hi = S;  // the last r with B[r] <= i
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (B[mid] <= i) lo = mid;
-                else hi = mid;
-            }
+            const uint32_t lo = last_at_most(B, S, i);
             const uint32_t b = B[lo], m = B[lo + 1] - b;
             if (m > RANK_MAX) continue;
             const uint32_t s0 = A.start[q] + b, u = keys[px(e)];
-            uint32_t rank = 0;
-            for (uint32_t j = 0; j < m; j++) {
-                const uint32_t v = keys[px(s0 + j)];
-                rank += (v < u) || (v == u && s0 + j < e);
-            }
-            if (rank == (m - 1) / 2) dyn[g * stride + S + 1 + lo] = u;
+            if (rank_in_subset(keys, s0, m, u, e) == (m - 1) / 2) dyn[g * stride + S + 1 + lo] = u;
         }
         for (uint32_t g = w; g < g1; g += NW) {
             const uint32_t *B = dyn + g * stride;
