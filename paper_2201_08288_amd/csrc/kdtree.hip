@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "kdtree.h"
@@ -2465,24 +2466,37 @@ __global__ __launch_bounds__(NT, MAXVAR ? (RULE == KD_SPLIT_EXACT ? 3 : 2)
                             for (int i = 0; i < 3; i++) pq[i] = ps[col * 3 + i];
                         }
                         VarSums a;
-                        // eight loads in flight per lane, eight values between
-                        // folds (no wrap): each batch of 8 * WAVE slots reads
-                        // its places first and then issues every load, the
-                        // slots past the child's end reading its last place
-                        // again and adding zero (no branch: a load under a
-                        // condition is issued only after the others complete)
-                        for (uint32_t eb = s0; eb < s1; eb += 8 * WAVE) {
-                            uint32_t kx[8], xv[8];
+                        // up to eight loads in flight per lane, at most eight
+                        // values between folds (no wrap): each batch of B * WAVE
+                        // slots reads its places first and then issues every
+                        // load, the slots past the child's end reading its last
+                        // place again and adding zero (no branch: a load under
+                        // a condition is issued only after the others
+                        // complete).  Batches of eight while more than four
+                        // rows of the wave remain, then one of four, two or one
+                        // (most children hold 129 to 512 points).
+                        auto batch = [&](auto bc, uint32_t eb) {
+                            constexpr int B = decltype(bc)::value;
+                            uint32_t kx[B], xv[B];
 #pragma unroll
-                            for (int j = 0; j < 8; j++) kx[j] = keys[min(eb + j * WAVE + l, s1 - 1)];
+                            for (int j = 0; j < B; j++) kx[j] = keys[min(eb + j * WAVE + l, s1 - 1)];
 #pragma unroll
-                            for (int j = 0; j < 8; j++) xv[j] = src[kx[j]];
+                            for (int j = 0; j < B; j++) xv[j] = src[kx[j]];
 #pragma unroll
-                            for (int j = 0; j < 8; j++) {
+                            for (int j = 0; j < B; j++) {
                                 const int q = maxvar_q32(xv[j], shift);
                                 a.add(eb + j * WAVE + l < s1 ? q : 0);
                             }
                             a.fold();
+                        };
+                        uint32_t eb = s0;
+                        for (; eb < s1 && s1 - eb > 4 * WAVE; eb += 8 * WAVE)
+                            batch(std::integral_constant<int, 8>{}, eb);
+                        if (eb < s1) {
+                            const uint32_t rem = s1 - eb;
+                            if (rem > 2 * WAVE) batch(std::integral_constant<int, 4>{}, eb);
+                            else if (rem > WAVE) batch(std::integral_constant<int, 2>{}, eb);
+                            else batch(std::integral_constant<int, 1>{}, eb);
                         }
                         const unsigned long long v[3] = {wave_sum64(a.s1), wave_sum64(a.hi),
                                                          wave_sum64(a.lo)};
