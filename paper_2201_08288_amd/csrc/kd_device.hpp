@@ -169,17 +169,6 @@ __device__ __forceinline__ uint32_t bits_of_key(uint32_t u) {
 __device__ __forceinline__ int lane() { return threadIdx.x & (WAVE - 1); }
 __device__ __forceinline__ int wave() { return threadIdx.x / WAVE; }
 
-// Inclusive prefix sum over a wave64.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-    const int l = lane();
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, WAVE);
-        if (l >= o) x += y;
-    }
-    return x;
-}
-
 
 // Inclusive prefix sum over a wave64 with DPP moves (no LDS traffic): row
 // shifts scan each row of 16 lanes, then the row broadcasts carry the totals
@@ -197,6 +186,22 @@ __device__ __forceinline__ unsigned long long wave_scan64(unsigned long long x) 
     x = dpp_add64<0x118, 0xf>(x);  // row_shr:8
     x = dpp_add64<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
     x = dpp_add64<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+// The same inclusive prefix sum on 32 bits.  Call with every lane of the
+// wave active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_add32(uint32_t x) {
+    return x + __builtin_amdgcn_update_dpp(0u, x, CTRL, ROWS, 0xf, true);
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x = dpp_add32<0x111, 0xf>(x);
+    x = dpp_add32<0x112, 0xf>(x);
+    x = dpp_add32<0x114, 0xf>(x);
+    x = dpp_add32<0x118, 0xf>(x);
+    x = dpp_add32<0x142, 0xa>(x);
+    x = dpp_add32<0x143, 0xc>(x);
     return x;
 }
 
@@ -241,16 +246,13 @@ struct VarSums {
     }
 };
 
+// Wave minimum and maximum, in every lane (every lane active).
 __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, WAVE));
-    return x;
+    return wave_reduce32(x, ~0u, [](uint32_t a, uint32_t b) { return min(a, b); });
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t x) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor(x, o, WAVE));
-    return x;
+    return wave_reduce32(x, 0u, [](uint32_t a, uint32_t b) { return max(a, b); });
 }
 
 // Exclusive prefix of one value per thread over the workgroup.  sh must hold
