@@ -246,6 +246,11 @@ struct VarSums {
     }
 };
 
+// Lane src's value in every lane (src the same in every lane).
+__device__ __forceinline__ uint32_t wave_bcast(uint32_t x, int src) {
+    return uint32_t(__builtin_amdgcn_readlane(int(x), src));
+}
+
 // Wave minimum and maximum, in every lane (every lane active).
 __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
     return wave_reduce32(x, ~0u, [](uint32_t a, uint32_t b) { return min(a, b); });

@@ -172,8 +172,8 @@ __device__ uint32_t wave_select(const uint32_t *keys, uint32_t off, uint32_t n, 
                 below += c[j];
             }
         }
-        bin = __shfl(bin, src, WAVE);
-        below = __shfl(below, src, WAVE);
+        bin = wave_bcast(bin, src);
+        below = wave_bcast(below, src);
         prefix |= bin << shift;
         k -= below;
         wave_sync();

@@ -580,7 +580,7 @@ __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t
             const uint32_t v[4] = {hv[q].x, hv[q].y, hv[q].z, hv[q].w};
             const uint32_t local = v[0] + v[1] + v[2] + v[3];
             const uint32_t incl = wave_incl_scan(local);
-            const uint32_t tot = __shfl(incl, WAVE - 1, WAVE);
+            const uint32_t tot = wave_bcast(incl, WAVE - 1);
             if (base <= r.rank && r.rank < base + tot) {  // uniform: the rank's row
                 const uint32_t ex = base + incl - local;
                 const unsigned long long m = __ballot(ex <= r.rank && r.rank < ex + local);
@@ -597,9 +597,9 @@ __global__ __launch_bounds__(NT) void k_big_pick(Ctx c, uint32_t level, uint32_t
                         lbelow += v[j];
                     }
                 }
-                bin = __shfl(lb, src, WAVE);
-                below = __shfl(lbelow, src, WAVE);
-                cnt = __shfl(lcnt, src, WAVE);
+                bin = wave_bcast(lb, src);
+                below = wave_bcast(lbelow, src);
+                cnt = wave_bcast(lcnt, src);
             }
             base += tot;
         }
@@ -1373,7 +1373,7 @@ __device__ void form_chunk(const Ctx &c, uint32_t cur, uint32_t ncells, uint32_t
         const unsigned long long below_fb = fb == WAVE ? ~0ull : ((1ull << fb) - 1);
         const unsigned long long smask = __ballot(small) & below_fb;
         if (tree == NONE && smask) {
-            tree = __shfl(cl.tree, __builtin_ctzll(smask), WAVE);
+            tree = wave_bcast(cl.tree, __builtin_ctzll(smask));
             first = c.ts[tree].first[cur];
         }
         const uint32_t before =
@@ -1398,7 +1398,7 @@ __device__ void form_chunk(const Ctx &c, uint32_t cur, uint32_t ncells, uint32_t
         if (take && nk > WAVE_CELL_MAX) C.wide[nwide + __popcll(wmask & ((1ull << l) - 1))] = before;
         nwide += uint32_t(__popcll(wmask));
         count += uint32_t(__popcll(__ballot(take)));
-        total += __shfl(incl, WAVE - 1, WAVE);
+        total += wave_bcast(incl, WAVE - 1);
         pos += uint32_t(s);
         if (s < WAVE) break;
     }
@@ -2308,7 +2308,7 @@ __global__ __launch_bounds__(NT, MAXVAR ? (RULE == KD_SPLIT_EXACT ? 3 : 2)
                             A.kid[q][0] = go0 ? id0 : NONE;
                             A.kid[q][1] = go1 ? id0 + uint32_t(go0) : NONE;
                         }
-                        run += __shfl(incl, WAVE - 1, WAVE);
+                        run += wave_bcast(incl, WAVE - 1);
                     }
                     if (l == 0) {
                         // more than SC children: they stop here and are split at
