@@ -57,6 +57,18 @@ def test_subset_equal(n, S):
     assert_same_tree(gpu_tree(x, **kw)[1], oracle_tree(x, **kw), x)
 
 
+@pytest.mark.parametrize("n,S", [(3 * 4097, 3), (2 * 8192 + 2, 2), (2 * 262145, 2),
+                                 (5 * 262144 + 11, 5)])
+def test_subset_large_segments(n, S):
+    """Subsets just above 4096 points (two histogram workgroups each), at
+    2 * 4096 + 1, and above 64 * 4096 (64 workgroups of more than 4096
+    points each): every part of the block map against the oracle."""
+    print(f"case subset large segments n={n} S={S}", flush=True)
+    x = synth.uniform24(n, 2, seed=n)
+    kw = dict(leaf_size=64, split_rule=SUBSET, num_subsets=S)
+    assert_same_tree(gpu_tree(x, **kw)[1], oracle_tree(x, **kw), x)
+
+
 @pytest.mark.parametrize("n,S", [(3000, 8), (50000, 64)])
 def test_subset_pool(n, S):
     print(f"case subset pool n={n} S={S}", flush=True)
